@@ -1,0 +1,198 @@
+"""Benchmark: NVE velocity-Verlet MD of a 1,048,576-atom Lennard-Jones fluid
+on one MI355X through libmd.
+
+Workload: FCC 64^3 x 4 sites at density 0.8442, Maxwell velocities at T = 1.0,
+rc = 2.5, skin = 0.3, dt = 0.005, energy-shifted LJ, full Verlet list.
+One step = Integrate1 + skin test + (gated) re-sort and list build + forces
+with energy and virial + Integrate2 with kinetic energy -- every kernel of
+the path, nothing skipped.  Both pair-arithmetic precisions are run on the
+same inputs: FP32-mixed (the headline value) and FP64.
+
+Prints ONE JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pairs_within_rc(s):
+    """Unordered pairs within rc at the current positions, counted from the
+    full list with torch ops (measurement only, outside the timed region)."""
+    import torch
+    N, K = s.N, s.max_nbr
+    idx = s.idx.view(K, s.ld)[:, :N].long() & 0xFFFFFFFF
+    j = idx & 0x03FFFFFF
+    code = idx >> 26
+    cnt = s.count.long()
+    valid = torch.arange(K, device=s.dev)[:, None] < cnt[None, :]
+    L = s.box.view(-1, 3)[0]
+    tot = 0
+    for k, (p, Ld) in enumerate(((s.x, L[0]), (s.y, L[1]), (s.z, L[2]))):
+        c = (code >> (2 * k)) & 3
+        sh = torch.where(c == 1, 1.0, torch.where(c == 2, -1.0, 0.0)).double()
+        d = p[None, :] - p[j] + sh * Ld
+        tot = tot + d * d
+    inside = (tot < s.rc * s.rc) & valid
+    return int(inside.sum().item()) // 2
+
+
+def sampled_force_error(s, nsample=32, seed=0):
+    """Normwise relative force error of the GPU forces against the FP64
+    oracle (O(N) loop per atom) on sampled atoms of the current state."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    pos = s.positions()
+    f = s.forces_np()
+    planes = tuple(np.ascontiguousarray(pos[:, k]) for k in range(3))
+    smp = rng.choice(s.N, nsample, replace=False)
+    ref = np.array([oracle.lj_force_one(i, None, s.h_box[0], s.rc, planes=planes)[0]
+                    for i in smp])
+    return float(np.linalg.norm(f[smp] - ref) / np.linalg.norm(ref))
+
+
+def time_path(cfg, prec, steps, warmup, mode, graph_k=50):
+    import torch
+    from paper_2109_10876_amd import MDSystem
+    s = MDSystem(cfg.natoms, cfg.box, cfg.pos, cfg.vel, rc=cfg.rc, skin=cfg.skin, dt=cfg.dt,
+                 shift=cfg.shift, mode=mode, prec=prec)
+    s.setup()
+    s.ensure_list()
+    if warmup:
+        s.run_graphed(warmup, k=graph_k)
+    s.ensure_list()
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for attempt in range(3):
+        torch.cuda.synchronize()
+        t0.record(stream)
+        s.run_graphed(steps, k=graph_k)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        st = int(s.status.item())
+        if st == 0:
+            break
+        log(f"[{prec}] list overflow during the timed run (status {st}); regrow and repeat")
+        s.ensure_list()
+    else:
+        raise RuntimeError("list overflow persisted")
+    # dominant kernel: md_lj_forces, timed launch by launch with HIP events
+    # on the stream it is launched on
+    nrep = 50
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(nrep)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        s.forces()
+        b.record(stream)
+    torch.cuda.synchronize()
+    f_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    mean_k = float(s.count.double().mean().item())
+    npairs = pairs_within_rc(s)
+    err = sampled_force_error(s)
+    return s, ms, f_ms, mean_k, npairs, err
+
+
+def cpu_baseline(cfg):
+    """The FP64 oracle as it stands, single-threaded on a host core: one NVE
+    step of the same 1,048,576-atom system, taken as the difference of a
+    2-step and a 1-step run (each run starts with one force evaluation)."""
+    import oracle
+    oracle.build()
+    t = time.perf_counter()
+    oracle.md_run(cfg.pos, cfg.vel, cfg.box[0], cfg.rc, cfg.skin, cfg.dt, 1)
+    t1 = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.md_run(cfg.pos, cfg.vel, cfg.box[0], cfg.rc, cfg.skin, cfg.dt, 2)
+    t2 = time.perf_counter() - t
+    per_step = max(t2 - t1, 1e-9)
+    return {"value": cfg.n / per_step, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 NVE step of the full {cfg.n}-atom system (2-step minus 1-step run), "
+                      f"{per_step:.2f} s/step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--mode", default="full", choices=["full", "half"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(spatial decomposition across GPUs is described, not implemented)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import md_inputs
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = md_inputs.CONFIGS["lj1m"]()
+    out = {}
+    for prec in ("mixed", "fp64"):
+        log(f"[{prec}] timing {args.steps} steps after {args.warmup} warm-up steps")
+        s, ms, f_ms, mean_k, npairs, err = time_path(cfg, prec, args.steps, args.warmup,
+                                                     args.mode)
+        # algorithmic bytes of one md_lj_forces launch: per atom the list
+        # column (4 B x entries), count (4 B), own position (24 B) and force
+        # write (24 B); neighbour positions are cache-resident gathers
+        bytes_launch = s.N * (4.0 * mean_k + 4 + 24 + 24)
+        gbs = bytes_launch / (f_ms * 1e-3) / 1e9
+        out[prec] = {
+            "ms_per_step": ms / args.steps,
+            "atom_steps_per_s": s.N * args.steps / (ms * 1e-3),
+            "pair_evals_per_s": npairs * args.steps / (ms * 1e-3),
+            "pairs_within_rc": npairs,
+            "mean_list_entries": mean_k,
+            "force_err_rel": err,
+            "forces_kernel_ms": f_ms,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                         "bytes_per_launch": bytes_launch},
+        }
+        log(f"[{prec}] {json.dumps(out[prec])}")
+        del s
+        torch.cuda.empty_cache()
+    m = out["mixed"]
+    line = {
+        "metric": "atom-steps/s and pair-evals/s, FP32-mixed vs FP64 path, at force err <=1e-5 rel",
+        "value": m["atom_steps_per_s"],
+        "unit": "atom-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": "LJ fluid FCC 64^3x4 N=1048576 rho=0.8442 T=1.0 rc=2.5 "
+                               "skin=0.3 dt=0.005 NVE", "list": args.mode, "N": cfg.n},
+        "pair_evals_per_s": m["pair_evals_per_s"],
+        "force_err_rel": m["force_err_rel"],
+        "roofline": m["roofline"],
+        "fp64": {k: out["fp64"][k] for k in ("atom_steps_per_s", "pair_evals_per_s",
+                                             "ms_per_step", "force_err_rel", "roofline")},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        log("cpu baseline: oracle, one step of the full system")
+        line["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * md.h -- C ABI of libmd, an MI355X (gfx950) library for the hot path of
+ * short-range non-bonded molecular dynamics as studied in arXiv 2109.10876
+ * ("Code modernization strategies for short-range non-bonded molecular
+ * dynamics simulations"): Lennard-Jones pair forces with a cutoff, evaluated
+ * over cell-list-built Verlet neighbour lists with a skin, on a
+ * structure-of-arrays particle layout, inside a velocity-Verlet step.
+ *
+ * General rules for every call below
+ * ----------------------------------
+ *  - Pointers named in structs or arguments are DEVICE pointers unless the
+ *    argument name starts with h_ (host).  The caller allocates and owns every
+ *    buffer; the library keeps no pointer between calls and never allocates.
+ *  - Work is only enqueued on `stream` (a hipStream_t passed as void*; NULL is
+ *    the null stream).  No call synchronises, so every call may be captured in
+ *    a HIP graph.  Calls that share a workspace must be ordered (same stream).
+ *  - Host-detectable errors are returned immediately (negative MD_E* code)
+ *    and nothing is enqueued.  Errors found on the device are sticky bits
+ *    OR-ed into *status (MD_F_*); the caller clears the word and reads it
+ *    after synchronising.  Nothing is ever truncated silently.
+ *  - Batching: a call works on R independent replicas ("systems") at once.
+ *    Replica r owns atoms [atom_off[r], atom_off[r+1]) and cells
+ *    [cell_off[r], cell_off[r+1]).  R = 1 is the single-system case.
+ *  - Per-atom arrays are structure-of-arrays planes (Sec. 3.1 of the paper:
+ *    each attribute in its own array).  After md_cell_sort they are in cell
+ *    order; `id` keeps each atom's original global index.
+ *  - gate (optional, [R] uint32): replicas with gate[r] == 0 are skipped by
+ *    md_cell_sort and md_verlet_build.  NULL means "all replicas".
+ */
+#ifndef MD_H
+#define MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MD_ABI_VERSION 1
+
+/* ------------------------------------------------------------ return codes */
+#define MD_OK            0
+#define MD_EINVAL       -1  /* null/misaligned pointer, bad count, mode or precision   */
+#define MD_EBOX         -2  /* a box edge < 2 (rc + skin): minimum image not unique    */
+#define MD_ENOWS        -3  /* workspace smaller than md_workspace_bytes()             */
+#define MD_EUNSUPPORTED -4  /* valid request this build does not implement             */
+#define MD_EHIP         -5  /* a HIP launch failed                                     */
+#define MD_ERANGE       -6  /* sizes beyond the encoding limits below                  */
+
+/* ------------------------------------------------ device status bits (sticky) */
+#define MD_F_NBR_OVERFLOW 0x1u  /* some atom has more list entries than max_nbr     */
+#define MD_F_NONFINITE    0x2u  /* a force or energy came out NaN/Inf               */
+#define MD_F_BOND_BROKEN  0x4u  /* a FENE bond reached its maximum extension        */
+
+/* ------------------------------------------------------------------- enums */
+#define MD_HALF 0         /* each unordered pair stored once (Newton's third law) */
+#define MD_FULL 1         /* each pair stored for both atoms                      */
+#define MD_FP64 0         /* all pair arithmetic in double precision              */
+#define MD_FP32_MIXED 1   /* distances, cutoff test and force accumulation in
+                             double; reciprocal and LJ polynomial in single     */
+
+/* ------------------------------------------------------------------ limits */
+#define MD_UNIT_ATOMS 256           /* atoms per work unit (one workgroup)        */
+#define MD_IDX_BITS   26            /* list entry: low 26 bits = neighbour index  */
+#define MD_IDX_MASK   0x03FFFFFFu
+#define MD_MAX_ATOMS  0x03FFFFFF    /* total atoms per call                       */
+#define MD_MAX_TYPES  8             /* atom types                                 */
+
+/* Verlet-list entry encoding.  Entry e of atom i names atom j = e & MD_IDX_MASK
+ * and the periodic image under which j is i's neighbour: for dimension d
+ * (x, y, z), the two bits (e >> (26 + 2d)) & 3 hold s_d = 0, +1 (code 1) or
+ * -1 (code 2), and the minimum-image displacement is
+ *     d_d = x_i[d] - x_j[d] + s_d * L_d.
+ * The image is fixed when the list is built and stays valid until the next
+ * rebuild because positions are only wrapped into the box at rebuild time. */
+
+/* ------------------------------------------------------------------ structs */
+
+/* Partition of the atoms into replicas, cells and work units.  Fill the
+ * host-side arrays with md_plan_fill() and copy them to the device. */
+typedef struct md_batch {
+    int32_t R;                /* replicas, >= 1                                  */
+    int32_t N;                /* total atoms, 1 .. MD_MAX_ATOMS                  */
+    int32_t C;                /* total cells                                     */
+    int32_t n_units;          /* work units: ceil(N_r / MD_UNIT_ATOMS) summed    */
+    const int32_t *atom_off;  /* [R+1] first atom of each replica                */
+    const int32_t *cell_off;  /* [R+1] first cell of each replica                */
+    const int32_t *ncell;     /* [3R] cells per dimension (x, y, z)              */
+    const double  *box;       /* [3R] orthorhombic box edges L_x, L_y, L_z       */
+    const int32_t *unit_rep;  /* [n_units] replica of each work unit             */
+    const int32_t *unit_off;  /* [R+1] first work unit of each replica           */
+} md_batch;
+
+/* Structure-of-arrays atom state, N entries per plane (img: 3 planes of N). */
+typedef struct md_atoms {
+    double  *x, *y, *z;       /* positions                                        */
+    double  *vx, *vy, *vz;    /* velocities                                       */
+    double  *fx, *fy, *fz;    /* forces                                           */
+    double  *xb, *yb, *zb;    /* positions at the last list build                 */
+    int32_t *type;            /* atom type in [0, ntypes)                         */
+    int32_t *id;              /* original global index, unique in [0, N)          */
+    int32_t *img;             /* [3N] periodic image counters, planes x | y | z   */
+    int32_t *where;           /* optional [N]: where[id] = current index          */
+} md_atoms;
+
+/* Verlet list in ELL layout, column-major so that entry k of consecutive
+ * atoms is contiguous: entry k of atom i is idx[k * ld + i]. */
+typedef struct md_nlist {
+    int32_t  mode;            /* MD_HALF or MD_FULL                               */
+    int32_t  max_nbr;         /* capacity per atom (columns)                      */
+    int32_t  ld;              /* leading dimension, >= N and a multiple of 64     */
+    int32_t  _pad;
+    int32_t  *count;          /* [N] true entry count (may exceed max_nbr)        */
+    uint32_t *idx;            /* [max_nbr * ld] encoded entries (see above)       */
+} md_nlist;
+
+/* Lennard-Jones parameters (Eq. lj: U = 4 eps [(sig/r)^12 - (sig/r)^6] for
+ * r < rc), per type pair, in symmetric [ntypes * ntypes] row-major tables. */
+typedef struct md_lj {
+    int32_t ntypes;           /* 1 .. MD_MAX_TYPES                                */
+    int32_t shift;            /* 1: energy lowered by U(rc) (continuous at rc)    */
+    double  rc;               /* cutoff radius                                    */
+    const double *eps;        /* [ntypes*ntypes] device                           */
+    const double *sig;        /* [ntypes*ntypes] device                           */
+} md_lj;
+
+/* ---------------------------------------------------------------- plumbing */
+
+int         md_abi_version(void);
+const char *md_strerror(int code);
+
+/* Host-only planning (no GPU work).  Cells per dimension n_d = floor(L_d /
+ * (rc + skin)) so that the cell edge is at least rc + skin (Sec. 2.1.2).
+ * Returns MD_EBOX if some L_d < 2 (rc + skin), MD_EINVAL for R < 1, an empty
+ * replica or non-positive radii, MD_ERANGE if sizes exceed the limits. */
+int md_plan_sizes(int32_t R, const int32_t *h_natoms, const double *h_box,
+                  double rc, double skin,
+                  int32_t *h_N, int32_t *h_C, int32_t *h_n_units);
+/* Fills atom_off[R+1], cell_off[R+1], ncell[3R], unit_rep[n_units] and
+ * unit_off[R+1] (host arrays sized from md_plan_sizes). */
+int md_plan_fill(int32_t R, const int32_t *h_natoms, const double *h_box,
+                 double rc, double skin,
+                 int32_t *h_atom_off, int32_t *h_cell_off, int32_t *h_ncell,
+                 int32_t *h_unit_rep, int32_t *h_unit_off);
+
+/* Bytes of the device workspace used by the calls below for this batch.
+ * The workspace must be zero-filled once after allocation; every call
+ * leaves the parts that must start at zero back at zero. */
+size_t md_workspace_bytes(const md_batch *b);
+
+/* ------------------------------------------------------------- the path */
+
+/* Cell binning and re-sort ("Resort", Sec. 2.1.3 and Sec. 3.1): wraps
+ * positions into the box (updating img), bins atoms into cells, orders atoms
+ * cell by cell (ascending id inside a cell, so the order is deterministic),
+ * permutes x, v, type, id, img of `atoms` in place (through `scratch`, whose
+ * x, y, z, vx, vy, vz, type, id, img planes must be distinct N-sized
+ * buffers), sets x_build := x, fills cell_start[C+1] (cell c holds atoms
+ * [cell_start[c], cell_start[c+1])) and, if atoms->where is set, where[].
+ * Forces are not carried through the permutation.  Replicas whose gate is
+ * zero are left untouched. */
+int md_cell_sort(const md_batch *b, md_atoms *atoms, md_atoms *scratch,
+                 int32_t *cell_start, void *ws, size_t ws_bytes,
+                 const uint32_t *gate, uint32_t *status, void *stream);
+
+/* Verlet list build (Sec. 2.1.2, Sec. 3.2 "SortedList"): for each atom, the
+ * atoms of its own cell and the 26 neighbouring cells (each distinct cell
+ * once) whose minimum-image distance is < rc + skin.  MD_FULL lists every
+ * neighbour; MD_HALF lists pair (i, j) only at i < j.  The per-atom order is
+ * cells in (z, y, x) stencil order, then ascending index -- deterministic.
+ * If an atom has more than max_nbr entries its count still holds the true
+ * number, MD_F_NBR_OVERFLOW is raised and *need (device int32, optional)
+ * receives the maximum count; the list is then unusable until rebuilt with
+ * max_nbr >= need.  Expects atoms sorted by md_cell_sort. */
+int md_verlet_build(const md_batch *b, const md_atoms *atoms,
+                    const int32_t *cell_start, double rc, double skin,
+                    md_nlist *nl, int32_t *need, const uint32_t *gate,
+                    uint32_t *status, void *stream);
+
+/* Lennard-Jones forces, potential energy and virial (Eq. lj) over the list:
+ * F_i = sum_j fr(r_ij) d_ij with fr = -U'(r)/r for r < rc, E_r = sum over
+ * pairs of U (minus U(rc) if shift), W_r = sum over pairs of fr r^2.
+ * accumulate = 0 overwrites fx, fy, fz; 1 adds to them.  energy/virial ([R],
+ * optional) receive per-replica totals, reduced in a fixed order (FP64).
+ * MD_FULL results are bitwise deterministic; MD_HALF uses atomic adds for
+ * the partner atom's force.  prec = MD_FP64 or MD_FP32_MIXED. */
+int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
+                 const md_lj *p, int32_t prec, int32_t accumulate,
+                 double *energy, double *virial, void *ws, size_t ws_bytes,
+                 uint32_t *status, void *stream);
+
+/* Velocity-Verlet update (Sec. 2.1, Fig. 1: Integrate1 / Integrate2).
+ *  phase 1: v += dt/2 F/m; x += dt v; gate[r] = 1 if some atom of replica r
+ *           moved more than skin/2 from x_build (the list may miss a pair
+ *           within rc), else 0.
+ *  phase 2: v += dt/2 F/m; ke[r] = sum 1/2 m v^2.
+ *  phase 3: phase 2 immediately followed by phase 1 in one pass (ke is taken
+ *           between the two half kicks).
+ * inv_mass: [ntypes] device array of 1/m.  gate is required for phases 1 and
+ * 3; ke is optional. */
+int md_vv_step(const md_batch *b, md_atoms *atoms, int32_t phase, double dt,
+               const double *inv_mass, int32_t ntypes, double skin,
+               uint32_t *gate, double *ke, void *ws, size_t ws_bytes,
+               uint32_t *status, void *stream);
+
+/* Vector-Jacobian product of md_lj_forces: given G = dL/dF (planes gfx,
+ * gfy, gfz, [N] each, same atom order) and gE ([R], dL/dE_r, optional),
+ * writes gx = dL/dx (planes [3N]) and, optionally, geps and gsig ([ntypes^2],
+ * derivatives with respect to the shared parameter of each unordered type
+ * pair; both mirrored entries hold it, summed over all replicas).  Pair terms
+ * are recomputed from the list, nothing is stored by md_lj_forces.  Requires
+ * an MD_FULL list. */
+int md_lj_forces_vjp(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
+                     const md_lj *p, int32_t prec, const double *gfx,
+                     const double *gfy, const double *gfz, const double *gE,
+                     double *gx, double *geps, double *gsig, void *ws,
+                     size_t ws_bytes, uint32_t *status, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MD_H */

@@ -1,0 +1,130 @@
+"""ctypes binding of libmd's C ABI (``include/md.h``).
+
+Argument marshalling only: every step of the MD path runs in the HIP
+kernels of ``libmd.so``.  The library must have been built in-tree
+(``paper_2109_10876_amd.build.build_library()``); loading fails loudly
+otherwise -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmd.so")
+
+# Constants mirrored from md.h.
+MD_OK = 0
+MD_EINVAL = -1
+MD_EBOX = -2
+MD_ENOWS = -3
+MD_EUNSUPPORTED = -4
+MD_EHIP = -5
+MD_ERANGE = -6
+MD_F_NBR_OVERFLOW = 0x1
+MD_F_NONFINITE = 0x2
+MD_F_BOND_BROKEN = 0x4
+MD_HALF = 0
+MD_FULL = 1
+MD_FP64 = 0
+MD_FP32_MIXED = 1
+MD_UNIT_ATOMS = 256
+MD_IDX_BITS = 26
+MD_IDX_MASK = 0x03FFFFFF
+MD_MAX_ATOMS = 0x03FFFFFF
+MD_MAX_TYPES = 8
+
+EXPORTS = (
+    "md_abi_version", "md_strerror", "md_plan_sizes", "md_plan_fill",
+    "md_workspace_bytes", "md_cell_sort", "md_verlet_build", "md_lj_forces",
+    "md_vv_step", "md_lj_forces_vjp",
+)
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+
+
+class MdBatch(ctypes.Structure):
+    _fields_ = [("R", _i32), ("N", _i32), ("C", _i32), ("n_units", _i32),
+                ("atom_off", _vp), ("cell_off", _vp), ("ncell", _vp), ("box", _vp),
+                ("unit_rep", _vp), ("unit_off", _vp)]
+
+
+class MdAtoms(ctypes.Structure):
+    _fields_ = [(n, _vp) for n in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz",
+                                   "xb", "yb", "zb", "type", "id", "img", "where")]
+
+
+class MdNlist(ctypes.Structure):
+    _fields_ = [("mode", _i32), ("max_nbr", _i32), ("ld", _i32), ("_pad", _i32),
+                ("count", _vp), ("idx", _vp)]
+
+
+class MdLj(ctypes.Structure):
+    _fields_ = [("ntypes", _i32), ("shift", _i32), ("rc", _dbl), ("eps", _vp), ("sig", _vp)]
+
+
+class MDError(RuntimeError):
+    """A libmd call returned a negative MD_E* code."""
+
+    def __init__(self, fn, code):
+        self.code = code
+        super().__init__(f"{fn}: {strerror(code)} (code {code})")
+
+
+_lib = None
+
+
+def load():
+    """Load libmd.so (built in-tree); raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"libmd.so not found at {LIB_PATH}; build it first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lib.md_abi_version.restype = ctypes.c_int
+    lib.md_abi_version.argtypes = []
+    lib.md_strerror.restype = ctypes.c_char_p
+    lib.md_strerror.argtypes = [ctypes.c_int]
+    lib.md_plan_sizes.restype = ctypes.c_int
+    lib.md_plan_sizes.argtypes = [_i32, _vp, _vp, _dbl, _dbl, P(_i32), P(_i32), P(_i32)]
+    lib.md_plan_fill.restype = ctypes.c_int
+    lib.md_plan_fill.argtypes = [_i32, _vp, _vp, _dbl, _dbl, _vp, _vp, _vp, _vp, _vp]
+    lib.md_workspace_bytes.restype = ctypes.c_size_t
+    lib.md_workspace_bytes.argtypes = [P(MdBatch)]
+    lib.md_cell_sort.restype = ctypes.c_int
+    lib.md_cell_sort.argtypes = [P(MdBatch), P(MdAtoms), P(MdAtoms), _vp, _vp, ctypes.c_size_t,
+                                 _vp, _vp, _vp]
+    lib.md_verlet_build.restype = ctypes.c_int
+    lib.md_verlet_build.argtypes = [P(MdBatch), P(MdAtoms), _vp, _dbl, _dbl, P(MdNlist), _vp,
+                                    _vp, _vp, _vp]
+    lib.md_lj_forces.restype = ctypes.c_int
+    lib.md_lj_forces.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32, _i32,
+                                 _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
+    lib.md_vv_step.restype = ctypes.c_int
+    lib.md_vv_step.argtypes = [P(MdBatch), P(MdAtoms), _i32, _dbl, _vp, _i32, _dbl, _vp, _vp,
+                               _vp, ctypes.c_size_t, _vp, _vp]
+    lib.md_lj_forces_vjp.restype = ctypes.c_int
+    lib.md_lj_forces_vjp.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32,
+                                     _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                     _vp, _vp]
+    _lib = lib
+    return lib
+
+
+def strerror(code):
+    try:
+        return load().md_strerror(int(code)).decode()
+    except Exception:  # library missing: still give the code back
+        return f"md error {code}"
+
+
+def check(fn, code):
+    if code != MD_OK:
+        raise MDError(fn, code)
+    return code

@@ -1,0 +1,196 @@
+// md_common.hpp -- shared device/host helpers of libmd (gfx950, wave64).
+//
+// Only the HIP translation units of libmd include this file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "md.h"
+
+namespace md {
+
+constexpr int kUnit = MD_UNIT_ATOMS;   // atoms per work unit == threads per block
+constexpr int kWave = 64;
+constexpr int kWavesPerUnit = kUnit / kWave;
+constexpr int kXcds = 8;               // MI355X: 8 accelerator complex dies
+
+static_assert(kUnit % kWave == 0, "unit must be whole waves");
+
+// ----------------------------------------------------------------- layout
+
+// Workspace layout (all regions 256-byte aligned).  Counters and the cell
+// histogram must be zero between calls; the kernels restore them.
+struct WsLayout {
+    size_t counters;     // 64 x uint32
+    size_t partial;      // n_units x kPartials doubles (per-unit reduction slots)
+    size_t cell_count;   // C x int32
+    size_t cell_of;      // N x int32
+    size_t slot;         // N x int32
+    size_t key;          // N x int32
+    size_t vjp_partial;  // n_units x 2 x MD_MAX_TYPES^2 doubles
+    size_t total;
+};
+constexpr int kPartials = 4;   // E, W, KE, max displacement^2
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+inline WsLayout ws_layout(const md_batch *b)
+{
+    WsLayout l;
+    size_t o = 0;
+    l.counters = o;    o = align256(o + 64 * sizeof(uint32_t));
+    l.partial = o;     o = align256(o + size_t(b->n_units) * kPartials * sizeof(double));
+    l.cell_count = o;  o = align256(o + size_t(b->C) * sizeof(int32_t));
+    l.cell_of = o;     o = align256(o + size_t(b->N) * sizeof(int32_t));
+    l.slot = o;        o = align256(o + size_t(b->N) * sizeof(int32_t));
+    l.key = o;         o = align256(o + size_t(b->N) * sizeof(int32_t));
+    l.vjp_partial = o; o = align256(o + size_t(b->n_units) * 2 * MD_MAX_TYPES * MD_MAX_TYPES * sizeof(double));
+    l.total = o;
+    return l;
+}
+
+template <typename T>
+inline T *ws_at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
+
+// Counter slots inside the workspace counter block.
+enum Counter : int { kCntForces = 0, kCntVV = 1, kCntVjp = 2 };
+
+// ------------------------------------------------------------- unit mapping
+
+// Hardware dispatch hands workgroup b to XCD (b mod 8).  Remap so each XCD
+// receives one contiguous range of work units: neighbouring atoms (and the
+// neighbour positions they gather) then stay in one XCD's L2.
+__device__ __forceinline__ int xcd_swizzle(int b, int nblocks)
+{
+    const int x = b % kXcds, k = b / kXcds;
+    const int per = nblocks / kXcds, rem = nblocks % kXcds;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+struct Unit {
+    int rep;    // replica
+    int begin;  // first atom of the unit
+    int end;    // one past the last atom of the unit
+};
+
+__device__ __forceinline__ Unit unit_of(int u, const int32_t *__restrict__ unit_rep,
+                                        const int32_t *__restrict__ unit_off,
+                                        const int32_t *__restrict__ atom_off)
+{
+    Unit w;
+    w.rep = unit_rep[u];
+    const int a0 = atom_off[w.rep], a1 = atom_off[w.rep + 1];
+    w.begin = a0 + (u - unit_off[w.rep]) * kUnit;
+    w.end = min(w.begin + kUnit, a1);
+    return w;
+}
+
+// ---------------------------------------------------------------- geometry
+
+// Cell coordinate of a wrapped coordinate w in [0, L): floor(w n / L), clamped
+// to [0, n-1].  Binning and list build both call this on the same stored
+// value, so an atom is always searched from the cell it was binned into.
+__device__ __forceinline__ int cell_coord(double w, double L, int n)
+{
+    int c = static_cast<int>(floor(w * static_cast<double>(n) / L));
+    return c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
+}
+
+// Wrap x into [0, L); returns the number of box lengths removed.
+__device__ __forceinline__ double wrap_coord(double x, double L, int *shift)
+{
+    double f = floor(x / L);
+    double w = x - L * f;
+    if (w >= L) { w -= L; f += 1.0; }
+    if (w < 0.0) { w += L; f -= 1.0; }
+    *shift = static_cast<int>(f);
+    return w;
+}
+
+// Two-bit image code of s in {0, +1, -1}.
+__device__ __forceinline__ uint32_t image_code(int s) { return s == 0 ? 0u : (s > 0 ? 1u : 2u); }
+// Inverse: code 0 -> 0, 1 -> +1, 2 -> -1.
+__device__ __forceinline__ double image_shift(uint32_t c) { return c == 0u ? 0.0 : (c == 1u ? 1.0 : -1.0); }
+
+// ------------------------------------------------------------- arithmetic
+
+// Double-precision reciprocal: hardware estimate refined by two
+// Newton-Raphson steps y <- y + y (1 - a y).
+__device__ __forceinline__ double rcp_f64(double a)
+{
+    double y = __builtin_amdgcn_rcp(a);
+    y = fma(y, fma(-a, y, 1.0), y);
+    y = fma(y, fma(-a, y, 1.0), y);
+    return y;
+}
+
+// ------------------------------------------------------------- reductions
+
+// Deterministic wave64 sum (fixed butterfly order).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Block-level sum over kUnit threads in a fixed order; result valid in
+// thread 0.  `lds` must hold kWavesPerUnit doubles.
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kWavesPerUnit; ++k) s += lds[k];
+    __syncthreads();
+    return s;
+}
+__device__ __forceinline__ double block_max(double v, double *lds)
+{
+    v = wave_max(v);
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kWavesPerUnit; ++k) s = fmax(s, lds[k]);
+    __syncthreads();
+    return s;
+}
+
+// -------------------------------------------------------------- host side
+
+// Per-replica fixed-order sums of partial slots k0 and k0+1 (md_forces.hip).
+void launch_finalize_sum2(int R, const int32_t *unit_off, const double *partial, int k0,
+                          double *out0, double *out1, hipStream_t s);
+
+inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+inline int launch_status()
+{
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_EHIP;
+}
+
+// Host validation of a batch descriptor.
+inline int check_batch(const md_batch *b)
+{
+    if (!b || b->R < 1 || b->N < 1 || b->C < 1 || b->n_units < 1) return MD_EINVAL;
+    if (b->N > MD_MAX_ATOMS) return MD_ERANGE;
+    if (!b->atom_off || !b->cell_off || !b->ncell || !b->box || !b->unit_rep || !b->unit_off)
+        return MD_EINVAL;
+    return MD_OK;
+}
+
+inline bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+}  // namespace md

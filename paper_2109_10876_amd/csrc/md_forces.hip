@@ -1,0 +1,250 @@
+// md_forces.hip -- md_lj_forces: Lennard-Jones forces, energy and virial.
+//
+// Eq. lj of the paper, U(r) = 4 eps [(sig/r)^12 - (sig/r)^6] for r < r_cut,
+// summed over the Verlet list (Sec. 2.1.1-2.1.2).  With s6 = (sig^2/r^2)^3:
+//     fr = -U'(r)/r = 24 eps s6 (2 s6 - 1) / r^2,   U = 4 eps s6 (s6 - 1)
+// and the force on i from j is fr * d with d = x_i - x_j + s L (list image).
+//
+// Mapping: one thread per atom i, 256 atoms per workgroup, work units
+// remapped per XCD.  The thread walks its column of the ELL list; entry k of
+// 64 consecutive atoms is one coalesced 256-byte row.  Neighbour positions
+// are gathered from the cell-sorted SoA planes (mostly L2 hits).
+//
+// MD_FULL: each atom sums its own force, no atomics, bitwise deterministic;
+// each pair's energy and virial are counted from both sides and halved.
+// MD_HALF: the paper's Newton's-third-law list (Sec. 2.1.2); the partner's
+// force is added with FP64 atomics.
+//
+// MD_FP32_MIXED: displacement, r^2, the cutoff test and the force
+// accumulation stay in double (positions up to ~100 sigma would lose the
+// displacement's low bits in single); only the reciprocal and the LJ
+// polynomial are single precision.  Per-atom energy/virial sums are single,
+// the per-replica totals double.
+//
+// Energy and virial: per-unit partial sums in fixed order, then one
+// workgroup per replica sums its units in fixed order.
+#include "md_common.hpp"
+
+namespace md {
+namespace {
+
+struct ForceArgs {
+    const int32_t *atom_off, *unit_rep, *unit_off;
+    const double *box;
+    const double *x, *y, *z;
+    const int32_t *type;
+    const int32_t *count;
+    const uint32_t *idx;
+    int32_t ld, max_nbr;
+    const double *eps, *sig;
+    int32_t ntypes, shift;
+    double rc;
+    double *fx, *fy, *fz;
+    int32_t accumulate;
+    double *partial;     // [n_units * kPartials]
+    uint32_t *status;
+};
+
+// Per type pair constants: 24 eps, 4 eps, sig^2, energy shift U(rc).
+struct PairConst {
+    double e24, e4, s2, ush;
+};
+
+__device__ __forceinline__ PairConst pair_const(double eps, double sig, double rc, int shift)
+{
+    PairConst p;
+    p.e24 = 24.0 * eps;
+    p.e4 = 4.0 * eps;
+    p.s2 = sig * sig;
+    double sc2 = p.s2 / (rc * rc);
+    double sc6 = sc2 * sc2 * sc2;
+    p.ush = shift ? 4.0 * eps * (sc6 * sc6 - sc6) : 0.0;
+    return p;
+}
+
+template <int PREC, bool HALF, bool TYPED>
+__global__ __launch_bounds__(kUnit) void k_lj(ForceArgs a)
+{
+    __shared__ PairConst tab[MD_MAX_TYPES * MD_MAX_TYPES];
+    __shared__ double red[kWavesPerUnit];
+    const int u = xcd_swizzle(blockIdx.x, gridDim.x);
+    const Unit w = unit_of(u, a.unit_rep, a.unit_off, a.atom_off);
+
+    PairConst pc0;
+    if (TYPED) {
+        const int nt2 = a.ntypes * a.ntypes;
+        for (int t = threadIdx.x; t < nt2; t += kUnit)
+            tab[t] = pair_const(a.eps[t], a.sig[t], a.rc, a.shift);
+        __syncthreads();
+    } else {
+        pc0 = pair_const(a.eps[0], a.sig[0], a.rc, a.shift);
+    }
+
+    const int i = w.begin + threadIdx.x;
+    const bool active = i < w.end;
+    const double rc2 = a.rc * a.rc;
+    double e_acc = 0.0, w_acc = 0.0;
+    if (active) {
+        const double Lx = a.box[3 * w.rep], Ly = a.box[3 * w.rep + 1], Lz = a.box[3 * w.rep + 2];
+        const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
+        const int ti = TYPED ? a.type[i] : 0;
+        const int n = min(a.count[i], a.max_nbr);
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        float ef = 0.0f, wf = 0.0f;    // mixed-precision per-atom sums
+        double ed = 0.0, wd = 0.0;     // double-precision per-atom sums
+        const uint32_t *col = a.idx + i;
+        for (int k = 0; k < n; ++k) {
+            const uint32_t ent = col[size_t(k) * a.ld];
+            const int j = static_cast<int>(ent & MD_IDX_MASK);
+            double dx = xi - a.x[j], dy = yi - a.y[j], dz = zi - a.z[j];
+            const uint32_t code = ent >> MD_IDX_BITS;
+            if (code != 0u) {
+                dx += image_shift(code & 3u) * Lx;
+                dy += image_shift((code >> 2) & 3u) * Ly;
+                dz += image_shift((code >> 4) & 3u) * Lz;
+            }
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < rc2) {
+                const PairConst pc = TYPED ? tab[ti * a.ntypes + a.type[j]] : pc0;
+                double fr;
+                if (PREC == MD_FP64) {
+                    const double inv = rcp_f64(r2);
+                    const double s2 = pc.s2 * inv;
+                    const double s6 = s2 * s2 * s2;
+                    fr = pc.e24 * s6 * (2.0 * s6 - 1.0) * inv;
+                    ed += pc.e4 * s6 * (s6 - 1.0) - pc.ush;
+                    wd += fr * r2;
+                } else {
+                    const float r2f = static_cast<float>(r2);
+                    const float inv = __builtin_amdgcn_rcpf(r2f);
+                    const float s2 = static_cast<float>(pc.s2) * inv;
+                    const float s6 = s2 * s2 * s2;
+                    const float frf = static_cast<float>(pc.e24) * s6 * (2.0f * s6 - 1.0f) * inv;
+                    fr = static_cast<double>(frf);
+                    ef += static_cast<float>(pc.e4) * s6 * (s6 - 1.0f) - static_cast<float>(pc.ush);
+                    wf += frf * r2f;
+                }
+                fx = fma(fr, dx, fx);
+                fy = fma(fr, dy, fy);
+                fz = fma(fr, dz, fz);
+                if (HALF) {
+                    atomicAdd(a.fx + j, -fr * dx);
+                    atomicAdd(a.fy + j, -fr * dy);
+                    atomicAdd(a.fz + j, -fr * dz);
+                }
+            }
+        }
+        if (PREC != MD_FP64) {
+            ed = static_cast<double>(ef);
+            wd = static_cast<double>(wf);
+        }
+        e_acc = HALF ? ed : 0.5 * ed;
+        w_acc = HALF ? wd : 0.5 * wd;
+        if (HALF) {
+            atomicAdd(a.fx + i, fx);
+            atomicAdd(a.fy + i, fy);
+            atomicAdd(a.fz + i, fz);
+        } else if (a.accumulate) {
+            a.fx[i] += fx;
+            a.fy[i] += fy;
+            a.fz[i] += fz;
+        } else {
+            a.fx[i] = fx;
+            a.fy[i] = fy;
+            a.fz[i] = fz;
+        }
+        if (a.status && !isfinite(fx + fy + fz + ed)) atomicOr(a.status, MD_F_NONFINITE);
+    }
+    const double es = block_sum(e_acc, red);
+    const double ws = block_sum(w_acc, red);
+    if (threadIdx.x == 0) {
+        a.partial[size_t(u) * kPartials + 0] = es;
+        a.partial[size_t(u) * kPartials + 1] = ws;
+    }
+}
+
+__global__ __launch_bounds__(kUnit) void k_zero3(int32_t N, double *fx, double *fy, double *fz)
+{
+    const int i = blockIdx.x * kUnit + threadIdx.x;
+    if (i < N) {
+        fx[i] = 0.0;
+        fy[i] = 0.0;
+        fz[i] = 0.0;
+    }
+}
+
+}  // namespace
+
+// One workgroup per replica: fixed-order sum of slot `k0` (and `k0+1`) of its
+// work units' partials.
+__global__ __launch_bounds__(kUnit) void k_finalize_sum2(const int32_t *unit_off,
+                                                         const double *partial, int k0,
+                                                         double *out0, double *out1)
+{
+    __shared__ double red[kWavesPerUnit];
+    const int r = blockIdx.x;
+    const int u0 = unit_off[r], u1 = unit_off[r + 1];
+    double s0 = 0.0, s1 = 0.0;
+    for (int u = u0 + threadIdx.x; u < u1; u += kUnit) {
+        s0 += partial[size_t(u) * kPartials + k0];
+        s1 += partial[size_t(u) * kPartials + k0 + 1];
+    }
+    s0 = block_sum(s0, red);
+    s1 = block_sum(s1, red);
+    if (threadIdx.x == 0) {
+        if (out0) out0[r] = s0;
+        if (out1) out1[r] = s1;
+    }
+}
+
+void launch_finalize_sum2(int R, const int32_t *unit_off, const double *partial, int k0,
+                          double *out0, double *out1, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize_sum2, dim3(R), dim3(kUnit), 0, s, unit_off, partial, k0,
+                       out0, out1);
+}
+
+}  // namespace md
+
+extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
+                            const md_lj *p, int32_t prec, int32_t accumulate, double *energy,
+                            double *virial, void *ws, size_t ws_bytes, uint32_t *status,
+                            void *stream)
+{
+    using namespace md;
+    int e = check_batch(b);
+    if (e != MD_OK) return e;
+    if (!atoms || !atoms->x || !atoms->y || !atoms->z || !atoms->fx || !atoms->fy ||
+        !atoms->fz || !nl || !nl->count || !nl->idx || !p || !p->eps || !p->sig || !ws)
+        return MD_EINVAL;
+    if (nl->mode != MD_HALF && nl->mode != MD_FULL) return MD_EINVAL;
+    if (nl->max_nbr < 1 || nl->ld < b->N || nl->ld % 64 != 0) return MD_EINVAL;
+    if (p->ntypes < 1 || p->ntypes > MD_MAX_TYPES || !(p->rc > 0.0)) return MD_EINVAL;
+    if (p->ntypes > 1 && !atoms->type) return MD_EINVAL;
+    if (prec != MD_FP64 && prec != MD_FP32_MIXED) return MD_EINVAL;
+    const WsLayout l = ws_layout(b);
+    if (ws_bytes < l.total) return MD_ENOWS;
+    ForceArgs a{b->atom_off, b->unit_rep, b->unit_off, b->box, atoms->x, atoms->y, atoms->z,
+                atoms->type, nl->count, nl->idx, nl->ld, nl->max_nbr, p->eps, p->sig,
+                p->ntypes, p->shift, p->rc, atoms->fx, atoms->fy, atoms->fz, accumulate,
+                ws_at<double>(ws, l.partial), status};
+    hipStream_t s = as_stream(stream);
+    const dim3 grid(b->n_units), block(kUnit);
+    const bool half = nl->mode == MD_HALF, typed = p->ntypes > 1;
+    if (half && !accumulate)
+        hipLaunchKernelGGL(k_zero3, dim3((b->N + kUnit - 1) / kUnit), block, 0, s, b->N,
+                           atoms->fx, atoms->fy, atoms->fz);
+#define MD_LJ_LAUNCH(P, H, T) hipLaunchKernelGGL((k_lj<P, H, T>), grid, block, 0, s, a)
+    if (prec == MD_FP64) {
+        if (half) { if (typed) MD_LJ_LAUNCH(MD_FP64, true, true); else MD_LJ_LAUNCH(MD_FP64, true, false); }
+        else      { if (typed) MD_LJ_LAUNCH(MD_FP64, false, true); else MD_LJ_LAUNCH(MD_FP64, false, false); }
+    } else {
+        if (half) { if (typed) MD_LJ_LAUNCH(MD_FP32_MIXED, true, true); else MD_LJ_LAUNCH(MD_FP32_MIXED, true, false); }
+        else      { if (typed) MD_LJ_LAUNCH(MD_FP32_MIXED, false, true); else MD_LJ_LAUNCH(MD_FP32_MIXED, false, false); }
+    }
+#undef MD_LJ_LAUNCH
+    if (energy || virial)
+        launch_finalize_sum2(b->R, b->unit_off, ws_at<const double>(ws, l.partial), 0, energy,
+                             virial, s);
+    return launch_status();
+}

@@ -1,0 +1,210 @@
+// md_sort.hip -- md_cell_sort: cell binning and re-sort of the SoA arrays.
+//
+// The paper's Resort step (Sec. 2.1.3) re-bins particles into cells; its
+// SoA layout (Sec. 3.1) keeps each attribute in its own array.  Here the
+// atoms themselves are reordered cell by cell, so a cell's atoms are a
+// contiguous index range and neighbour gathers in the list build and the
+// force loop hit nearby addresses.
+//
+// Five stream-ordered kernels, each skipping replicas whose gate is 0:
+//   1 bin      wrap, cell index, histogram slot (atomic per cell)
+//   2 scan     per-replica exclusive scan of cell counts -> cell_start,
+//              clearing the counts for the next call
+//   3 keys     key[cell_start[c] + slot] = id   (cell members, any order)
+//   4 gather   rank inside the cell by id (deterministic order), gather the
+//              atom's wrapped data into scratch at its final index
+//   5 copy     scratch -> atoms, x_build := x
+#include "md_common.hpp"
+
+namespace md {
+namespace {
+
+struct BatchArgs {
+    const int32_t *atom_off, *cell_off, *ncell, *unit_rep, *unit_off;
+    const double *box;
+    const uint32_t *gate;
+};
+
+BatchArgs batch_args(const md_batch *b, const uint32_t *gate)
+{
+    return BatchArgs{b->atom_off, b->cell_off, b->ncell, b->unit_rep, b->unit_off, b->box, gate};
+}
+
+__device__ __forceinline__ bool gated_off(const BatchArgs &a, int rep)
+{
+    return a.gate != nullptr && a.gate[rep] == 0u;
+}
+
+__global__ __launch_bounds__(kUnit) void k_bin(BatchArgs a, const double *__restrict__ x,
+                                               const double *__restrict__ y,
+                                               const double *__restrict__ z,
+                                               int32_t *__restrict__ cell_count,
+                                               int32_t *__restrict__ cell_of,
+                                               int32_t *__restrict__ slot)
+{
+    const Unit w = unit_of(blockIdx.x, a.unit_rep, a.unit_off, a.atom_off);
+    if (gated_off(a, w.rep)) return;
+    const int i = w.begin + threadIdx.x;
+    if (i >= w.end) return;
+    const double *L = a.box + 3 * w.rep;
+    const int32_t *n = a.ncell + 3 * w.rep;
+    int s;
+    const int cx = cell_coord(wrap_coord(x[i], L[0], &s), L[0], n[0]);
+    const int cy = cell_coord(wrap_coord(y[i], L[1], &s), L[1], n[1]);
+    const int cz = cell_coord(wrap_coord(z[i], L[2], &s), L[2], n[2]);
+    const int c = a.cell_off[w.rep] + (cz * n[1] + cy) * n[0] + cx;
+    cell_of[i] = c;
+    slot[i] = atomicAdd(cell_count + c, 1);
+}
+
+// One workgroup per replica scans its cells in chunks of 4 * kUnit.
+__global__ __launch_bounds__(kUnit) void k_scan(BatchArgs a, int32_t *__restrict__ cell_count,
+                                                int32_t *__restrict__ cell_start)
+{
+    const int r = blockIdx.x;
+    if (gated_off(a, r)) return;
+    __shared__ int32_t wsum[kWavesPerUnit];
+    const int c0 = a.cell_off[r], c1 = a.cell_off[r + 1];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    int32_t carry = a.atom_off[r];
+    for (int base = c0; base < c1; base += 4 * kUnit) {
+        const int c = base + 4 * threadIdx.x;
+        int32_t v[4];
+        int32_t t = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = (c + k < c1) ? cell_count[c + k] : 0;
+            t += v[k];
+        }
+        // inclusive wave scan of t
+        int32_t inc = t;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            int32_t up = __shfl_up(inc, o, kWave);
+            if (lane >= o) inc += up;
+        }
+        if (lane == kWave - 1) wsum[wid] = inc;
+        __syncthreads();
+        int32_t before = 0, total = 0;
+        for (int k = 0; k < kWavesPerUnit; ++k) {
+            if (k < wid) before += wsum[k];
+            total += wsum[k];
+        }
+        int32_t run = carry + before + inc - t;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (c + k < c1) {
+                cell_start[c + k] = run;
+                cell_count[c + k] = 0;
+            }
+            run += v[k];
+        }
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cell_start[c1] = a.atom_off[r + 1];
+}
+
+__global__ __launch_bounds__(kUnit) void k_keys(BatchArgs a, const int32_t *__restrict__ id,
+                                                const int32_t *__restrict__ cell_of,
+                                                const int32_t *__restrict__ slot,
+                                                const int32_t *__restrict__ cell_start,
+                                                int32_t *__restrict__ key)
+{
+    const Unit w = unit_of(blockIdx.x, a.unit_rep, a.unit_off, a.atom_off);
+    if (gated_off(a, w.rep)) return;
+    const int i = w.begin + threadIdx.x;
+    if (i >= w.end) return;
+    key[cell_start[cell_of[i]] + slot[i]] = id[i];
+}
+
+__global__ __launch_bounds__(kUnit) void k_gather(BatchArgs a, md_atoms in, md_atoms out,
+                                                  int32_t N,
+                                                  const int32_t *__restrict__ cell_of,
+                                                  const int32_t *__restrict__ cell_start,
+                                                  const int32_t *__restrict__ key)
+{
+    const Unit w = unit_of(blockIdx.x, a.unit_rep, a.unit_off, a.atom_off);
+    if (gated_off(a, w.rep)) return;
+    const int i = w.begin + threadIdx.x;
+    if (i >= w.end) return;
+    const int c = cell_of[i];
+    const int s = cell_start[c], e = cell_start[c + 1];
+    const int32_t me = in.id[i];
+    int rank = 0;
+    for (int m = s; m < e; ++m) rank += key[m] < me ? 1 : 0;
+    const int dst = s + rank;
+    const double *L = a.box + 3 * w.rep;
+    int sx, sy, sz;
+    out.x[dst] = wrap_coord(in.x[i], L[0], &sx);
+    out.y[dst] = wrap_coord(in.y[i], L[1], &sy);
+    out.z[dst] = wrap_coord(in.z[i], L[2], &sz);
+    out.vx[dst] = in.vx[i];
+    out.vy[dst] = in.vy[i];
+    out.vz[dst] = in.vz[i];
+    out.type[dst] = in.type[i];
+    out.id[dst] = me;
+    out.img[dst] = in.img[i] + sx;
+    out.img[N + dst] = in.img[N + i] + sy;
+    out.img[2 * N + dst] = in.img[2 * N + i] + sz;
+    if (in.where) in.where[me] = dst;
+}
+
+__global__ __launch_bounds__(kUnit) void k_copy_back(BatchArgs a, md_atoms s, md_atoms d,
+                                                     int32_t N)
+{
+    const Unit w = unit_of(blockIdx.x, a.unit_rep, a.unit_off, a.atom_off);
+    if (gated_off(a, w.rep)) return;
+    const int i = w.begin + threadIdx.x;
+    if (i >= w.end) return;
+    const double x = s.x[i], y = s.y[i], z = s.z[i];
+    d.x[i] = x; d.y[i] = y; d.z[i] = z;
+    d.xb[i] = x; d.yb[i] = y; d.zb[i] = z;
+    d.vx[i] = s.vx[i]; d.vy[i] = s.vy[i]; d.vz[i] = s.vz[i];
+    d.type[i] = s.type[i];
+    d.id[i] = s.id[i];
+    d.img[i] = s.img[i];
+    d.img[N + i] = s.img[N + i];
+    d.img[2 * N + i] = s.img[2 * N + i];
+}
+
+bool atoms_ok(const md_atoms *a, bool need_build)
+{
+    if (!a) return false;
+    const void *dbl[] = {a->x, a->y, a->z, a->vx, a->vy, a->vz};
+    for (const void *q : dbl)
+        if (!q || !aligned8(q)) return false;
+    if (!a->type || !a->id || !a->img) return false;
+    if (need_build && (!a->xb || !a->yb || !a->zb)) return false;
+    return true;
+}
+
+}  // namespace
+}  // namespace md
+
+extern "C" int md_cell_sort(const md_batch *b, md_atoms *atoms, md_atoms *scratch,
+                            int32_t *cell_start, void *ws, size_t ws_bytes,
+                            const uint32_t *gate, uint32_t *status, void *stream)
+{
+    using namespace md;
+    (void)status;
+    int e = check_batch(b);
+    if (e != MD_OK) return e;
+    if (!atoms_ok(atoms, true) || !atoms_ok(scratch, false) || !cell_start || !ws)
+        return MD_EINVAL;
+    const WsLayout l = ws_layout(b);
+    if (ws_bytes < l.total) return MD_ENOWS;
+    hipStream_t s = as_stream(stream);
+    const BatchArgs a = batch_args(b, gate);
+    int32_t *cnt = ws_at<int32_t>(ws, l.cell_count);
+    int32_t *cell_of = ws_at<int32_t>(ws, l.cell_of);
+    int32_t *slot = ws_at<int32_t>(ws, l.slot);
+    int32_t *key = ws_at<int32_t>(ws, l.key);
+    const dim3 grid(b->n_units), block(kUnit);
+    hipLaunchKernelGGL(k_bin, grid, block, 0, s, a, atoms->x, atoms->y, atoms->z, cnt, cell_of, slot);
+    hipLaunchKernelGGL(k_scan, dim3(b->R), block, 0, s, a, cnt, cell_start);
+    hipLaunchKernelGGL(k_keys, grid, block, 0, s, a, atoms->id, cell_of, slot, cell_start, key);
+    hipLaunchKernelGGL(k_gather, grid, block, 0, s, a, *atoms, *scratch, b->N, cell_of, cell_start, key);
+    hipLaunchKernelGGL(k_copy_back, grid, block, 0, s, a, *scratch, *atoms, b->N);
+    return launch_status();
+}

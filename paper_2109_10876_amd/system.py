@@ -1,0 +1,286 @@
+"""Device-resident MD state and the step loop, driving libmd through its C ABI.
+
+PyTorch only allocates device memory and supplies the HIP stream; every
+step of the path (re-sort, list build, forces, integration, reductions)
+runs in libmd's kernels.  The step follows Fig. 1 of the paper:
+
+    Integrate1 -> [skin test -> Resort + Neigh] -> forces -> Integrate2
+
+with the skin test evaluated on the device (a per-replica gate that the
+re-sort and list-build kernels read), so a step never waits for the host.
+Consecutive steps fuse Integrate2 of one step with Integrate1 of the next.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import _abi as abi
+from ._abi import check
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class MDSystem:
+    """R independent periodic LJ systems, concatenated, resident on one GPU.
+
+    Parameters mirror a workload description: per-replica atom counts and
+    boxes, initial positions/velocities [N,3] (replicas concatenated), atom
+    types, symmetric (eps, sigma) tables, masses per type, cutoff rc, skin,
+    time step.  ``mode`` is "full" or "half" (Verlet list storage), ``prec``
+    is "fp64" or "mixed" (FP32 pair polynomial, FP64 accumulation).
+    """
+
+    def __init__(self, natoms, box, pos, vel, types=None, eps=1.0, sig=1.0, mass=None,
+                 rc=2.5, skin=0.3, dt=0.005, shift=1, mode="full", prec="fp64",
+                 max_nbr=None, device="cuda"):
+        self.lib = abi.load()
+        self.dev = torch.device(device)
+        natoms = np.asarray(natoms, dtype=np.int32).ravel()
+        box = np.asarray(box, dtype=np.float64).reshape(-1, 3)
+        self.R = int(natoms.shape[0])
+        self.rc, self.skin, self.dt, self.shift = float(rc), float(skin), float(dt), int(shift)
+        self.mode = abi.MD_FULL if mode == "full" else abi.MD_HALF
+        self.prec = abi.MD_FP64 if prec == "fp64" else abi.MD_FP32_MIXED
+        eps = np.atleast_2d(np.asarray(eps, dtype=np.float64))
+        sig = np.atleast_2d(np.asarray(sig, dtype=np.float64))
+        self.ntypes = int(eps.shape[0])
+        mass = np.ones(self.ntypes) if mass is None else np.asarray(mass, np.float64).ravel()
+
+        # ---- host planning
+        N, C, U = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check("md_plan_sizes", self.lib.md_plan_sizes(
+            self.R, natoms.ctypes.data, box.ctypes.data, self.rc, self.skin,
+            ctypes.byref(N), ctypes.byref(C), ctypes.byref(U)))
+        self.N, self.C, self.n_units = N.value, C.value, U.value
+        h_atom_off = np.zeros(self.R + 1, np.int32)
+        h_cell_off = np.zeros(self.R + 1, np.int32)
+        h_ncell = np.zeros(3 * self.R, np.int32)
+        h_unit_rep = np.zeros(self.n_units, np.int32)
+        h_unit_off = np.zeros(self.R + 1, np.int32)
+        check("md_plan_fill", self.lib.md_plan_fill(
+            self.R, natoms.ctypes.data, box.ctypes.data, self.rc, self.skin,
+            h_atom_off.ctypes.data, h_cell_off.ctypes.data, h_ncell.ctypes.data,
+            h_unit_rep.ctypes.data, h_unit_off.ctypes.data))
+        self.h_atom_off, self.h_ncell, self.h_box = h_atom_off, h_ncell.reshape(-1, 3), box
+        d = self.dev
+        i32 = lambda a: torch.as_tensor(a, dtype=torch.int32).to(d)
+        f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).to(d)
+        self.atom_off, self.cell_off = i32(h_atom_off), i32(h_cell_off)
+        self.ncell, self.box = i32(h_ncell), f64(box.ravel())
+        self.unit_rep, self.unit_off = i32(h_unit_rep), i32(h_unit_off)
+        self.batch = abi.MdBatch(self.R, self.N, self.C, self.n_units,
+                                 self.atom_off.data_ptr(), self.cell_off.data_ptr(),
+                                 self.ncell.data_ptr(), self.box.data_ptr(),
+                                 self.unit_rep.data_ptr(), self.unit_off.data_ptr())
+
+        # ---- atom state (SoA planes)
+        pos = np.asarray(pos, np.float64).reshape(self.N, 3)
+        vel = np.asarray(vel, np.float64).reshape(self.N, 3)
+        types = np.zeros(self.N, np.int32) if types is None else np.asarray(types, np.int32)
+        z64 = lambda: torch.zeros(self.N, dtype=torch.float64, device=d)
+        self.x, self.y, self.z = (f64(pos[:, k]) for k in range(3))
+        self.vx, self.vy, self.vz = (f64(vel[:, k]) for k in range(3))
+        self.fx, self.fy, self.fz = z64(), z64(), z64()
+        self.xb, self.yb, self.zb = self.x.clone(), self.y.clone(), self.z.clone()
+        self.type = i32(types)
+        self.id = torch.arange(self.N, dtype=torch.int32, device=d)
+        self.img = torch.zeros(3 * self.N, dtype=torch.int32, device=d)
+        self.where = torch.arange(self.N, dtype=torch.int32, device=d)
+        self.atoms = self._atoms_struct(self)
+        # re-sort scratch planes
+        self.s_x, self.s_y, self.s_z, self.s_vx, self.s_vy, self.s_vz = (z64() for _ in range(6))
+        self.s_type = torch.zeros(self.N, dtype=torch.int32, device=d)
+        self.s_id = torch.zeros(self.N, dtype=torch.int32, device=d)
+        self.s_img = torch.zeros(3 * self.N, dtype=torch.int32, device=d)
+        self.scratch = abi.MdAtoms(self.s_x.data_ptr(), self.s_y.data_ptr(), self.s_z.data_ptr(),
+                                   self.s_vx.data_ptr(), self.s_vy.data_ptr(),
+                                   self.s_vz.data_ptr(), None, None, None, None, None, None,
+                                   self.s_type.data_ptr(), self.s_id.data_ptr(),
+                                   self.s_img.data_ptr(), None)
+
+        # ---- parameters, list, workspace, outputs
+        self.eps_t, self.sig_t = f64(eps.ravel()), f64(sig.ravel())
+        self.inv_mass = f64(1.0 / mass)
+        self.lj = abi.MdLj(self.ntypes, self.shift, self.rc, self.eps_t.data_ptr(),
+                           self.sig_t.data_ptr())
+        self.cell_start = torch.zeros(self.C + 1, dtype=torch.int32, device=d)
+        self.ld = (self.N + 63) // 64 * 64
+        if max_nbr is None:
+            # ideal-gas estimate of neighbours within rc + skin, with margin
+            rho = float(np.max(natoms / np.prod(box, axis=1)))
+            full = 4.0 / 3.0 * math.pi * (self.rc + self.skin) ** 3 * rho
+            max_nbr = int(1.35 * full * (0.5 if self.mode == abi.MD_HALF else 1.0)) + 16
+        self._alloc_list(max_nbr)
+        self.ws_bytes = int(self.lib.md_workspace_bytes(ctypes.byref(self.batch)))
+        self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=d)
+        self.gate = torch.ones(self.R, dtype=torch.int32, device=d)
+        self.status = torch.zeros(1, dtype=torch.int32, device=d)
+        self.need = torch.zeros(1, dtype=torch.int32, device=d)
+        self.energy = torch.zeros(self.R, dtype=torch.float64, device=d)
+        self.virial = torch.zeros(self.R, dtype=torch.float64, device=d)
+        self.ke = torch.zeros(self.R, dtype=torch.float64, device=d)
+        self._graph = None
+
+    @staticmethod
+    def _atoms_struct(s):
+        return abi.MdAtoms(s.x.data_ptr(), s.y.data_ptr(), s.z.data_ptr(), s.vx.data_ptr(),
+                           s.vy.data_ptr(), s.vz.data_ptr(), s.fx.data_ptr(), s.fy.data_ptr(),
+                           s.fz.data_ptr(), s.xb.data_ptr(), s.yb.data_ptr(), s.zb.data_ptr(),
+                           s.type.data_ptr(), s.id.data_ptr(), s.img.data_ptr(),
+                           s.where.data_ptr())
+
+    def _alloc_list(self, max_nbr):
+        self.max_nbr = int(max_nbr)
+        self.count = torch.zeros(self.N, dtype=torch.int32, device=self.dev)
+        self.idx = torch.zeros(self.max_nbr * self.ld, dtype=torch.int32, device=self.dev)
+        self.nlist = abi.MdNlist(self.mode, self.max_nbr, self.ld, 0, self.count.data_ptr(),
+                                 self.idx.data_ptr())
+
+    @property
+    def stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)
+
+    # ------------------------------------------------------------ ABI calls
+    def sort(self, gated=True):
+        check("md_cell_sort", self.lib.md_cell_sort(
+            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.scratch),
+            _ptr(self.cell_start), _ptr(self.ws), self.ws_bytes,
+            _ptr(self.gate) if gated else None, _ptr(self.status), self.stream))
+
+    def build(self, gated=True):
+        check("md_verlet_build", self.lib.md_verlet_build(
+            ctypes.byref(self.batch), ctypes.byref(self.atoms), _ptr(self.cell_start),
+            self.rc, self.skin, ctypes.byref(self.nlist), _ptr(self.need),
+            _ptr(self.gate) if gated else None, _ptr(self.status), self.stream))
+
+    def forces(self, accumulate=False):
+        check("md_lj_forces", self.lib.md_lj_forces(
+            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.nlist),
+            ctypes.byref(self.lj), self.prec, int(accumulate), _ptr(self.energy),
+            _ptr(self.virial), _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
+
+    def vv(self, phase):
+        check("md_vv_step", self.lib.md_vv_step(
+            ctypes.byref(self.batch), ctypes.byref(self.atoms), int(phase), self.dt,
+            _ptr(self.inv_mass), self.ntypes, self.skin, _ptr(self.gate), _ptr(self.ke),
+            _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
+
+    def vjp(self, gfx, gfy, gfz, gE, gx, geps=None, gsig=None):
+        check("md_lj_forces_vjp", self.lib.md_lj_forces_vjp(
+            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.nlist),
+            ctypes.byref(self.lj), self.prec, _ptr(gfx), _ptr(gfy), _ptr(gfz), _ptr(gE),
+            _ptr(gx), _ptr(geps), _ptr(gsig), _ptr(self.ws), self.ws_bytes,
+            _ptr(self.status), self.stream))
+
+    # ------------------------------------------------------------ the step
+    def setup(self):
+        """Initial re-sort, list build and forces (all replicas)."""
+        self.sort(gated=False)
+        self.build(gated=False)
+        self.ensure_list()
+        self.forces()
+
+    def ensure_list(self):
+        """Synchronise; on list overflow grow max_nbr and rebuild every replica."""
+        torch.cuda.synchronize(self.dev)
+        st = int(self.status.item())
+        if st & abi.MD_F_NBR_OVERFLOW:
+            need = int(self.need.item())
+            self._alloc_list(int(need * 1.2) + 8)
+            self._graph = None   # captured launches hold the old list pointers
+            self.status.zero_()
+            self.need.zero_()
+            self.build(gated=False)
+            torch.cuda.synchronize(self.dev)
+            st = int(self.status.item())
+        if st & ~abi.MD_F_NBR_OVERFLOW:
+            raise RuntimeError(f"device status flags 0x{st:x}")
+        return st
+
+    def step_body(self, first):
+        """One velocity-Verlet step except its final half kick."""
+        self.vv(1 if first else 3)
+        self.sort()
+        self.build()
+        self.forces()
+
+    def run(self, steps, check_every=50):
+        """`steps` full steps (Integrate2 of step s fused with Integrate1 of s+1)."""
+        for s in range(steps):
+            self.step_body(first=(s == 0))
+            if check_every and (s + 1) % check_every == 0:
+                self.ensure_list()
+        self.vv(2)
+
+    def capture(self, k):
+        """Capture k fused steps (Integrate2+Integrate1, gated re-sort and list
+        build, forces) as one HIP graph; replays launch on the current stream."""
+        torch.cuda.synchronize(self.dev)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(k):
+                self.step_body(first=False)
+        torch.cuda.synchronize(self.dev)
+        self._graph = (k, g)
+        return g
+
+    def run_graphed(self, steps, k=50):
+        """Same trajectory as run(steps) with the repeated steps replayed from a
+        captured graph of k steps.  Status flags are not inspected here."""
+        if self._graph is None or self._graph[0] != k:
+            self.capture(k)
+        kk, g = self._graph
+        self.step_body(first=True)
+        rest = steps - 1
+        for _ in range(rest // kk):
+            g.replay()
+        for _ in range(rest % kk):
+            self.step_body(first=False)
+        self.vv(2)
+
+    # ------------------------------------------------------------ readback
+    def order(self):
+        """Current slot of each original atom id."""
+        return self.where.cpu().numpy()
+
+    def positions(self):
+        """Unwrapped positions [N,3] in original id order (x + img L)."""
+        ids = self.id.cpu().numpy()
+        L = np.repeat(self.h_box, np.diff(self.h_atom_off), axis=0)
+        img = self.img.cpu().numpy().reshape(3, self.N).T
+        p = np.stack([self.x.cpu().numpy(), self.y.cpu().numpy(), self.z.cpu().numpy()], 1)
+        rep = np.repeat(np.arange(self.R), np.diff(self.h_atom_off))
+        out = np.empty_like(p)
+        out[ids] = p + img * self.h_box[rep]
+        return out
+
+    def _by_id(self, a, b, c):
+        ids = self.id.cpu().numpy()
+        out = np.empty((self.N, 3))
+        out[ids] = np.stack([a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()], 1)
+        return out
+
+    def velocities(self):
+        return self._by_id(self.vx, self.vy, self.vz)
+
+    def forces_np(self):
+        return self._by_id(self.fx, self.fy, self.fz)
+
+    def list_pairs(self):
+        """Verlet list as (id_i, id_j) pairs [P,2] plus decoded image codes."""
+        cnt = self.count.cpu().numpy()
+        n = np.minimum(cnt, self.max_nbr)
+        idx = self.idx.cpu().numpy().view(np.uint32).reshape(self.max_nbr, self.ld)[:, :self.N]
+        k = np.arange(self.max_nbr)[:, None]
+        mask = k < n[None, :]
+        ent = idx[mask.nonzero()]
+        ii = np.nonzero(mask)[1]
+        jj = (ent & abi.MD_IDX_MASK).astype(np.int64)
+        ids = self.id.cpu().numpy()
+        return np.stack([ids[ii], ids[jj]], 1), (ent >> abi.MD_IDX_BITS)

@@ -1,0 +1,118 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+that include/md.h declares, and validates arguments on the host (no GPU
+work is enqueued by any call here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2109_10876_amd import _abi as abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "md.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(md_[a-z_0-9]+)\s*\(",
+                                 src, flags=re.M)))
+
+
+def test_header_and_binding_agree():
+    assert set(_declared()) == set(abi.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = abi.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.md_abi_version() == 1
+
+
+def test_header_constants_match_binding():
+    src = open(os.path.join(ROOT, "include", "md.h")).read()
+    for name in ("MD_OK", "MD_EINVAL", "MD_EBOX", "MD_ENOWS", "MD_EUNSUPPORTED", "MD_EHIP",
+                 "MD_ERANGE", "MD_HALF", "MD_FULL", "MD_FP64", "MD_FP32_MIXED",
+                 "MD_UNIT_ATOMS", "MD_IDX_BITS", "MD_MAX_TYPES"):
+        m = re.search(rf"#define\s+{name}\s+(-?\w+)", src)
+        assert m, name
+        assert int(m.group(1), 0) == getattr(abi, name), name
+
+
+def _plan(natoms, box, rc=2.5, skin=0.3):
+    lib = abi.load()
+    natoms = np.asarray(natoms, np.int32)
+    box = np.asarray(box, np.float64).reshape(-1, 3)
+    N, C, U = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    code = lib.md_plan_sizes(len(natoms), natoms.ctypes.data, box.ctypes.data, rc, skin,
+                             ctypes.byref(N), ctypes.byref(C), ctypes.byref(U))
+    return code, N.value, C.value, U.value
+
+
+def test_plan_single_system():
+    # 1,048,576 atoms in a 107.494 box: 38 cells of edge >= 2.8 per dimension
+    L = (1048576 / 0.8442) ** (1 / 3)
+    code, N, C, U = _plan([1048576], [L, L, L])
+    assert code == abi.MD_OK
+    assert (N, C, U) == (1048576, 38 ** 3, 4096)
+
+
+def test_plan_fill_batch():
+    lib = abi.load()
+    natoms = np.array([500, 257, 3000], np.int32)
+    box = np.array([[8.5, 8.5, 8.5], [7.0, 6.0, 5.7], [15.2, 15.2, 15.2]])
+    code, N, C, U = _plan(natoms, box)
+    assert code == abi.MD_OK and N == 3757 and U == 2 + 2 + 12
+    ao, co, uo = (np.zeros(4, np.int32) for _ in range(3))
+    nc = np.zeros(9, np.int32)
+    ur = np.zeros(U, np.int32)
+    assert lib.md_plan_fill(3, natoms.ctypes.data, box.ctypes.data, 2.5, 0.3, ao.ctypes.data,
+                            co.ctypes.data, nc.ctypes.data, ur.ctypes.data,
+                            uo.ctypes.data) == abi.MD_OK
+    assert list(ao) == [0, 500, 757, 3757]
+    assert list(nc) == [3, 3, 3, 2, 2, 2, 5, 5, 5]
+    assert list(co) == [0, 27, 35, 160] and C == 160
+    assert list(uo) == [0, 2, 4, 16]
+    assert list(ur) == [0, 0, 1, 1] + [2] * 12
+
+
+@pytest.mark.parametrize("natoms,box,rc,skin,code", [
+    ([100], [5.5, 8, 8], 2.5, 0.3, abi.MD_EBOX),      # L < 2 (rc + skin)
+    ([0], [8, 8, 8], 2.5, 0.3, abi.MD_EINVAL),        # empty replica
+    ([10], [8, 8, 8], -1.0, 0.3, abi.MD_EINVAL),      # negative cutoff
+    ([10], [8, -8, 8], 2.5, 0.3, abi.MD_EINVAL),      # negative box
+    ([1 << 26], [500, 500, 500], 2.5, 0.3, abi.MD_ERANGE),
+])
+def test_plan_rejects(natoms, box, rc, skin, code):
+    assert _plan(natoms, box, rc, skin)[0] == code
+
+
+def test_calls_reject_bad_arguments_without_a_gpu():
+    lib = abi.load()
+    P = ctypes.byref
+    bad = abi.MdBatch()   # R = 0
+    atoms, nl, lj = abi.MdAtoms(), abi.MdNlist(), abi.MdLj()
+    assert lib.md_cell_sort(P(bad), P(atoms), P(atoms), None, None, 0, None, None, None) == abi.MD_EINVAL
+    assert lib.md_verlet_build(P(bad), P(atoms), None, 2.5, 0.3, P(nl), None, None, None, None) == abi.MD_EINVAL
+    assert lib.md_lj_forces(P(bad), P(atoms), P(nl), P(lj), 0, 0, None, None, None, 0, None, None) == abi.MD_EINVAL
+    assert lib.md_vv_step(P(bad), P(atoms), 1, 0.005, None, 1, 0.3, None, None, None, 0, None, None) == abi.MD_EINVAL
+    assert lib.md_lj_forces_vjp(P(bad), P(atoms), P(nl), P(lj), 0, None, None, None, None, None,
+                                None, None, None, 0, None, None) == abi.MD_EINVAL
+    assert lib.md_workspace_bytes(P(bad)) == 0
+    # a well-formed batch (fake device pointers) still fails on missing arrays,
+    # on bad modes and on a short workspace, before anything is launched
+    ok = abi.MdBatch(1, 1000, 27, 4, 8, 8, 8, 8, 8, 8)
+    assert lib.md_workspace_bytes(P(ok)) > 0
+    nl = abi.MdNlist(7, 64, 1024, 0, 8, 8)
+    assert lib.md_verlet_build(P(ok), P(atoms), 8, 2.5, 0.3, P(nl), None, None, None, None) == abi.MD_EINVAL
+    full = abi.MdAtoms(*([8] * 16))
+    nl = abi.MdNlist(abi.MD_HALF, 64, 1000, 0, 8, 8)   # ld not a multiple of 64
+    lj1 = abi.MdLj(1, 1, 2.5, 8, 8)
+    assert lib.md_lj_forces(P(ok), P(full), P(nl), P(lj1), 0, 0, None, None, 8, 1 << 30, None, None) == abi.MD_EINVAL
+    nl = abi.MdNlist(abi.MD_HALF, 64, 1024, 0, 8, 8)
+    assert lib.md_lj_forces(P(ok), P(full), P(nl), P(lj1), 5, 0, None, None, 8, 1 << 30, None, None) == abi.MD_EINVAL
+    assert lib.md_lj_forces(P(ok), P(full), P(nl), P(lj1), 0, 0, None, None, 8, 16, None, None) == abi.MD_ENOWS
+    assert lib.md_lj_forces_vjp(P(ok), P(full), P(nl), P(lj1), 0, 8, 8, 8, None, 8, None, None,
+                                8, 1 << 30, None, None) == abi.MD_EUNSUPPORTED
+    assert lib.md_vv_step(P(ok), P(full), 4, 0.005, 8, 1, 0.3, 8, None, 8, 1 << 30, None, None) == abi.MD_EINVAL

@@ -1,0 +1,319 @@
+"""GPU parity: libmd (through its C ABI) against the FP64 oracle.
+
+Tolerances (derivations):
+  FP64 path -- same arithmetic, different summation order and a reciprocal
+    refined by Newton steps: per-atom force error ~ (terms) x (largest term)
+    x 2^-53 ~ 50 x 200 x 1.1e-16 ~ 1e-12; bound 1e-10 absolute, 1e-12
+    normwise; energy/virial relative 1e-12.
+  FP32-mixed path -- single-precision reciprocal (1 ulp) and LJ polynomial:
+    relative pair-force error ~ 10 x 2^-24 ~ 6e-7, partly cancelling in the
+    sum; the required bound is the target's 1e-5 normwise relative force
+    error; energy and virial relative 1e-6.
+  Integer work (pair sets, counts, rebuild schedule): exact.
+"""
+import numpy as np
+import pytest
+
+import md_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+RC, SKIN = 2.5, 0.3
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def _system(cfg, **kw):
+    from paper_2109_10876_amd import MDSystem
+    return MDSystem(cfg.natoms, cfg.box, cfg.pos, cfg.vel, cfg.types, cfg.eps, cfg.sig,
+                    cfg.mass, rc=cfg.rc, skin=cfg.skin, dt=cfg.dt, shift=cfg.shift, **kw)
+
+
+def _err(f, ref):
+    return np.linalg.norm(f - ref) / np.linalg.norm(ref)
+
+
+@pytest.fixture(scope="module")
+def c1_snapshot():
+    # 4000-atom LJ fluid (FCC 10^3 x 4, rho 0.8442), sites jittered so forces are non-zero
+    return md_inputs.lj_fluid(10, temperature=0.72, seed=1, jitter_amp=0.1)
+
+
+@pytest.mark.parametrize("mode", ["full", "half"])
+def test_forces_fp64_match_oracle(c1_snapshot, mode):
+    cfg = c1_snapshot
+    say(f"case: forces fp64 {mode} N={cfg.n}")
+    s = _system(cfg, mode=mode, prec="fp64")
+    s.setup()
+    assert s.ensure_list() == 0
+    f = s.forces_np()
+    ref, e, w = oracle.lj_forces(cfg.pos, cfg.box[0], RC, shift=1)
+    assert np.abs(f - ref).max() < 1e-10
+    assert _err(f, ref) < 1e-12
+    assert float(s.energy[0]) == pytest.approx(e, rel=1e-12)
+    assert float(s.virial[0]) == pytest.approx(w, rel=1e-12)
+
+
+@pytest.mark.parametrize("mode", ["full", "half"])
+def test_forces_mixed_within_bound(c1_snapshot, mode):
+    cfg = c1_snapshot
+    say(f"case: forces mixed {mode} N={cfg.n}")
+    s = _system(cfg, mode=mode, prec="mixed")
+    s.setup()
+    f = s.forces_np()
+    ref, e, w = oracle.lj_forces(cfg.pos, cfg.box[0], RC, shift=1)
+    err = _err(f, ref)
+    say(f"  mixed e_F = {err:.3e}")
+    assert err < 1e-5
+    assert float(s.energy[0]) == pytest.approx(e, rel=1e-6)
+    assert float(s.virial[0]) == pytest.approx(w, rel=1e-6)
+
+
+def test_full_list_forces_are_deterministic_and_match_half(c1_snapshot):
+    cfg = c1_snapshot
+    say("case: determinism full vs half")
+    a = _system(cfg, mode="full")
+    a.setup()
+    b = _system(cfg, mode="full")
+    b.setup()
+    assert np.array_equal(a.forces_np(), b.forces_np())
+    h = _system(cfg, mode="half")
+    h.setup()
+    assert np.abs(h.forces_np() - a.forces_np()).max() < 1e-10
+
+
+def _unordered(pairs):
+    p = np.sort(pairs, axis=1)
+    return set(map(tuple, np.unique(p, axis=0)))
+
+
+@pytest.mark.parametrize("mode", ["full", "half"])
+def test_verlet_list_is_the_skin_pair_set(c1_snapshot, mode):
+    cfg = c1_snapshot
+    say(f"case: list set {mode}")
+    s = _system(cfg, mode=mode)
+    s.setup()
+    pairs, codes = s.list_pairs()
+    # each unordered pair exactly twice (full) or once (half)
+    p = np.sort(pairs, axis=1)
+    _, mult = np.unique(p, axis=0, return_counts=True)
+    assert np.all(mult == (2 if mode == "full" else 1))
+    got = _unordered(pairs)
+    rl = RC + SKIN
+    ref = oracle.pairs_cells(cfg.pos, cfg.box[0], rl)
+    exp = set(map(tuple, ref))
+    # the set is unique up to pairs within rounding of the Verlet radius
+    diff = got.symmetric_difference(exp)
+    for i, j in diff:
+        d = cfg.pos[i] - cfg.pos[j]
+        d -= cfg.box[0] * np.rint(d / cfg.box[0])
+        assert abs(np.dot(d, d) - rl * rl) < 1e-10
+    assert len(diff) <= 2
+
+
+def test_fcc_lattice_exact_counts():
+    cfg = md_inputs.lj_fluid(10, temperature=0.72, seed=1)
+    say("case: fcc counts")
+    for mode, per in (("full", 78), ("half", 39)):
+        s = _system(cfg, mode=mode)
+        s.setup()
+        cnt = s.count.cpu().numpy()
+        if mode == "full":
+            assert np.all(cnt == per)
+        else:
+            assert cnt.sum() == per * cfg.n
+        assert np.abs(s.forces_np()).max() < 1e-10
+
+
+def test_trajectory_matches_oracle_100_steps():
+    # the 4000-atom parity workload: T = 0.72, 100 NVE steps, FP64
+    cfg = md_inputs.lj_fluid(10, temperature=0.72, seed=1)
+    say("case: trajectory 100 steps fp64")
+    s = _system(cfg, mode="full", prec="fp64")
+    s.setup()
+    flags, ek, ep = [], [], []
+    for t in range(cfg.steps):
+        s.step_body(first=(t == 0))
+        flags.append(int(s.gate[0].item()))
+        ep.append(float(s.energy[0]))
+        if t > 0:
+            ek.append(float(s.ke[0]))
+    s.vv(2)
+    ek.append(float(s.ke[0]))
+    assert s.ensure_list() == 0
+    ref = oracle.md_run(cfg.pos, cfg.vel, cfg.box[0], RC, SKIN, cfg.dt, cfg.steps)
+    assert flags == list(ref["rebuild"].astype(int))
+    assert sum(flags) >= 1
+    assert np.abs(s.positions() - ref["pos"]).max() < 1e-9
+    assert np.abs(s.velocities() - ref["vel"]).max() < 1e-9
+    np.testing.assert_allclose(ep, ref["epot"][1:], rtol=1e-10)
+    np.testing.assert_allclose(ek, ref["ekin"][1:], rtol=1e-10)
+
+
+def test_graph_replays_match_eager_steps():
+    cfg = md_inputs.lj_fluid(8, temperature=1.5, seed=21)
+    say("case: graph replay vs eager")
+    a = _system(cfg)
+    a.setup()
+    a.run(36, check_every=0)
+    b = _system(cfg)
+    b.setup()
+    b.run_graphed(36, k=5)      # 7 replays with eager work between them
+    b.ensure_list()
+    a.ensure_list()
+    assert np.array_equal(a.positions(), b.positions())
+    assert np.array_equal(a.forces_np(), b.forces_np())
+    assert float(a.ke[0]) == float(b.ke[0])
+    # the same captured graph again, from a new starting point
+    a.run(12, check_every=0)
+    b.run_graphed(12, k=5)
+    a.ensure_list()
+    b.ensure_list()
+    assert np.array_equal(a.positions(), b.positions())
+
+
+def test_mixed_trajectory_short_horizon():
+    cfg = md_inputs.lj_fluid(10, temperature=0.72, seed=1)
+    say("case: trajectory 20 steps mixed")
+    s = _system(cfg, mode="full", prec="mixed")
+    s.setup()
+    s.run(20)
+    s.ensure_list()
+    ref = oracle.md_run(cfg.pos, cfg.vel, cfg.box[0], RC, SKIN, cfg.dt, 20)
+    assert np.abs(s.positions() - ref["pos"]).max() < 1e-6
+    assert float(s.ke[0]) == pytest.approx(ref["ekin"][-1], rel=1e-6)
+
+
+def test_contains_all_pairs_within_cutoff_along_a_trajectory():
+    cfg = md_inputs.lj_fluid(8, temperature=1.5, seed=9)
+    say("case: containment along trajectory")
+    s = _system(cfg, mode="half")
+    s.setup()
+    for chunk in range(4):
+        s.run(15, check_every=0)
+        s.ensure_list()
+        pos = s.positions()
+        need = set(map(tuple, oracle.pairs_cells(pos, cfg.box[0], RC)))
+        assert need <= _unordered(s.list_pairs()[0])
+
+
+def test_neighbour_overflow_is_flagged_then_recovered(c1_snapshot):
+    from paper_2109_10876_amd import _abi as abi
+    cfg = c1_snapshot
+    say("case: overflow")
+    s = _system(cfg, mode="full", max_nbr=10)
+    s.sort(gated=False)
+    s.build(gated=False)
+    import torch
+    torch.cuda.synchronize()
+    assert int(s.status.item()) & abi.MD_F_NBR_OVERFLOW
+    assert int(s.need.item()) == int(s.count.max().item()) > 10
+    s.ensure_list()
+    assert s.max_nbr >= int(s.count.max().item())
+    s.forces()
+    ref, _, _ = oracle.lj_forces(cfg.pos, cfg.box[0], RC, shift=1)
+    assert np.abs(s.forces_np() - ref).max() < 1e-10
+
+
+def test_small_boxes_with_two_cells_per_dimension():
+    # replicas of 500 atoms: box 8.398 gives 2 cells of edge >= 2.8 per dimension
+    cfg = md_inputs.replica_batch(nrep=5, nmin=500, nmax=700, seed=11)
+    say("case: small replicas")
+    for mode in ("full", "half"):
+        s = _system(cfg, mode=mode)
+        s.setup()
+        f = s.forces_np()
+        off = cfg.atom_off()
+        for r in range(cfg.nrep):
+            a, b = off[r], off[r + 1]
+            ref, e, w = oracle.lj_forces(cfg.pos[a:b], cfg.box[r], RC, cfg.eps, cfg.sig,
+                                         cfg.types[a:b], 1)
+            assert np.abs(f[a:b] - ref).max() < 1e-9
+            assert float(s.energy[r]) == pytest.approx(e, rel=1e-12)
+            assert float(s.virial[r]) == pytest.approx(w, rel=1e-12)
+
+
+def test_batch_equals_each_replica_alone():
+    cfg = md_inputs.replica_batch(nrep=6, nmin=500, nmax=5000, seed=12)
+    say("case: batch vs single")
+    s = _system(cfg)
+    s.setup()
+    s.run(10)
+    s.ensure_list()
+    pos_b, f_b = s.positions(), s.forces_np()
+    off = cfg.atom_off()
+    for r in (0, 3, 5):
+        a, b = off[r], off[r + 1]
+        one = md_inputs.Config("one", cfg.pos[a:b], cfg.vel[a:b], cfg.box[r:r + 1],
+                               cfg.natoms[r:r + 1], cfg.types[a:b], 2, cfg.eps, cfg.sig,
+                               cfg.mass, RC, SKIN, cfg.dt, 1.0, 10)
+        t = _system(one)
+        t.setup()
+        t.run(10)
+        t.ensure_list()
+        assert np.array_equal(t.positions(), pos_b[a:b])
+        assert np.array_equal(t.forces_np(), f_b[a:b])
+        assert float(t.ke[0]) == float(s.ke[r])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_vjp_matches_oracle(prec):
+    import torch
+    cfg = md_inputs.replica_batch(nrep=3, nmin=900, nmax=2500, seed=13)
+    say(f"case: vjp {prec}")
+    s = _system(cfg, mode="full", prec=prec)
+    s.setup()
+    rng = np.random.default_rng(0)
+    G = rng.normal(size=(cfg.n, 3))
+    gE = rng.normal(size=cfg.nrep)
+    ids = s.id.cpu().numpy()
+    d = s.dev
+    Gs = G[ids]
+    gfx, gfy, gfz = (torch.tensor(Gs[:, k].copy(), device=d) for k in range(3))
+    gx = torch.zeros(3 * cfg.n, dtype=torch.float64, device=d)
+    geps = torch.zeros(4, dtype=torch.float64, device=d)
+    gsig = torch.zeros(4, dtype=torch.float64, device=d)
+    s.vjp(gfx, gfy, gfz, torch.tensor(gE, device=d), gx, geps, gsig)
+    torch.cuda.synchronize()
+    gxs = gx.cpu().numpy().reshape(3, cfg.n).T
+    got = np.empty_like(gxs)
+    got[ids] = gxs
+    off = cfg.atom_off()
+    ge_ref = np.zeros((2, 2))
+    gs_ref = np.zeros((2, 2))
+    tol = 1e-11 if prec == "fp64" else 1e-5
+    for r in range(cfg.nrep):
+        a, b = off[r], off[r + 1]
+        gx_r, ge_r, gs_r = oracle.lj_vjp(cfg.pos[a:b], cfg.box[r], RC, G[a:b], gE[r], cfg.eps,
+                                         cfg.sig, cfg.types[a:b], 1)
+        assert _err(got[a:b], gx_r) < tol
+        ge_ref += ge_r
+        gs_ref += gs_r
+    np.testing.assert_allclose(geps.cpu().numpy().reshape(2, 2), ge_ref, rtol=tol * 10)
+    np.testing.assert_allclose(gsig.cpu().numpy().reshape(2, 2), gs_ref, rtol=tol * 10)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_full_size_sampled_forces(prec):
+    # the 1,048,576-atom workload, in the configuration the benchmark times,
+    # jittered so forces are non-zero; 48 sampled atoms by O(N) oracle loops
+    cfg = md_inputs.lj_fluid(64, temperature=1.0, seed=2, jitter_amp=0.1)
+    say(f"case: 1M sampled {prec}")
+    s = _system(cfg, mode="full", prec=prec)
+    s.setup()
+    s.ensure_list()
+    f = s.forces_np()
+    planes = tuple(np.ascontiguousarray(cfg.pos[:, k]) for k in range(3))
+    rng = np.random.default_rng(1)
+    sample = rng.choice(cfg.n, 48, replace=False)
+    ref = np.array([oracle.lj_force_one(i, None, cfg.box[0], RC, planes=planes)[0]
+                    for i in sample])
+    err = _err(f[sample], ref)
+    say(f"  sampled e_F = {err:.3e}")
+    assert err < (1e-12 if prec == "fp64" else 1e-5)
+    # the list at t=0 holds every pair within rc + skin: FCC-perturbed counts
+    cnt = s.count.cpu().numpy()
+    assert cnt.min() > 40 and cnt.max() < s.max_nbr
