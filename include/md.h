@@ -102,6 +102,11 @@ typedef struct md_atoms {
     int32_t *id;              /* original global index, unique in [0, N)          */
     int32_t *img;             /* [3N] periodic image counters, planes x | y | z   */
     int32_t *where;           /* optional [N]: where[id] = current index          */
+    double  *pos4;            /* optional [4N] packed (x, y, z, 0) per atom: when
+                                 set, md_cell_sort and md_vv_step keep it equal to
+                                 the x, y, z planes and the pair kernels gather
+                                 neighbour positions from it (one 32-byte load
+                                 instead of three 8-byte loads from three planes) */
 } md_atoms;
 
 /* Verlet list in ELL layout, column-major so that entry k of consecutive
@@ -129,6 +134,17 @@ typedef struct md_lj {
 
 int         md_abi_version(void);
 const char *md_strerror(int code);
+
+/* Process-wide tuning knobs, read on the host at launch time.  They change
+ * speed only, never results beyond summation order (FP64 paths stay
+ * bitwise deterministic for a fixed setting).  md_tune_set returns
+ * MD_EINVAL for an unknown knob or value. */
+#define MD_TUNE_PAIR_BATCH 0   /* list entries whose neighbour positions are
+                                  gathered together in the force and VJP loops:
+                                  1, 2, 4 or 8 (default 4)                      */
+#define MD_TUNE_NKNOBS     1
+int md_tune_set(int32_t knob, int32_t value);
+int md_tune_get(int32_t knob);
 
 /* Host-only planning (no GPU work).  Cells per dimension n_d = floor(L_d /
  * (rc + skin)) so that the cell edge is at least rc + skin (Sec. 2.1.2).

@@ -33,9 +33,10 @@ MD_IDX_BITS = 26
 MD_IDX_MASK = 0x03FFFFFF
 MD_MAX_ATOMS = 0x03FFFFFF
 MD_MAX_TYPES = 8
+MD_TUNE_PAIR_BATCH = 0
 
 EXPORTS = (
-    "md_abi_version", "md_strerror", "md_plan_sizes", "md_plan_fill",
+    "md_abi_version", "md_strerror", "md_tune_set", "md_tune_get", "md_plan_sizes", "md_plan_fill",
     "md_workspace_bytes", "md_cell_sort", "md_verlet_build", "md_lj_forces",
     "md_vv_step", "md_lj_forces_vjp",
 )
@@ -53,7 +54,7 @@ class MdBatch(ctypes.Structure):
 
 class MdAtoms(ctypes.Structure):
     _fields_ = [(n, _vp) for n in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz",
-                                   "xb", "yb", "zb", "type", "id", "img", "where")]
+                                   "xb", "yb", "zb", "type", "id", "img", "where", "pos4")]
 
 
 class MdNlist(ctypes.Structure):
@@ -91,6 +92,10 @@ def load():
     lib.md_abi_version.argtypes = []
     lib.md_strerror.restype = ctypes.c_char_p
     lib.md_strerror.argtypes = [ctypes.c_int]
+    lib.md_tune_set.restype = ctypes.c_int
+    lib.md_tune_set.argtypes = [_i32, _i32]
+    lib.md_tune_get.restype = ctypes.c_int
+    lib.md_tune_get.argtypes = [_i32]
     lib.md_plan_sizes.restype = ctypes.c_int
     lib.md_plan_sizes.argtypes = [_i32, _vp, _vp, _dbl, _dbl, P(_i32), P(_i32), P(_i32)]
     lib.md_plan_fill.restype = ctypes.c_int

@@ -32,6 +32,7 @@ struct ForceArgs {
     const int32_t *atom_off, *unit_rep, *unit_off;
     const double *box;
     const double *x, *y, *z;
+    const double *pos4;  // optional packed gather source
     const int32_t *type;
     const int32_t *count;
     const uint32_t *idx;
@@ -62,7 +63,80 @@ __device__ __forceinline__ PairConst pair_const(double eps, double sig, double r
     return p;
 }
 
-template <int PREC, bool HALF, bool TYPED>
+// Per-atom accumulators.  FP64 path: ed, wd; mixed path: ef, wf (single).
+struct Acc {
+    double fx, fy, fz, ed, wd;
+    float ef, wf;
+};
+
+// Neighbour position j: from the packed copy (one 32-byte load) or from the
+// three SoA planes.
+template <bool P4>
+__device__ __forceinline__ void load_pos(const ForceArgs &a, int j, double &px, double &py,
+                                         double &pz)
+{
+    if (P4) {
+        const double4 p = reinterpret_cast<const double4 *>(a.pos4)[j];
+        px = p.x;
+        py = p.y;
+        pz = p.z;
+    } else {
+        px = a.x[j];
+        py = a.y[j];
+        pz = a.z[j];
+    }
+}
+
+// One list entry: displacement with the entry's periodic image, cutoff test
+// (always in double), pair force / energy / virial.
+template <int PREC, bool HALF>
+__device__ __forceinline__ void pair(const ForceArgs &a, const PairConst &pc, uint32_t ent,
+                                     double dx, double dy, double dz, double Lx, double Ly,
+                                     double Lz, double rc2, Acc &c)
+{
+    const uint32_t code = ent >> MD_IDX_BITS;
+    if (code != 0u) {
+        dx += image_shift(code & 3u) * Lx;
+        dy += image_shift((code >> 2) & 3u) * Ly;
+        dz += image_shift((code >> 4) & 3u) * Lz;
+    }
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < rc2) {
+        double fr;
+        if (PREC == MD_FP64) {
+            const double inv = rcp_f64(r2);
+            const double s2 = pc.s2 * inv;
+            const double s6 = s2 * s2 * s2;
+            fr = pc.e24 * s6 * (2.0 * s6 - 1.0) * inv;
+            c.ed += pc.e4 * s6 * (s6 - 1.0) - pc.ush;
+            c.wd += fr * r2;
+        } else {
+            const float r2f = static_cast<float>(r2);
+            const float inv = __builtin_amdgcn_rcpf(r2f);
+            const float s2 = static_cast<float>(pc.s2) * inv;
+            const float s6 = s2 * s2 * s2;
+            const float frf = static_cast<float>(pc.e24) * s6 * (2.0f * s6 - 1.0f) * inv;
+            fr = static_cast<double>(frf);
+            c.ef += static_cast<float>(pc.e4) * s6 * (s6 - 1.0f) - static_cast<float>(pc.ush);
+            c.wf += frf * r2f;
+        }
+        c.fx = fma(fr, dx, c.fx);
+        c.fy = fma(fr, dy, c.fy);
+        c.fz = fma(fr, dz, c.fz);
+        if (HALF) {
+            const int j = static_cast<int>(ent & MD_IDX_MASK);
+            atomicAdd(a.fx + j, -fr * dx);
+            atomicAdd(a.fy + j, -fr * dy);
+            atomicAdd(a.fz + j, -fr * dz);
+        }
+    }
+}
+
+// One thread per atom.  The list column is consumed U entries at a time:
+// U coalesced (non-temporal: the list is streamed once per call) index
+// loads, then all U neighbour gathers, then the U pair evaluations -- so
+// each wave keeps U gathers in flight instead of one.
+template <int PREC, bool HALF, bool TYPED, int U, bool P4>
 __global__ __launch_bounds__(kUnit) void k_lj(ForceArgs a)
 {
     __shared__ PairConst tab[MD_MAX_TYPES * MD_MAX_TYPES];
@@ -89,71 +163,58 @@ __global__ __launch_bounds__(kUnit) void k_lj(ForceArgs a)
         const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
         const int ti = TYPED ? a.type[i] : 0;
         const int n = min(a.count[i], a.max_nbr);
-        double fx = 0.0, fy = 0.0, fz = 0.0;
-        float ef = 0.0f, wf = 0.0f;    // mixed-precision per-atom sums
-        double ed = 0.0, wd = 0.0;     // double-precision per-atom sums
+        Acc c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
         const uint32_t *col = a.idx + i;
-        for (int k = 0; k < n; ++k) {
-            const uint32_t ent = col[size_t(k) * a.ld];
-            const int j = static_cast<int>(ent & MD_IDX_MASK);
-            double dx = xi - a.x[j], dy = yi - a.y[j], dz = zi - a.z[j];
-            const uint32_t code = ent >> MD_IDX_BITS;
-            if (code != 0u) {
-                dx += image_shift(code & 3u) * Lx;
-                dy += image_shift((code >> 2) & 3u) * Ly;
-                dz += image_shift((code >> 4) & 3u) * Lz;
+        int k = 0;
+        for (; k + U <= n; k += U) {
+            uint32_t ent[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+                ent[q] = __builtin_nontemporal_load(col + size_t(k + q) * a.ld);
+            double px[U], py[U], pz[U];
+            int tj[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int j = static_cast<int>(ent[q] & MD_IDX_MASK);
+                load_pos<P4>(a, j, px[q], py[q], pz[q]);
+                tj[q] = TYPED ? a.type[j] : 0;
             }
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 < rc2) {
-                const PairConst pc = TYPED ? tab[ti * a.ntypes + a.type[j]] : pc0;
-                double fr;
-                if (PREC == MD_FP64) {
-                    const double inv = rcp_f64(r2);
-                    const double s2 = pc.s2 * inv;
-                    const double s6 = s2 * s2 * s2;
-                    fr = pc.e24 * s6 * (2.0 * s6 - 1.0) * inv;
-                    ed += pc.e4 * s6 * (s6 - 1.0) - pc.ush;
-                    wd += fr * r2;
-                } else {
-                    const float r2f = static_cast<float>(r2);
-                    const float inv = __builtin_amdgcn_rcpf(r2f);
-                    const float s2 = static_cast<float>(pc.s2) * inv;
-                    const float s6 = s2 * s2 * s2;
-                    const float frf = static_cast<float>(pc.e24) * s6 * (2.0f * s6 - 1.0f) * inv;
-                    fr = static_cast<double>(frf);
-                    ef += static_cast<float>(pc.e4) * s6 * (s6 - 1.0f) - static_cast<float>(pc.ush);
-                    wf += frf * r2f;
-                }
-                fx = fma(fr, dx, fx);
-                fy = fma(fr, dy, fy);
-                fz = fma(fr, dz, fz);
-                if (HALF) {
-                    atomicAdd(a.fx + j, -fr * dx);
-                    atomicAdd(a.fy + j, -fr * dy);
-                    atomicAdd(a.fz + j, -fr * dz);
-                }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const PairConst &pc = TYPED ? tab[ti * a.ntypes + tj[q]] : pc0;
+                pair<PREC, HALF>(a, pc, ent[q], xi - px[q], yi - py[q], zi - pz[q], Lx, Ly, Lz,
+                                 rc2, c);
             }
         }
+        for (; k < n; ++k) {
+            const uint32_t ent = __builtin_nontemporal_load(col + size_t(k) * a.ld);
+            const int j = static_cast<int>(ent & MD_IDX_MASK);
+            double px, py, pz;
+            load_pos<P4>(a, j, px, py, pz);
+            const PairConst &pc = TYPED ? tab[ti * a.ntypes + a.type[j]] : pc0;
+            pair<PREC, HALF>(a, pc, ent, xi - px, yi - py, zi - pz, Lx, Ly, Lz, rc2, c);
+        }
+        double ed = c.ed, wd = c.wd;
         if (PREC != MD_FP64) {
-            ed = static_cast<double>(ef);
-            wd = static_cast<double>(wf);
+            ed = static_cast<double>(c.ef);
+            wd = static_cast<double>(c.wf);
         }
         e_acc = HALF ? ed : 0.5 * ed;
         w_acc = HALF ? wd : 0.5 * wd;
         if (HALF) {
-            atomicAdd(a.fx + i, fx);
-            atomicAdd(a.fy + i, fy);
-            atomicAdd(a.fz + i, fz);
+            atomicAdd(a.fx + i, c.fx);
+            atomicAdd(a.fy + i, c.fy);
+            atomicAdd(a.fz + i, c.fz);
         } else if (a.accumulate) {
-            a.fx[i] += fx;
-            a.fy[i] += fy;
-            a.fz[i] += fz;
+            a.fx[i] += c.fx;
+            a.fy[i] += c.fy;
+            a.fz[i] += c.fz;
         } else {
-            a.fx[i] = fx;
-            a.fy[i] = fy;
-            a.fz[i] = fz;
+            a.fx[i] = c.fx;
+            a.fy[i] = c.fy;
+            a.fz[i] = c.fz;
         }
-        if (a.status && !isfinite(fx + fy + fz + ed)) atomicOr(a.status, MD_F_NONFINITE);
+        if (a.status && !isfinite(c.fx + c.fy + c.fz + ed)) atomicOr(a.status, MD_F_NONFINITE);
     }
     const double es = block_sum(e_acc, red);
     const double ws = block_sum(w_acc, red);
@@ -197,6 +258,45 @@ __global__ __launch_bounds__(kUnit) void k_finalize_sum2(const int32_t *unit_off
     }
 }
 
+// Template dispatch: precision x list mode x typed x batch x gather source.
+template <int PREC, bool HALF, bool TYPED, int U>
+void launch_lj_u(const ForceArgs &a, int n_units, bool p4, hipStream_t s)
+{
+    if (p4) hipLaunchKernelGGL((k_lj<PREC, HALF, TYPED, U, true>), dim3(n_units), dim3(kUnit), 0, s, a);
+    else hipLaunchKernelGGL((k_lj<PREC, HALF, TYPED, U, false>), dim3(n_units), dim3(kUnit), 0, s, a);
+}
+
+template <int PREC, bool HALF, bool TYPED>
+void launch_lj_t(const ForceArgs &a, int n_units, int batch, bool p4, hipStream_t s)
+{
+    switch (batch) {
+    case 1: launch_lj_u<PREC, HALF, TYPED, 1>(a, n_units, p4, s); break;
+    case 2: launch_lj_u<PREC, HALF, TYPED, 2>(a, n_units, p4, s); break;
+    case 8: launch_lj_u<PREC, HALF, TYPED, 8>(a, n_units, p4, s); break;
+    default: launch_lj_u<PREC, HALF, TYPED, 4>(a, n_units, p4, s); break;
+    }
+}
+
+template <int PREC>
+void launch_lj_p(const ForceArgs &a, int n_units, bool half, bool typed, int batch, bool p4,
+                 hipStream_t s)
+{
+    if (half) {
+        if (typed) launch_lj_t<PREC, true, true>(a, n_units, batch, p4, s);
+        else launch_lj_t<PREC, true, false>(a, n_units, batch, p4, s);
+    } else {
+        if (typed) launch_lj_t<PREC, false, true>(a, n_units, batch, p4, s);
+        else launch_lj_t<PREC, false, false>(a, n_units, batch, p4, s);
+    }
+}
+
+void launch_lj(const ForceArgs &a, int n_units, int prec, bool half, bool typed, int batch,
+               bool p4, hipStream_t s)
+{
+    if (prec == MD_FP64) launch_lj_p<MD_FP64>(a, n_units, half, typed, batch, p4, s);
+    else launch_lj_p<MD_FP32_MIXED>(a, n_units, half, typed, batch, p4, s);
+}
+
 void launch_finalize_sum2(int R, const int32_t *unit_off, const double *partial, int k0,
                           double *out0, double *out1, hipStream_t s)
 {
@@ -225,24 +325,16 @@ extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_n
     const WsLayout l = ws_layout(b);
     if (ws_bytes < l.total) return MD_ENOWS;
     ForceArgs a{b->atom_off, b->unit_rep, b->unit_off, b->box, atoms->x, atoms->y, atoms->z,
-                atoms->type, nl->count, nl->idx, nl->ld, nl->max_nbr, p->eps, p->sig,
-                p->ntypes, p->shift, p->rc, atoms->fx, atoms->fy, atoms->fz, accumulate,
+                atoms->pos4, atoms->type, nl->count, nl->idx, nl->ld, nl->max_nbr, p->eps,
+                p->sig, p->ntypes, p->shift, p->rc, atoms->fx, atoms->fy, atoms->fz, accumulate,
                 ws_at<double>(ws, l.partial), status};
     hipStream_t s = as_stream(stream);
-    const dim3 grid(b->n_units), block(kUnit);
-    const bool half = nl->mode == MD_HALF, typed = p->ntypes > 1;
+    const bool half = nl->mode == MD_HALF;
     if (half && !accumulate)
-        hipLaunchKernelGGL(k_zero3, dim3((b->N + kUnit - 1) / kUnit), block, 0, s, b->N,
+        hipLaunchKernelGGL(k_zero3, dim3((b->N + kUnit - 1) / kUnit), dim3(kUnit), 0, s, b->N,
                            atoms->fx, atoms->fy, atoms->fz);
-#define MD_LJ_LAUNCH(P, H, T) hipLaunchKernelGGL((k_lj<P, H, T>), grid, block, 0, s, a)
-    if (prec == MD_FP64) {
-        if (half) { if (typed) MD_LJ_LAUNCH(MD_FP64, true, true); else MD_LJ_LAUNCH(MD_FP64, true, false); }
-        else      { if (typed) MD_LJ_LAUNCH(MD_FP64, false, true); else MD_LJ_LAUNCH(MD_FP64, false, false); }
-    } else {
-        if (half) { if (typed) MD_LJ_LAUNCH(MD_FP32_MIXED, true, true); else MD_LJ_LAUNCH(MD_FP32_MIXED, true, false); }
-        else      { if (typed) MD_LJ_LAUNCH(MD_FP32_MIXED, false, true); else MD_LJ_LAUNCH(MD_FP32_MIXED, false, false); }
-    }
-#undef MD_LJ_LAUNCH
+    launch_lj(a, b->n_units, prec, half, p->ntypes > 1, md_tune_get(MD_TUNE_PAIR_BATCH),
+              atoms->pos4 != nullptr, s);
     if (energy || virial)
         launch_finalize_sum2(b->R, b->unit_off, ws_at<const double>(ws, l.partial), 0, energy,
                              virial, s);

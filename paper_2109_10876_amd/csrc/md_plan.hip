@@ -11,6 +11,23 @@ extern "C" {
 
 int md_abi_version(void) { return MD_ABI_VERSION; }
 
+static int32_t g_tune[MD_TUNE_NKNOBS] = {4};
+
+int md_tune_set(int32_t knob, int32_t value)
+{
+    if (knob == MD_TUNE_PAIR_BATCH) {
+        if (value != 1 && value != 2 && value != 4 && value != 8) return MD_EINVAL;
+        g_tune[knob] = value;
+        return MD_OK;
+    }
+    return MD_EINVAL;
+}
+
+int md_tune_get(int32_t knob)
+{
+    return (knob >= 0 && knob < MD_TUNE_NKNOBS) ? g_tune[knob] : MD_EINVAL;
+}
+
 const char *md_strerror(int code)
 {
     switch (code) {

@@ -13,7 +13,7 @@
 //   3 keys     key[cell_start[c] + slot] = id   (cell members, any order)
 //   4 gather   rank inside the cell by id (deterministic order), gather the
 //              atom's wrapped data into scratch at its final index
-//   5 copy     scratch -> atoms, x_build := x
+//   5 copy     scratch -> atoms, x_build := x (and the packed copy)
 #include "md_common.hpp"
 
 namespace md {
@@ -160,6 +160,7 @@ __global__ __launch_bounds__(kUnit) void k_copy_back(BatchArgs a, md_atoms s, md
     const double x = s.x[i], y = s.y[i], z = s.z[i];
     d.x[i] = x; d.y[i] = y; d.z[i] = z;
     d.xb[i] = x; d.yb[i] = y; d.zb[i] = z;
+    if (d.pos4) reinterpret_cast<double4 *>(d.pos4)[i] = make_double4(x, y, z, 0.0);
     d.vx[i] = s.vx[i]; d.vy[i] = s.vy[i]; d.vz[i] = s.vz[i];
     d.type[i] = s.type[i];
     d.id[i] = s.id[i];

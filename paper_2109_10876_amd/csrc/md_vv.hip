@@ -19,6 +19,7 @@ namespace {
 struct VVArgs {
     const int32_t *atom_off, *unit_rep, *unit_off;
     double *x, *y, *z, *vx, *vy, *vz;
+    double *pos4;
     const double *fx, *fy, *fz, *xb, *yb, *zb;
     const int32_t *type;
     const double *inv_mass;
@@ -56,6 +57,7 @@ __global__ __launch_bounds__(kUnit) void k_vv(VVArgs a)
             a.x[i] = x;
             a.y[i] = y;
             a.z[i] = z;
+            if (a.pos4) reinterpret_cast<double4 *>(a.pos4)[i] = make_double4(x, y, z, 0.0);
             const double ex = x - a.xb[i], ey = y - a.yb[i], ez = z - a.zb[i];
             d2 = ex * ex + ey * ey + ez * ez;
         }
@@ -116,7 +118,7 @@ extern "C" int md_vv_step(const md_batch *b, md_atoms *atoms, int32_t phase, dou
     if (ws_bytes < l.total) return MD_ENOWS;
     double *partial = ws_at<double>(ws, l.partial);
     VVArgs a{b->atom_off, b->unit_rep, b->unit_off, atoms->x, atoms->y, atoms->z, atoms->vx,
-             atoms->vy, atoms->vz, atoms->fx, atoms->fy, atoms->fz, atoms->xb, atoms->yb,
+             atoms->vy, atoms->vz, atoms->pos4, atoms->fx, atoms->fy, atoms->fz, atoms->xb, atoms->yb,
              atoms->zb, atoms->type, inv_mass, ntypes, 0.5 * dt, dt, partial};
     hipStream_t s = as_stream(stream);
     const dim3 grid(b->n_units), block(kUnit);

@@ -38,7 +38,7 @@ class MDSystem:
 
     def __init__(self, natoms, box, pos, vel, types=None, eps=1.0, sig=1.0, mass=None,
                  rc=2.5, skin=0.3, dt=0.005, shift=1, mode="full", prec="fp64",
-                 max_nbr=None, device="cuda"):
+                 max_nbr=None, pos4=True, device="cuda"):
         self.lib = abi.load()
         self.dev = torch.device(device)
         natoms = np.asarray(natoms, dtype=np.int32).ravel()
@@ -92,6 +92,8 @@ class MDSystem:
         self.id = torch.arange(self.N, dtype=torch.int32, device=d)
         self.img = torch.zeros(3 * self.N, dtype=torch.int32, device=d)
         self.where = torch.arange(self.N, dtype=torch.int32, device=d)
+        # packed (x, y, z, 0) gather copy, maintained by the re-sort and the integrator
+        self.pos4 = torch.zeros(4 * self.N, dtype=torch.float64, device=d) if pos4 else None
         self.atoms = self._atoms_struct(self)
         # re-sort scratch planes
         self.s_x, self.s_y, self.s_z, self.s_vx, self.s_vy, self.s_vz = (z64() for _ in range(6))
@@ -102,7 +104,7 @@ class MDSystem:
                                    self.s_vx.data_ptr(), self.s_vy.data_ptr(),
                                    self.s_vz.data_ptr(), None, None, None, None, None, None,
                                    self.s_type.data_ptr(), self.s_id.data_ptr(),
-                                   self.s_img.data_ptr(), None)
+                                   self.s_img.data_ptr(), None, None)
 
         # ---- parameters, list, workspace, outputs
         self.eps_t, self.sig_t = f64(eps.ravel()), f64(sig.ravel())
@@ -133,7 +135,8 @@ class MDSystem:
                            s.vy.data_ptr(), s.vz.data_ptr(), s.fx.data_ptr(), s.fy.data_ptr(),
                            s.fz.data_ptr(), s.xb.data_ptr(), s.yb.data_ptr(), s.zb.data_ptr(),
                            s.type.data_ptr(), s.id.data_ptr(), s.img.data_ptr(),
-                           s.where.data_ptr())
+                           s.where.data_ptr(),
+                           s.pos4.data_ptr() if s.pos4 is not None else None)
 
     def _alloc_list(self, max_nbr):
         self.max_nbr = int(max_nbr)

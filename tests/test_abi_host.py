@@ -40,6 +40,17 @@ def test_header_constants_match_binding():
         assert int(m.group(1), 0) == getattr(abi, name), name
 
 
+def test_tuning_knobs():
+    lib = abi.load()
+    assert lib.md_tune_get(abi.MD_TUNE_PAIR_BATCH) == 4
+    for v in (1, 2, 8, 4):
+        assert lib.md_tune_set(abi.MD_TUNE_PAIR_BATCH, v) == abi.MD_OK
+        assert lib.md_tune_get(abi.MD_TUNE_PAIR_BATCH) == v
+    assert lib.md_tune_set(abi.MD_TUNE_PAIR_BATCH, 3) == abi.MD_EINVAL
+    assert lib.md_tune_set(99, 1) == abi.MD_EINVAL
+    assert lib.md_tune_get(99) == abi.MD_EINVAL
+
+
 def _plan(natoms, box, rc=2.5, skin=0.3):
     lib = abi.load()
     natoms = np.asarray(natoms, np.int32)
@@ -106,7 +117,7 @@ def test_calls_reject_bad_arguments_without_a_gpu():
     assert lib.md_workspace_bytes(P(ok)) > 0
     nl = abi.MdNlist(7, 64, 1024, 0, 8, 8)
     assert lib.md_verlet_build(P(ok), P(atoms), 8, 2.5, 0.3, P(nl), None, None, None, None) == abi.MD_EINVAL
-    full = abi.MdAtoms(*([8] * 16))
+    full = abi.MdAtoms(*([8] * 17))
     nl = abi.MdNlist(abi.MD_HALF, 64, 1000, 0, 8, 8)   # ld not a multiple of 64
     lj1 = abi.MdLj(1, 1, 2.5, 8, 8)
     assert lib.md_lj_forces(P(ok), P(full), P(nl), P(lj1), 0, 0, None, None, 8, 1 << 30, None, None) == abi.MD_EINVAL

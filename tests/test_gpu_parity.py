@@ -85,6 +85,31 @@ def test_full_list_forces_are_deterministic_and_match_half(c1_snapshot):
     assert np.abs(h.forces_np() - a.forces_np()).max() < 1e-10
 
 
+@pytest.mark.parametrize("mode", ["full", "half"])
+def test_pair_batch_and_gather_source_do_not_change_results(c1_snapshot, mode):
+    from paper_2109_10876_amd import _abi as abi
+    cfg = c1_snapshot
+    say(f"case: batch/gather variants {mode}")
+    lib = abi.load()
+    ref = None
+    try:
+        for p4 in (True, False):
+            s = _system(cfg, mode=mode, pos4=p4)
+            s.setup()
+            for batch in (1, 2, 4, 8):
+                assert lib.md_tune_set(abi.MD_TUNE_PAIR_BATCH, batch) == 0
+                s.forces()
+                f = s.forces_np()
+                if ref is None:
+                    ref = f
+                elif mode == "full":
+                    assert np.array_equal(f, ref)       # same summation order
+                else:
+                    assert np.abs(f - ref).max() < 1e-10
+    finally:
+        lib.md_tune_set(abi.MD_TUNE_PAIR_BATCH, 4)
+
+
 def _unordered(pairs):
     p = np.sort(pairs, axis=1)
     return set(map(tuple, np.unique(p, axis=0)))
