@@ -25,6 +25,22 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
 
+# HBM bytes per md_lj_forces launch on this workload from rocprofv3 FETCH_SIZE
+# and WRITE_SIZE (calibrated against a plain copy), valid only for the kernel
+# source they were taken on (profiles/lj_forces_lj1m_hbm_counters.md).
+COUNTED_TRAFFIC = {"src_sha256_16": "fc65f92f8a9bfda0",
+                   "bytes_per_launch": {"mixed": 208596.2 * 1024 * 2.0 + 24721.2 * 1024,
+                                        "fp64": 208608.7 * 1024 * 2.0 + 24723.3 * 1024}}
+
+
+def force_kernel_src_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("md_forces.hip", "md_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2109_10876_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -134,6 +150,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--mode", default="full", choices=["full", "half"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 512 MiB device-to-device copy five times (the "
+                         "calibration kernel for HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -143,6 +162,14 @@ def main():
     import torch
     import md_inputs
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")   # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 8, "launches": 5}))
+        return
     cfg = md_inputs.CONFIGS["lj1m"]()
     out = {}
     for prec in ("mixed", "fp64"):
@@ -154,6 +181,9 @@ def main():
         # write (24 B); neighbour positions are cache-resident gathers
         bytes_launch = s.N * (4.0 * mean_k + 4 + 24 + 24)
         gbs = bytes_launch / (f_ms * 1e-3) / 1e9
+        traffic = None
+        if force_kernel_src_hash() == COUNTED_TRAFFIC["src_sha256_16"]:
+            traffic = COUNTED_TRAFFIC["bytes_per_launch"][prec] / (f_ms * 1e-3) / 1e9
         out[prec] = {
             "ms_per_step": ms / args.steps,
             "atom_steps_per_s": s.N * args.steps / (ms * 1e-3),
@@ -163,8 +193,9 @@ def main():
             "force_err_rel": err,
             "forces_kernel_ms": f_ms,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                         "bytes_per_launch": bytes_launch},
+                         "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                         "bytes_per_launch": bytes_launch,
+                         "kernel": "md_lj_forces (k_lj)"},
         }
         log(f"[{prec}] {json.dumps(out[prec])}")
         del s

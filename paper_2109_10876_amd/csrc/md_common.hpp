@@ -176,6 +176,14 @@ void launch_finalize_sum2(int R, const int32_t *unit_off, const double *partial,
 
 inline hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
+// Grid of the kernels that a gate may skip: with a gate, a grid-stride grid
+// of at most 1024 workgroups (four per CU), so a skipped call is one short
+// launch; without one, a workgroup per unit.
+inline int gated_grid(int n_units, bool gated)
+{
+    return gated ? (n_units < 1024 ? n_units : 1024) : n_units;
+}
+
 inline int launch_status()
 {
     return hipGetLastError() == hipSuccess ? MD_OK : MD_EHIP;

@@ -23,17 +23,48 @@ struct BatchArgs {
     const int32_t *atom_off, *cell_off, *ncell, *unit_rep, *unit_off;
     const double *box;
     const uint32_t *gate;
+    int32_t n_units;
 };
 
 BatchArgs batch_args(const md_batch *b, const uint32_t *gate)
 {
-    return BatchArgs{b->atom_off, b->cell_off, b->ncell, b->unit_rep, b->unit_off, b->box, gate};
+    return BatchArgs{b->atom_off, b->cell_off, b->ncell, b->unit_rep, b->unit_off, b->box, gate,
+                     b->n_units};
 }
 
 __device__ __forceinline__ bool gated_off(const BatchArgs &a, int rep)
 {
     return a.gate != nullptr && a.gate[rep] == 0u;
 }
+
+// Lanes of a wave that fall into the same cell take their slots with one
+// atomic add per distinct cell (consecutive atoms are mostly cell-mates).
+// Must be reached by every lane of the wave.
+__device__ __forceinline__ int aggregated_slot(int32_t *count, int c, bool active)
+{
+    const int lane = __lane_id();
+    unsigned long long todo = __ballot(active);
+    int slot = 0;
+    while (todo) {
+        const int leader = __ffsll(static_cast<long long>(todo)) - 1;
+        const int cl = __shfl(c, leader, kWave);
+        const bool mine = active && c == cl;
+        const unsigned long long grp = __ballot(mine);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(count + cl, __popcll(grp));
+        base = __shfl(base, leader, kWave);
+        if (mine) slot = base + __popcll(grp & ((1ull << lane) - 1ull));
+        todo &= ~grp;
+    }
+    return slot;
+}
+
+// Grid-stride loop over work units; a unit whose replica's gate is 0 is
+// skipped, so a skipped rebuild costs one short launch.
+#define MD_FOR_UNITS(a, w)                                                          \
+    for (int lb_ = blockIdx.x; lb_ < (a).n_units; lb_ += gridDim.x)                \
+        if (const Unit w = unit_of(lb_, (a).unit_rep, (a).unit_off, (a).atom_off); \
+            !gated_off((a), w.rep))
 
 __global__ __launch_bounds__(kUnit) void k_bin(BatchArgs a, const double *__restrict__ x,
                                                const double *__restrict__ y,
@@ -42,32 +73,42 @@ __global__ __launch_bounds__(kUnit) void k_bin(BatchArgs a, const double *__rest
                                                int32_t *__restrict__ cell_of,
                                                int32_t *__restrict__ slot)
 {
-    const Unit w = unit_of(blockIdx.x, a.unit_rep, a.unit_off, a.atom_off);
-    if (gated_off(a, w.rep)) return;
-    const int i = w.begin + threadIdx.x;
-    if (i >= w.end) return;
-    const double *L = a.box + 3 * w.rep;
-    const int32_t *n = a.ncell + 3 * w.rep;
-    int s;
-    const int cx = cell_coord(wrap_coord(x[i], L[0], &s), L[0], n[0]);
-    const int cy = cell_coord(wrap_coord(y[i], L[1], &s), L[1], n[1]);
-    const int cz = cell_coord(wrap_coord(z[i], L[2], &s), L[2], n[2]);
-    const int c = a.cell_off[w.rep] + (cz * n[1] + cy) * n[0] + cx;
-    cell_of[i] = c;
-    slot[i] = atomicAdd(cell_count + c, 1);
+    MD_FOR_UNITS(a, w) {
+        const int i = w.begin + threadIdx.x;
+        const bool active = i < w.end;
+        int c = 0;
+        if (active) {
+            const double *L = a.box + 3 * w.rep;
+            const int32_t *n = a.ncell + 3 * w.rep;
+            int s;
+            const int cx = cell_coord(wrap_coord(x[i], L[0], &s), L[0], n[0]);
+            const int cy = cell_coord(wrap_coord(y[i], L[1], &s), L[1], n[1]);
+            const int cz = cell_coord(wrap_coord(z[i], L[2], &s), L[2], n[2]);
+            c = a.cell_off[w.rep] + (cz * n[1] + cy) * n[0] + cx;
+        }
+        const int sl = aggregated_slot(cell_count, c, active);
+        if (active) {
+            cell_of[i] = c;
+            slot[i] = sl;
+        }
+    }
 }
 
-// One workgroup per replica scans its cells in chunks of 4 * kUnit.
-__global__ __launch_bounds__(kUnit) void k_scan(BatchArgs a, int32_t *__restrict__ cell_count,
+// One workgroup of kScan threads per replica scans its cells in chunks of
+// 4 * kScan cells.
+constexpr int kScan = 1024;
+
+__global__ __launch_bounds__(kScan) void k_scan(BatchArgs a, int32_t *__restrict__ cell_count,
                                                 int32_t *__restrict__ cell_start)
 {
     const int r = blockIdx.x;
     if (gated_off(a, r)) return;
-    __shared__ int32_t wsum[kWavesPerUnit];
+    constexpr int kW = kScan / kWave;
+    __shared__ int32_t wsum[kW];
     const int c0 = a.cell_off[r], c1 = a.cell_off[r + 1];
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
     int32_t carry = a.atom_off[r];
-    for (int base = c0; base < c1; base += 4 * kUnit) {
+    for (int base = c0; base < c1; base += 4 * kScan) {
         const int c = base + 4 * threadIdx.x;
         int32_t v[4];
         int32_t t = 0;
@@ -76,19 +117,19 @@ __global__ __launch_bounds__(kUnit) void k_scan(BatchArgs a, int32_t *__restrict
             v[k] = (c + k < c1) ? cell_count[c + k] : 0;
             t += v[k];
         }
-        // inclusive wave scan of t
-        int32_t inc = t;
+        int32_t inc = t;   // inclusive wave scan of the per-thread totals
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
-            int32_t up = __shfl_up(inc, o, kWave);
+            const int32_t up = __shfl_up(inc, o, kWave);
             if (lane >= o) inc += up;
         }
         if (lane == kWave - 1) wsum[wid] = inc;
         __syncthreads();
         int32_t before = 0, total = 0;
-        for (int k = 0; k < kWavesPerUnit; ++k) {
-            if (k < wid) before += wsum[k];
-            total += wsum[k];
+        for (int k = 0; k < kW; ++k) {
+            const int32_t ws = wsum[k];
+            before += k < wid ? ws : 0;
+            total += ws;
         }
         int32_t run = carry + before + inc - t;
 #pragma unroll
@@ -111,11 +152,10 @@ __global__ __launch_bounds__(kUnit) void k_keys(BatchArgs a, const int32_t *__re
                                                 const int32_t *__restrict__ cell_start,
                                                 int32_t *__restrict__ key)
 {
-    const Unit w = unit_of(blockIdx.x, a.unit_rep, a.unit_off, a.atom_off);
-    if (gated_off(a, w.rep)) return;
-    const int i = w.begin + threadIdx.x;
-    if (i >= w.end) return;
-    key[cell_start[cell_of[i]] + slot[i]] = id[i];
+    MD_FOR_UNITS(a, w) {
+        const int i = w.begin + threadIdx.x;
+        if (i < w.end) key[cell_start[cell_of[i]] + slot[i]] = id[i];
+    }
 }
 
 __global__ __launch_bounds__(kUnit) void k_gather(BatchArgs a, md_atoms in, md_atoms out,
@@ -124,49 +164,50 @@ __global__ __launch_bounds__(kUnit) void k_gather(BatchArgs a, md_atoms in, md_a
                                                   const int32_t *__restrict__ cell_start,
                                                   const int32_t *__restrict__ key)
 {
-    const Unit w = unit_of(blockIdx.x, a.unit_rep, a.unit_off, a.atom_off);
-    if (gated_off(a, w.rep)) return;
-    const int i = w.begin + threadIdx.x;
-    if (i >= w.end) return;
-    const int c = cell_of[i];
-    const int s = cell_start[c], e = cell_start[c + 1];
-    const int32_t me = in.id[i];
-    int rank = 0;
-    for (int m = s; m < e; ++m) rank += key[m] < me ? 1 : 0;
-    const int dst = s + rank;
-    const double *L = a.box + 3 * w.rep;
-    int sx, sy, sz;
-    out.x[dst] = wrap_coord(in.x[i], L[0], &sx);
-    out.y[dst] = wrap_coord(in.y[i], L[1], &sy);
-    out.z[dst] = wrap_coord(in.z[i], L[2], &sz);
-    out.vx[dst] = in.vx[i];
-    out.vy[dst] = in.vy[i];
-    out.vz[dst] = in.vz[i];
-    out.type[dst] = in.type[i];
-    out.id[dst] = me;
-    out.img[dst] = in.img[i] + sx;
-    out.img[N + dst] = in.img[N + i] + sy;
-    out.img[2 * N + dst] = in.img[2 * N + i] + sz;
-    if (in.where) in.where[me] = dst;
+    MD_FOR_UNITS(a, w) {
+        const int i = w.begin + threadIdx.x;
+        if (i >= w.end) continue;
+        const int c = cell_of[i];
+        const int s = cell_start[c], e = cell_start[c + 1];
+        const int32_t me = in.id[i];
+        int rank = 0;
+#pragma unroll 4
+        for (int m = s; m < e; ++m) rank += key[m] < me ? 1 : 0;
+        const int dst = s + rank;
+        const double *L = a.box + 3 * w.rep;
+        int sx, sy, sz;
+        out.x[dst] = wrap_coord(in.x[i], L[0], &sx);
+        out.y[dst] = wrap_coord(in.y[i], L[1], &sy);
+        out.z[dst] = wrap_coord(in.z[i], L[2], &sz);
+        out.vx[dst] = in.vx[i];
+        out.vy[dst] = in.vy[i];
+        out.vz[dst] = in.vz[i];
+        out.type[dst] = in.type[i];
+        out.id[dst] = me;
+        out.img[dst] = in.img[i] + sx;
+        out.img[N + dst] = in.img[N + i] + sy;
+        out.img[2 * N + dst] = in.img[2 * N + i] + sz;
+        if (in.where) in.where[me] = dst;
+    }
 }
 
 __global__ __launch_bounds__(kUnit) void k_copy_back(BatchArgs a, md_atoms s, md_atoms d,
                                                      int32_t N)
 {
-    const Unit w = unit_of(blockIdx.x, a.unit_rep, a.unit_off, a.atom_off);
-    if (gated_off(a, w.rep)) return;
-    const int i = w.begin + threadIdx.x;
-    if (i >= w.end) return;
-    const double x = s.x[i], y = s.y[i], z = s.z[i];
-    d.x[i] = x; d.y[i] = y; d.z[i] = z;
-    d.xb[i] = x; d.yb[i] = y; d.zb[i] = z;
-    if (d.pos4) reinterpret_cast<double4 *>(d.pos4)[i] = make_double4(x, y, z, 0.0);
-    d.vx[i] = s.vx[i]; d.vy[i] = s.vy[i]; d.vz[i] = s.vz[i];
-    d.type[i] = s.type[i];
-    d.id[i] = s.id[i];
-    d.img[i] = s.img[i];
-    d.img[N + i] = s.img[N + i];
-    d.img[2 * N + i] = s.img[2 * N + i];
+    MD_FOR_UNITS(a, w) {
+        const int i = w.begin + threadIdx.x;
+        if (i >= w.end) continue;
+        const double x = s.x[i], y = s.y[i], z = s.z[i];
+        d.x[i] = x; d.y[i] = y; d.z[i] = z;
+        d.xb[i] = x; d.yb[i] = y; d.zb[i] = z;
+        if (d.pos4) reinterpret_cast<double4 *>(d.pos4)[i] = make_double4(x, y, z, 0.0);
+        d.vx[i] = s.vx[i]; d.vy[i] = s.vy[i]; d.vz[i] = s.vz[i];
+        d.type[i] = s.type[i];
+        d.id[i] = s.id[i];
+        d.img[i] = s.img[i];
+        d.img[N + i] = s.img[N + i];
+        d.img[2 * N + i] = s.img[2 * N + i];
+    }
 }
 
 bool atoms_ok(const md_atoms *a, bool need_build)
@@ -201,9 +242,9 @@ extern "C" int md_cell_sort(const md_batch *b, md_atoms *atoms, md_atoms *scratc
     int32_t *cell_of = ws_at<int32_t>(ws, l.cell_of);
     int32_t *slot = ws_at<int32_t>(ws, l.slot);
     int32_t *key = ws_at<int32_t>(ws, l.key);
-    const dim3 grid(b->n_units), block(kUnit);
+    const dim3 grid(gated_grid(b->n_units, gate != nullptr)), block(kUnit);
     hipLaunchKernelGGL(k_bin, grid, block, 0, s, a, atoms->x, atoms->y, atoms->z, cnt, cell_of, slot);
-    hipLaunchKernelGGL(k_scan, dim3(b->R), block, 0, s, a, cnt, cell_start);
+    hipLaunchKernelGGL(k_scan, dim3(b->R), dim3(kScan), 0, s, a, cnt, cell_start);
     hipLaunchKernelGGL(k_keys, grid, block, 0, s, a, atoms->id, cell_of, slot, cell_start, key);
     hipLaunchKernelGGL(k_gather, grid, block, 0, s, a, *atoms, *scratch, b->N, cell_of, cell_start, key);
     hipLaunchKernelGGL(k_copy_back, grid, block, 0, s, a, *scratch, *atoms, b->N);
