@@ -24,7 +24,7 @@ import numpy as np
 
 __all__ = [
     "Config", "fcc_lattice", "maxwell_velocities", "jitter", "lj_fluid",
-    "random_walk_chains", "lj_slab", "replica_batch", "CONFIGS",
+    "random_walk_chains", "lattice_chains", "lj_slab", "replica_batch", "CONFIGS",
 ]
 
 # Basis of the FCC conventional cubic cell, in units of the lattice constant.
@@ -155,6 +155,36 @@ def random_walk_chains(nchains, length, rho=0.85, bond=0.97, seed=3,
                   wca, 0.4, dt, temperature, steps, shift=1, bonds=bonds)
 
 
+def lattice_chains(shape, length, rho=0.85, seed=3, temperature=1.0, dt=0.005,
+                   steps=1000):
+    """Linear chains laid along a serpentine (boustrophedon) path through a
+    simple-cubic lattice of shape (mx, my, mz) with spacing (1/rho)^(1/3):
+    consecutive path sites are lattice neighbours, so every bond has the
+    lattice spacing and no two beads overlap (no warm-up needed).  The path
+    is cut into chains of ``length`` beads (mx my mz must be a multiple)."""
+    mx, my, mz = shape
+    n = mx * my * mz
+    assert n % length == 0
+    a = (1.0 / rho) ** (1.0 / 3.0)
+    sites = []
+    for z in range(mz):
+        ys = range(my) if z % 2 == 0 else range(my - 1, -1, -1)
+        for k, y in enumerate(ys):
+            row = (z * my + k) % 2 == 0
+            xs = range(mx) if row else range(mx - 1, -1, -1)
+            sites.extend((x, y, z) for x in xs)
+    pos = (np.array(sites, dtype=np.float64) + 0.5) * a
+    vel = maxwell_velocities(n, temperature, 1.0, seed=seed)
+    nch = n // length
+    first = (np.arange(nch)[:, None] * length + np.arange(length - 1)[None, :]).ravel()
+    bonds = np.stack([first, first + 1], axis=1).astype(np.int32)
+    one = np.ones((1, 1))
+    return Config(f"kg_lattice_{nch}x{length}", pos, vel,
+                  np.array([[mx * a, my * a, mz * a]]), np.array([n], dtype=np.int64),
+                  np.zeros(n, np.int32), 1, one.copy(), one.copy(), np.ones(1),
+                  2.0 ** (1.0 / 6.0), 0.4, dt, temperature, steps, shift=1, bonds=bonds)
+
+
 def lj_slab(m=50, rho=0.8, temperature=0.85, seed=4, dt=0.005, steps=1000):
     """FCC slab of m^3 unit cells at density rho, centred in z in a box whose
     z edge is three times the slab thickness (vacuum on both sides)."""
@@ -217,7 +247,8 @@ CONFIGS = {
                                name="lj_fcc10_n4000"),
     "lj1m": lambda: lj_fluid(64, temperature=1.0, seed=2, steps=1000,
                              name="lj_fcc64_n1048576"),
-    "kg_melt": lambda: random_walk_chains(4096, 200, seed=3),
+    "kg_melt": lambda: lattice_chains((80, 80, 128), 200, seed=3),
+    "kg_melt_random_walk": lambda: random_walk_chains(4096, 200, seed=3),
     "lj_slab": lambda: lj_slab(50, seed=4),
     "replicas": lambda: replica_batch(256, seed=5),
 }

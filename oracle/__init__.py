@@ -94,6 +94,10 @@ def _load():
     lib.orc_fene_forces.restype = i64
     lib.orc_fene_forces.argtypes = [i32, _D, _D, _D, _D, i64, _I, _I, dbl, dbl,
                                     _D, _D, _D, _D, _D]
+    lib.orc_md_run_ext.restype = i64
+    lib.orc_md_run_ext.argtypes = [i32, _D, _D, _D, _D, _D, _D, _I, i32, _D, _D, _D, _D, dbl,
+                                   i32, dbl, dbl, i32, i64, _I, _I, dbl, dbl, dbl, dbl,
+                                   ctypes.c_uint64, ctypes.c_uint64, _U8, _D, _D, _D, _D, _D]
     _lib = lib
     return lib
 
@@ -358,3 +362,40 @@ def fene_forces(pos, box, bonds, K=30.0, R0=1.5):
                                  bonds.shape[0], _i(bi), _i(bj), float(K), float(R0),
                                  _d(fx), _d(fy), _d(fz), ctypes.byref(e), ctypes.byref(w))
     return np.stack([fx, fy, fz], axis=1), e.value, w.value, int(broken)
+
+
+def md_run_ext(pos, vel, box, rc, skin, dt, steps, eps=1.0, sig=1.0, types=None, mass=None,
+               shift=1, bonds=None, K=30.0, R0=1.5, gamma=0.0, temperature=1.0, seed=0,
+               step0=0):
+    """Velocity Verlet with LJ, optional FENE bonds ([Nb,2] atom indices) and
+    optional Langevin thermostat (noise counter step0 for the initial forces,
+    step0 + 1 + s for step s).  Returns final state, rebuild flags, energies
+    and the number of broken-bond events."""
+    lib = _load()
+    x, y, z = (p.copy() for p in _planes(pos))
+    vx, vy, vz = (p.copy() for p in _planes(vel))
+    n = x.shape[0]
+    e_t, s_t, nt = _tables(eps, sig)
+    t = _types(types, n)
+    m = _f64(np.ones(nt) if mass is None else mass).ravel().copy()
+    if bonds is None:
+        bonds = np.zeros((0, 2), np.int32)
+    bonds = np.ascontiguousarray(bonds, dtype=np.int32)
+    bi = np.ascontiguousarray(bonds[:, 0])
+    bj = np.ascontiguousarray(bonds[:, 1])
+    reb = np.zeros(max(steps, 1), np.uint8)
+    ep, ek = np.zeros(steps + 1), np.zeros(steps + 1)
+    fx, fy, fz = (np.zeros(n) for _ in range(3))
+    r = lib.orc_md_run_ext(n, _d(x), _d(y), _d(z), _d(vx), _d(vy), _d(vz), _i(t), nt, _d(m),
+                           _d(e_t), _d(s_t), _d(_f64(box).ravel().copy()), float(rc), int(shift),
+                           float(skin), float(dt), int(steps), bonds.shape[0], _i(bi), _i(bj),
+                           float(K), float(R0), float(gamma), float(temperature), int(seed),
+                           int(step0), reb.ctypes.data_as(_U8), _d(ep), _d(ek), _d(fx), _d(fy),
+                           _d(fz))
+    if r < 0:
+        raise ValueError(f"orc_md_run_ext failed ({r})")
+    return {
+        "pos": np.stack([x, y, z], axis=1), "vel": np.stack([vx, vy, vz], axis=1),
+        "force": np.stack([fx, fy, fz], axis=1), "rebuild": reb[:steps].astype(bool),
+        "epot": ep, "ekin": ek, "broken": int(r),
+    }

@@ -534,3 +534,108 @@ EXPORT int64_t orc_fene_forces(int32_t n, const double *x, const double *y,
     *virial += w;
     return broken;
 }
+
+/* ------------------------------------------- MD with bonds and a thermostat */
+
+static int64_t total_forces(int32_t n, const double *x, const double *y, const double *z,
+                            const double *vx, const double *vy, const double *vz,
+                            const int32_t *type, int32_t nt, const double *mass,
+                            const double *eps, const double *sig, const double *L,
+                            double rc, int32_t shift, int64_t nb, const int32_t *bi,
+                            const int32_t *bj, double K, double R0, double gamma,
+                            double temperature, double dt, uint64_t seed, uint64_t step,
+                            const int32_t *ids, double *fx, double *fy, double *fz,
+                            double *energy, int64_t *broken)
+{
+    double e, w;
+    int64_t np = orc_lj_forces(n, x, y, z, type, nt, eps, sig, L, rc, shift, fx, fy, fz, &e, &w);
+    if (np < 0) return np;
+    if (nb > 0) *broken += orc_fene_forces(n, x, y, z, L, nb, bi, bj, K, R0, fx, fy, fz, &e, &w);
+    if (gamma > 0.0)
+        orc_langevin(n, vx, vy, vz, type, mass, ids, gamma, temperature, dt, seed, step,
+                     fx, fy, fz);
+    *energy = e;
+    return 0;
+}
+
+/* Velocity Verlet (Sec. 2.1, Fig. 1) with LJ pair forces, optional FENE bonds
+ * (pairs bi[b]-bj[b] of atom indices, the polymer melt of Sec. 4) and an
+ * optional Langevin thermostat (Sec. 4: equilibration to a target T).  The
+ * thermostat force is evaluated with the velocity at the time of the force
+ * evaluation (after Integrate1) and noise counter step0 for the initial force
+ * evaluation, step0 + 1 + s for step s; atom ids are the indices.  Records the
+ * rebuild test like orc_md_run, the potential energy (LJ + FENE) and the
+ * kinetic energy.  Returns the number of broken-bond events (>= 0), or a
+ * negative error. */
+EXPORT int64_t orc_md_run_ext(int32_t n, double *x, double *y, double *z, double *vx,
+                              double *vy, double *vz, const int32_t *type, int32_t nt,
+                              const double *mass, const double *eps, const double *sig,
+                              const double *L, double rc, int32_t shift, double skin,
+                              double dt, int32_t steps, int64_t nb, const int32_t *bi,
+                              const int32_t *bj, double K, double R0, double gamma,
+                              double temperature, uint64_t seed, uint64_t step0,
+                              uint8_t *rebuild, double *epot, double *ekin,
+                              double *fx, double *fy, double *fz)
+{
+    double *xb = malloc(sizeof(double) * n), *yb = malloc(sizeof(double) * n),
+           *zb = malloc(sizeof(double) * n);
+    int32_t *ids = malloc(sizeof(int32_t) * n);
+    if (!xb || !yb || !zb || !ids) { free(xb); free(yb); free(zb); free(ids); return -2; }
+    for (int32_t i = 0; i < n; ++i) ids[i] = i;
+    memcpy(xb, x, sizeof(double) * n);
+    memcpy(yb, y, sizeof(double) * n);
+    memcpy(zb, z, sizeof(double) * n);
+    int64_t broken = 0, rc_ = 0;
+    double e = 0.0;
+    rc_ = total_forces(n, x, y, z, vx, vy, vz, type, nt, mass, eps, sig, L, rc, shift, nb, bi,
+                       bj, K, R0, gamma, temperature, dt, seed, step0, ids, fx, fy, fz, &e,
+                       &broken);
+    double k = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double m = mass[type ? type[i] : 0];
+        k += 0.5 * m * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
+    }
+    if (rc_ < 0) goto done;
+    epot[0] = e; ekin[0] = k;
+    const double lim2 = 0.25 * skin * skin;
+    for (int32_t s = 0; s < steps; ++s) {
+        for (int32_t i = 0; i < n; ++i) {
+            double im = 1.0 / mass[type ? type[i] : 0];
+            vx[i] += 0.5 * dt * fx[i] * im;
+            vy[i] += 0.5 * dt * fy[i] * im;
+            vz[i] += 0.5 * dt * fz[i] * im;
+            x[i] += dt * vx[i];
+            y[i] += dt * vy[i];
+            z[i] += dt * vz[i];
+        }
+        double dmax = 0.0;
+        for (int32_t i = 0; i < n; ++i) {
+            double a = x[i] - xb[i], b = y[i] - yb[i], c = z[i] - zb[i];
+            double d2 = a * a + b * b + c * c;
+            if (d2 > dmax) dmax = d2;
+        }
+        rebuild[s] = (uint8_t)(dmax > lim2);
+        if (rebuild[s]) {
+            memcpy(xb, x, sizeof(double) * n);
+            memcpy(yb, y, sizeof(double) * n);
+            memcpy(zb, z, sizeof(double) * n);
+        }
+        rc_ = total_forces(n, x, y, z, vx, vy, vz, type, nt, mass, eps, sig, L, rc, shift, nb,
+                           bi, bj, K, R0, gamma, temperature, dt, seed, step0 + 1 + (uint64_t)s,
+                           ids, fx, fy, fz, &e, &broken);
+        if (rc_ < 0) goto done;
+        k = 0.0;
+        for (int32_t i = 0; i < n; ++i) {
+            double m = mass[type ? type[i] : 0];
+            double im = 1.0 / m;
+            vx[i] += 0.5 * dt * fx[i] * im;
+            vy[i] += 0.5 * dt * fy[i] * im;
+            vz[i] += 0.5 * dt * fz[i] * im;
+            k += 0.5 * m * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
+        }
+        epot[s + 1] = e; ekin[s + 1] = k;
+    }
+done:
+    free(xb); free(yb); free(zb); free(ids);
+    return rc_ < 0 ? rc_ : broken;
+}

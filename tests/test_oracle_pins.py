@@ -389,3 +389,47 @@ def test_fene_forces_sum_and_broken_count():
     assert e == pytest.approx(u1 + u2, rel=1e-14)
     # bond 0-1 crosses the x face: d = x0 - x1 = +0.8, attractive pulls 0 to -x
     assert f[0, 0] == pytest.approx(fr1 * 0.8, rel=1e-14)
+
+
+# ------------------------------------------- MD with bonds and a thermostat
+
+def test_md_run_ext_reduces_to_nve_run():
+    pos, vel, box = _small_md()
+    a = oracle.md_run(pos, vel, box, RC, SKIN, 0.005, 25)
+    b = oracle.md_run_ext(pos, vel, box, RC, SKIN, 0.005, 25)
+    assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"])
+    assert np.array_equal(a["rebuild"], b["rebuild"])
+    assert np.array_equal(a["epot"], b["epot"]) and np.array_equal(a["ekin"], b["ekin"])
+
+
+def test_bonded_nve_conserves_energy_with_dt_squared_error():
+    # purely repulsive LJ + FENE chains on a lattice path, no thermostat
+    cfg = md_inputs.lattice_chains((6, 6, 10), 20, seed=5, temperature=1.0)
+    fl = []
+    for dt, steps in ((0.004, 100), (0.002, 200)):
+        r = oracle.md_run_ext(cfg.pos, cfg.vel, cfg.box[0], cfg.rc, cfg.skin, dt, steps,
+                              bonds=cfg.bonds)
+        assert r["broken"] == 0
+        etot = r["epot"] + r["ekin"]
+        fl.append(np.sqrt(np.mean((etot - etot.mean()) ** 2)))
+        assert np.abs(r["vel"].sum(axis=0)).max() < 1e-10     # bonds conserve momentum
+    assert 3.0 < fl[0] / fl[1] < 5.2
+
+
+def test_broken_bond_is_counted():
+    box = np.array([10.0, 10.0, 10.0])
+    pos = np.array([[1.0, 1.0, 1.0], [2.6, 1.0, 1.0]])    # 1.6 > R0 = 1.5
+    r = oracle.md_run_ext(pos, np.zeros((2, 3)), box, 2 ** (1 / 6), 0.4, 0.001, 1,
+                          bonds=np.array([[0, 1]]))
+    assert r["broken"] >= 1
+
+
+def test_langevin_thermostat_reaches_target_temperature():
+    pos, box = md_inputs.fcc_lattice(4, 0.8442)
+    vel = md_inputs.maxwell_velocities(pos.shape[0], 0.3, seed=2)
+    target = 1.2
+    r = oracle.md_run_ext(pos, vel, box, RC, SKIN, 0.005, 1600, gamma=1.0,
+                          temperature=target, seed=11)
+    n = pos.shape[0]
+    tkin = 2.0 * r["ekin"][800:] / (3 * n)
+    assert abs(tkin.mean() - target) < 0.08 * target
