@@ -66,6 +66,7 @@ extern "C" {
 #define MD_IDX_MASK   0x03FFFFFFu
 #define MD_MAX_ATOMS  0x03FFFFFF    /* total atoms per call                       */
 #define MD_MAX_TYPES  8             /* atom types                                 */
+#define MD_MAX_BONDS  4             /* bonds per atom                             */
 
 /* Verlet-list entry encoding.  Entry e of atom i names atom j = e & MD_IDX_MASK
  * and the periodic image under which j is i's neighbour: for dimension d
@@ -129,6 +130,16 @@ typedef struct md_lj {
     const double *eps;        /* [ntypes*ntypes] device                           */
     const double *sig;        /* [ntypes*ntypes] device                           */
 } md_lj;
+
+/* Bonds, indexed by original atom id (stable across re-sorts): partner k of
+ * the atom whose id is a is partner[k * N + a] (an id), k < count[a].  Each
+ * bond is listed for both of its atoms. */
+typedef struct md_bonds {
+    int32_t max_bonds;        /* columns of partner, 1 .. MD_MAX_BONDS            */
+    int32_t _pad;
+    const int32_t *count;     /* [N] bonds of the atom with id a                  */
+    const int32_t *partner;   /* [max_bonds * N] partner ids                      */
+} md_bonds;
 
 /* ---------------------------------------------------------------- plumbing */
 
@@ -232,6 +243,32 @@ int md_lj_forces_vjp(const md_batch *b, const md_atoms *atoms, const md_nlist *n
                      const double *gfy, const double *gfz, const double *gE,
                      double *gx, double *geps, double *gsig, void *ws,
                      size_t ws_bytes, uint32_t *status, void *stream);
+
+/* FENE bonds of the bead-spring polymer melt (Sec. 4 of the paper, after
+ * Kremer and Grest): U(r) = -(1/2) K R0^2 ln(1 - r^2/R0^2) with force factor
+ * fr = -K / (1 - r^2/R0^2), minimum-image bond vector.  Forces are ADDED to
+ * fx, fy, fz (call after md_lj_forces).  Needs atoms->where (id -> current
+ * index, kept by md_cell_sort).  A bond with r >= R0 contributes nothing and
+ * raises MD_F_BOND_BROKEN.  energy/virial ([R], optional) receive the bond
+ * energy and virial per replica, reduced in a fixed order.  Each atom sums
+ * its own bonds: deterministic, no atomics. */
+int md_fene_forces(const md_batch *b, const md_atoms *atoms, const md_bonds *bonds,
+                   double K, double R0, double *energy, double *virial, void *ws,
+                   size_t ws_bytes, uint32_t *status, void *stream);
+
+/* Langevin thermostat in force form (Sec. 4: particles equilibrated to a
+ * target temperature T): F_i += -gamma m_i v_i + sqrt(2 gamma m_i T / dt) xi_i
+ * with v the velocity at the time of the force evaluation.  xi_i are three
+ * standard normals from the counter-based generator Philox4x32-10 (Salmon,
+ * Moraes, Dror, Shaw, SC 2011) with key (seed low, seed high) and counters
+ * (id_i, step low, step high, 0) and (..., 1); each pair of 32-bit outputs
+ * forms a 53-bit uniform (w0 w1 >> 11 + 1/2) 2^-53 in (0, 1), and Box-Muller
+ * maps two uniforms to two normals (the fourth normal is unused).  `step`
+ * (device, one uint64) is read by every atom and then advanced by one, so
+ * calls replayed from a captured graph draw fresh noise.  mass: [ntypes]. */
+int md_langevin(const md_batch *b, const md_atoms *atoms, const double *mass,
+                int32_t ntypes, double gamma, double temperature, double dt,
+                uint64_t seed, uint64_t *step, uint32_t *status, void *stream);
 
 #ifdef __cplusplus
 }

@@ -33,12 +33,13 @@ MD_IDX_BITS = 26
 MD_IDX_MASK = 0x03FFFFFF
 MD_MAX_ATOMS = 0x03FFFFFF
 MD_MAX_TYPES = 8
+MD_MAX_BONDS = 4
 MD_TUNE_PAIR_BATCH = 0
 
 EXPORTS = (
     "md_abi_version", "md_strerror", "md_tune_set", "md_tune_get", "md_plan_sizes", "md_plan_fill",
     "md_workspace_bytes", "md_cell_sort", "md_verlet_build", "md_lj_forces",
-    "md_vv_step", "md_lj_forces_vjp",
+    "md_vv_step", "md_lj_forces_vjp", "md_fene_forces", "md_langevin",
 )
 
 _vp = ctypes.c_void_p
@@ -64,6 +65,10 @@ class MdNlist(ctypes.Structure):
 
 class MdLj(ctypes.Structure):
     _fields_ = [("ntypes", _i32), ("shift", _i32), ("rc", _dbl), ("eps", _vp), ("sig", _vp)]
+
+
+class MdBonds(ctypes.Structure):
+    _fields_ = [("max_bonds", _i32), ("_pad", _i32), ("count", _vp), ("partner", _vp)]
 
 
 class MDError(RuntimeError):
@@ -118,6 +123,12 @@ def load():
     lib.md_lj_forces_vjp.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32,
                                      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
                                      _vp, _vp]
+    lib.md_fene_forces.restype = ctypes.c_int
+    lib.md_fene_forces.argtypes = [P(MdBatch), P(MdAtoms), P(MdBonds), _dbl, _dbl, _vp, _vp,
+                                   _vp, ctypes.c_size_t, _vp, _vp]
+    lib.md_langevin.restype = ctypes.c_int
+    lib.md_langevin.argtypes = [P(MdBatch), P(MdAtoms), _vp, _i32, _dbl, _dbl, _dbl,
+                                ctypes.c_uint64, _vp, _vp, _vp]
     _lib = lib
     return lib
 

@@ -1,0 +1,99 @@
+// md_fene.hip -- md_fene_forces: FENE bonds of the bead-spring polymer melt.
+//
+// The paper's polymer melt (Sec. 4) bonds consecutive monomers with the FENE
+// potential U = -(1/2) K R0^2 ln(1 - r^2/R0^2); the force on i from its
+// partner j is fr d with fr = -K / (1 - r^2/R0^2), d = x_i - x_j (minimum
+// image).  One thread per atom walks its own bond row (bonds are indexed by
+// the stable atom id, partners found through where[id]); each bond is seen
+// from both of its atoms, so energy and virial are halved.  No atomics.
+#include "md_common.hpp"
+
+namespace md {
+namespace {
+
+struct FeneArgs {
+    const int32_t *atom_off, *unit_rep, *unit_off;
+    const double *box;
+    const double *x, *y, *z;
+    const int32_t *id, *where;
+    const int32_t *bcount, *bpartner;
+    int32_t N, max_bonds;
+    double K, R02;
+    double *fx, *fy, *fz;
+    double *partial;
+    uint32_t *status;
+};
+
+__global__ __launch_bounds__(kUnit) void k_fene(FeneArgs a)
+{
+    __shared__ double red[kWavesPerUnit];
+    const int u = blockIdx.x;
+    const Unit w = unit_of(u, a.unit_rep, a.unit_off, a.atom_off);
+    const int i = w.begin + threadIdx.x;
+    double e = 0.0, vir = 0.0;
+    if (i < w.end) {
+        const double Lx = a.box[3 * w.rep], Ly = a.box[3 * w.rep + 1], Lz = a.box[3 * w.rep + 2];
+        const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
+        const int me = a.id[i];
+        const int nb = min(a.bcount[me], a.max_bonds);
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        bool broken = false;
+        for (int k = 0; k < nb; ++k) {
+            const int j = a.where[a.bpartner[size_t(k) * a.N + me]];
+            double dx = xi - a.x[j], dy = yi - a.y[j], dz = zi - a.z[j];
+            dx -= Lx * rint(dx / Lx);
+            dy -= Ly * rint(dy / Ly);
+            dz -= Lz * rint(dz / Lz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double q = 1.0 - r2 / a.R02;
+            if (!(q > 0.0)) {
+                broken = true;
+                continue;
+            }
+            const double fr = -a.K / q;
+            fx = fma(fr, dx, fx);
+            fy = fma(fr, dy, fy);
+            fz = fma(fr, dz, fz);
+            e += -0.25 * a.K * a.R02 * log(q);
+            vir += 0.5 * fr * r2;
+        }
+        a.fx[i] += fx;
+        a.fy[i] += fy;
+        a.fz[i] += fz;
+        if (broken && a.status) atomicOr(a.status, MD_F_BOND_BROKEN);
+    }
+    const double es = block_sum(e, red);
+    const double ws = block_sum(vir, red);
+    if (threadIdx.x == 0) {
+        a.partial[size_t(u) * kPartials + 0] = es;
+        a.partial[size_t(u) * kPartials + 1] = ws;
+    }
+}
+
+}  // namespace
+}  // namespace md
+
+extern "C" int md_fene_forces(const md_batch *b, const md_atoms *atoms, const md_bonds *bonds,
+                              double K, double R0, double *energy, double *virial, void *ws,
+                              size_t ws_bytes, uint32_t *status, void *stream)
+{
+    using namespace md;
+    int e = check_batch(b);
+    if (e != MD_OK) return e;
+    if (!atoms || !atoms->x || !atoms->y || !atoms->z || !atoms->fx || !atoms->fy ||
+        !atoms->fz || !atoms->id || !atoms->where || !bonds || !bonds->count ||
+        !bonds->partner || !ws)
+        return MD_EINVAL;
+    if (bonds->max_bonds < 1 || bonds->max_bonds > MD_MAX_BONDS) return MD_EINVAL;
+    if (!(K >= 0.0) || !(R0 > 0.0)) return MD_EINVAL;
+    const WsLayout l = ws_layout(b);
+    if (ws_bytes < l.total) return MD_ENOWS;
+    double *partial = ws_at<double>(ws, l.partial);
+    FeneArgs a{b->atom_off, b->unit_rep, b->unit_off, b->box, atoms->x, atoms->y, atoms->z,
+               atoms->id, atoms->where, bonds->count, bonds->partner, b->N, bonds->max_bonds,
+               K, R0 * R0, atoms->fx, atoms->fy, atoms->fz, partial, status};
+    hipStream_t s = as_stream(stream);
+    hipLaunchKernelGGL(k_fene, dim3(b->n_units), dim3(kUnit), 0, s, a);
+    if (energy || virial) launch_finalize_sum2(b->R, b->unit_off, partial, 0, energy, virial, s);
+    return launch_status();
+}

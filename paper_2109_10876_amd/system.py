@@ -38,7 +38,8 @@ class MDSystem:
 
     def __init__(self, natoms, box, pos, vel, types=None, eps=1.0, sig=1.0, mass=None,
                  rc=2.5, skin=0.3, dt=0.005, shift=1, mode="full", prec="fp64",
-                 max_nbr=None, pos4=True, device="cuda"):
+                 max_nbr=None, pos4=True, bonds=None, fene=(30.0, 1.5), langevin=None,
+                 device="cuda"):
         self.lib = abi.load()
         self.dev = torch.device(device)
         natoms = np.asarray(natoms, dtype=np.int32).ravel()
@@ -129,6 +130,36 @@ class MDSystem:
         self.ke = torch.zeros(self.R, dtype=torch.float64, device=d)
         self._graph = None
 
+        # ---- optional FENE bonds (id pairs [Nb,2]) and Langevin thermostat
+        self.bonds = None
+        if bonds is not None and len(bonds):
+            bonds = np.asarray(bonds, np.int64).reshape(-1, 2)
+            u_ = np.concatenate([bonds[:, 0], bonds[:, 1]])
+            v_ = np.concatenate([bonds[:, 1], bonds[:, 0]])
+            order = np.argsort(u_, kind="stable")
+            u_, v_ = u_[order], v_[order]
+            cnt = np.bincount(u_, minlength=self.N).astype(np.int32)
+            if cnt.max() > abi.MD_MAX_BONDS:
+                raise ValueError(f"an atom has more than {abi.MD_MAX_BONDS} bonds")
+            start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+            part = np.full((abi.MD_MAX_BONDS, self.N), -1, np.int32)
+            part[np.arange(len(u_)) - start[u_], u_] = v_
+            mb = max(1, int(cnt.max()))
+            self.bond_count = i32(cnt)
+            self.bond_partner = i32(np.ascontiguousarray(part[:mb]))
+            self.bonds = abi.MdBonds(mb, 0, self.bond_count.data_ptr(),
+                                     self.bond_partner.data_ptr())
+            self.fene_K, self.fene_R0 = float(fene[0]), float(fene[1])
+            self.energy_bond = torch.zeros(self.R, dtype=torch.float64, device=d)
+            self.virial_bond = torch.zeros(self.R, dtype=torch.float64, device=d)
+        self.langevin_cfg = None
+        if langevin is not None:
+            gamma, temp, seed = langevin[:3]
+            step0 = langevin[3] if len(langevin) > 3 else 0
+            self.langevin_cfg = (float(gamma), float(temp), int(seed))
+            self.mass_t = f64(mass)
+            self.noise_step = torch.tensor([int(step0)], dtype=torch.int64, device=d)
+
     @staticmethod
     def _atoms_struct(s):
         return abi.MdAtoms(s.x.data_ptr(), s.y.data_ptr(), s.z.data_ptr(), s.vx.data_ptr(),
@@ -181,13 +212,34 @@ class MDSystem:
             _ptr(gx), _ptr(geps), _ptr(gsig), _ptr(self.ws), self.ws_bytes,
             _ptr(self.status), self.stream))
 
+    def fene(self):
+        check("md_fene_forces", self.lib.md_fene_forces(
+            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.bonds),
+            self.fene_K, self.fene_R0, _ptr(self.energy_bond), _ptr(self.virial_bond),
+            _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
+
+    def langevin(self):
+        gamma, temp, seed = self.langevin_cfg
+        check("md_langevin", self.lib.md_langevin(
+            ctypes.byref(self.batch), ctypes.byref(self.atoms), _ptr(self.mass_t), self.ntypes,
+            gamma, temp, self.dt, seed, _ptr(self.noise_step), _ptr(self.status),
+            self.stream))
+
+    def all_forces(self):
+        """Pair forces, then (if configured) bond forces and the thermostat."""
+        self.forces()
+        if self.bonds is not None:
+            self.fene()
+        if self.langevin_cfg is not None:
+            self.langevin()
+
     # ------------------------------------------------------------ the step
     def setup(self):
         """Initial re-sort, list build and forces (all replicas)."""
         self.sort(gated=False)
         self.build(gated=False)
         self.ensure_list()
-        self.forces()
+        self.all_forces()
 
     def ensure_list(self):
         """Synchronise; on list overflow grow max_nbr and rebuild every replica."""
@@ -211,7 +263,7 @@ class MDSystem:
         self.vv(1 if first else 3)
         self.sort()
         self.build()
-        self.forces()
+        self.all_forces()
 
     def run(self, steps, check_every=50):
         """`steps` full steps (Integrate2 of step s fused with Integrate1 of s+1)."""

@@ -1,0 +1,122 @@
+"""GPU parity of the polymer-melt and slab pieces: purely repulsive LJ (the
+LJ kernel with rc = 2^(1/6), energy shifted), FENE bonds and the Langevin
+thermostat, against the FP64 oracle (same Philox noise stream)."""
+import numpy as np
+import pytest
+
+import md_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _system(cfg, langevin=None, **kw):
+    from paper_2109_10876_amd import MDSystem
+    return MDSystem(cfg.natoms, cfg.box, cfg.pos, cfg.vel, cfg.types, cfg.eps, cfg.sig,
+                    cfg.mass, rc=cfg.rc, skin=cfg.skin, dt=cfg.dt, shift=cfg.shift,
+                    bonds=cfg.bonds, langevin=langevin, **kw)
+
+
+def test_langevin_noise_matches_oracle():
+    import torch
+    print("case: langevin noise", flush=True)
+    cfg = md_inputs.lj_fluid(6, temperature=1.0, seed=3)
+    s = _system(cfg, langevin=(0.5, 1.3, 12345, 77))
+    s.setup()
+    s.fx.zero_(); s.fy.zero_(); s.fz.zero_()
+    s.noise_step.fill_(77)
+    s.langevin()
+    torch.cuda.synchronize()
+    assert int(s.noise_step.item()) == 78
+    got = s.forces_np()
+    ref = oracle.langevin_forces(s.velocities(), np.arange(cfg.n), 0.5, 1.3, cfg.dt, 12345, 77)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_fene_and_wca_forces_match_oracle():
+    print("case: fene + wca forces", flush=True)
+    cfg = md_inputs.lattice_chains((8, 8, 10), 40, seed=4)
+    cfg.pos = md_inputs.jitter(cfg.pos, 0.05, seed=9)
+    s = _system(cfg)
+    s.setup()
+    s.ensure_list()
+    f_lj, e_lj, w_lj = oracle.lj_forces(cfg.pos, cfg.box[0], cfg.rc, shift=1)
+    f_b, e_b, w_b, broken = oracle.fene_forces(cfg.pos, cfg.box[0], cfg.bonds)
+    assert broken == 0
+    np.testing.assert_allclose(s.forces_np(), f_lj + f_b, rtol=0, atol=1e-9)
+    assert float(s.energy[0]) == pytest.approx(e_lj, rel=1e-12)
+    assert float(s.energy_bond[0]) == pytest.approx(e_b, rel=1e-12)
+    assert float(s.virial_bond[0]) == pytest.approx(w_b, rel=1e-12)
+
+
+def test_broken_bond_raises_the_flag():
+    import torch
+    from paper_2109_10876_amd import _abi as abi
+    print("case: broken bond", flush=True)
+    cfg = md_inputs.lattice_chains((6, 6, 10), 20, seed=4)
+    cfg.pos = cfg.pos.copy()
+    cfg.pos[1] = cfg.pos[0] + np.array([1.6, 0.0, 0.0])     # bond 0-1 beyond R0
+    s = _system(cfg)
+    s.sort(gated=False)
+    s.build(gated=False)
+    s.forces()
+    s.fene()
+    torch.cuda.synchronize()
+    assert int(s.status.item()) & abi.MD_F_BOND_BROKEN
+
+
+def test_melt_trajectory_with_thermostat_matches_oracle():
+    print("case: melt trajectory", flush=True)
+    cfg = md_inputs.lattice_chains((8, 8, 10), 40, seed=6, temperature=1.0)
+    steps = 60
+    s = _system(cfg, langevin=(0.5, 1.0, 2024, 0))
+    s.setup()
+    flags, ep = [], []
+    for t in range(steps):
+        s.step_body(first=(t == 0))
+        flags.append(int(s.gate[0].item()))
+        ep.append(float(s.energy[0]) + float(s.energy_bond[0]))
+    s.vv(2)
+    assert s.ensure_list() == 0
+    ref = oracle.md_run_ext(cfg.pos, cfg.vel, cfg.box[0], cfg.rc, cfg.skin, cfg.dt, steps,
+                            bonds=cfg.bonds, gamma=0.5, temperature=1.0, seed=2024, step0=0)
+    assert ref["broken"] == 0
+    assert flags == list(ref["rebuild"].astype(int))
+    assert np.abs(s.positions() - ref["pos"]).max() < 1e-9
+    assert np.abs(s.velocities() - ref["vel"]).max() < 1e-8
+    np.testing.assert_allclose(ep, ref["epot"][1:], rtol=1e-10)
+    assert float(s.ke[0]) == pytest.approx(ref["ekin"][-1], rel=1e-10)
+
+
+def test_graphed_melt_matches_eager():
+    print("case: melt graph vs eager", flush=True)
+    cfg = md_inputs.lattice_chains((8, 8, 10), 40, seed=6, temperature=1.0)
+    a = _system(cfg, langevin=(0.5, 1.0, 5, 0))
+    a.setup()
+    a.run(23, check_every=0)
+    b = _system(cfg, langevin=(0.5, 1.0, 5, 0))
+    b.setup()
+    b.run_graphed(23, k=4)
+    a.ensure_list()
+    b.ensure_list()
+    assert np.array_equal(a.positions(), b.positions())
+    assert int(a.noise_step.item()) == int(b.noise_step.item()) == 24
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_slab_forces_sampled(prec):
+    # LJ slab: FCC 20^3 x 4 at density 0.8 in the middle third of the box along z
+    print(f"case: slab {prec}", flush=True)
+    cfg = md_inputs.lj_slab(20, seed=8)
+    cfg.pos = md_inputs.jitter(cfg.pos, 0.08, seed=10)
+    s = _system(cfg, prec=prec)
+    s.setup()
+    s.ensure_list()
+    f = s.forces_np()
+    rng = np.random.default_rng(2)
+    smp = rng.choice(cfg.n, 64, replace=False)
+    planes = tuple(np.ascontiguousarray(cfg.pos[:, k]) for k in range(3))
+    ref = np.array([oracle.lj_force_one(i, None, cfg.box[0], cfg.rc, planes=planes)[0]
+                    for i in smp])
+    err = np.linalg.norm(f[smp] - ref) / np.linalg.norm(ref)
+    assert err < (1e-12 if prec == "fp64" else 1e-5)
