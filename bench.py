@@ -125,6 +125,55 @@ def time_path(cfg, prec, steps, warmup, mode, graph_k=50):
     return s, ms, f_ms, mean_k, npairs, err
 
 
+def time_workload(name, steps, warmup=10):
+    """Throughput of one of the other workloads (FP32-mixed, graphed steps):
+    the polymer melt (purely repulsive LJ + FENE + Langevin), the LJ slab
+    (Langevin) and the batch of uneven replicas (NVE), plus, for the batch,
+    one force + adjoint evaluation of a force-matching loss."""
+    import torch
+    import md_inputs
+    from paper_2109_10876_amd import MDSystem
+    cfg = md_inputs.CONFIGS[name]()
+    lang = {"kg_melt": (0.5, 1.0, 3), "lj_slab": (1.0, 0.85, 4)}.get(name)
+    s = MDSystem(cfg.natoms, cfg.box, cfg.pos, cfg.vel, cfg.types, cfg.eps, cfg.sig, cfg.mass,
+                 rc=cfg.rc, skin=cfg.skin, dt=cfg.dt, shift=cfg.shift, bonds=cfg.bonds,
+                 langevin=lang, prec="mixed")
+    s.setup()
+    s.ensure_list()
+    s.run_graphed(warmup, k=25)
+    s.ensure_list()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    s.run_graphed(steps, k=25)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    st = s.ensure_list()
+    out = {"N": s.N, "R": s.R, "steps": steps, "ms_per_step": ms / steps,
+           "atom_steps_per_s": s.N * steps / (ms * 1e-3), "status": st,
+           "mean_list_entries": float(s.count.double().mean().item())}
+    if name == "replicas":
+        gf = [torch.randn(s.N, dtype=torch.float64, device=s.dev) for _ in range(3)]
+        gE = torch.randn(s.R, dtype=torch.float64, device=s.dev)
+        gx = torch.empty(3 * s.N, dtype=torch.float64, device=s.dev)
+        ge = torch.empty(s.ntypes ** 2, dtype=torch.float64, device=s.dev)
+        gs = torch.empty(s.ntypes ** 2, dtype=torch.float64, device=s.dev)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(20):
+            s.forces()
+            s.vjp(*gf, gE, gx, ge, gs)
+        ev1.record()
+        torch.cuda.synchronize()
+        t = ev0.elapsed_time(ev1) / 20
+        out["force_plus_vjp_ms"] = t
+        out["force_plus_vjp_atoms_per_s"] = s.N / (t * 1e-3)
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(cfg):
     """The FP64 oracle as it stands, single-threaded on a host core: one NVE
     step of the same 1,048,576-atom system, taken as the difference of a
@@ -150,6 +199,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--mode", default="full", choices=["full", "half"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the melt / slab / replica-batch throughput lines")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy five times (the "
                          "calibration kernel for HBM byte counters) and exit")
@@ -219,6 +270,16 @@ def main():
                                              "ms_per_step", "force_err_rel", "roofline")},
         "cpu_baseline": None,
     }
+    if not args.no_other:
+        other = {}
+        for name, steps in (("kg_melt", 300), ("lj_slab", 300), ("replicas", 200)):
+            log(f"[{name}] timing {steps} steps")
+            try:
+                other[name] = time_workload(name, steps)
+            except Exception as exc:   # a secondary workload never hides the headline
+                other[name] = {"error": repr(exc)}
+            log(f"[{name}] {json.dumps(other[name])}")
+        line["workloads"] = other
     if not args.no_cpu:
         log("cpu baseline: oracle, one step of the full system")
         line["cpu_baseline"] = cpu_baseline(cfg)
