@@ -52,10 +52,12 @@ extern "C" {
 #define MD_F_NBR_OVERFLOW 0x1u  /* some atom has more list entries than max_nbr     */
 #define MD_F_NONFINITE    0x2u  /* a force or energy came out NaN/Inf               */
 #define MD_F_BOND_BROKEN  0x4u  /* a FENE bond reached its maximum extension        */
+#define MD_F_TILE_OVERFLOW 0x8u /* a tile's staged neighbourhood exceeds MD_TILE_SLOTS */
 
 /* ------------------------------------------------------------------- enums */
 #define MD_HALF 0         /* each unordered pair stored once (Newton's third law) */
 #define MD_FULL 1         /* each pair stored for both atoms                      */
+#define MD_TILE_FULL 2    /* full list in tile-local form (see "Tile-local lists")  */
 #define MD_FP64 0         /* all pair arithmetic in double precision              */
 #define MD_FP32_MIXED 1   /* distances, cutoff test and force accumulation in
                              double; reciprocal and LJ polynomial in single     */
@@ -67,6 +69,8 @@ extern "C" {
 #define MD_MAX_ATOMS  0x03FFFFFF    /* total atoms per call                       */
 #define MD_MAX_TYPES  8             /* atom types                                 */
 #define MD_MAX_BONDS  4             /* bonds per atom                             */
+#define MD_TILE_SLOTS 3072          /* staged atoms per tile (MD_TILE_FULL)       */
+#define MD_TILE_MAX_CELLS 64        /* cells per tile along x                     */
 
 /* Verlet-list entry encoding.  Entry e of atom i names atom j = e & MD_IDX_MASK
  * and the periodic image under which j is i's neighbour: for dimension d
@@ -75,6 +79,22 @@ extern "C" {
  *     d_d = x_i[d] - x_j[d] + s_d * L_d.
  * The image is fixed when the list is built and stays valid until the next
  * rebuild because positions are only wrapped into the box at rebuild time. */
+
+/* Tile-local lists (mode MD_TILE_FULL).  Each row of cells (fixed y, z cell
+ * coordinates) of a replica is cut into tiles of tile_cells consecutive
+ * cells along x (the last tile of a row may be shorter); tiles are numbered
+ * replica by replica, row by row (row = cz * ny + cy), then along x.  The
+ * staged neighbourhood of a tile whose cells are a..b is, for oz = -1, 0, 1
+ * and within it oy = -1, 0, 1 (nine rows, wrapped periodically with the
+ * image the wrap implies), the cells of unwrapped x = a-1 .. b+1 of that row
+ * (x = -1 is cell nx-1 one box length to the left, x = nx is cell 0 one box
+ * length to the right), each cell's atoms in index order, concatenated.
+ * Entry k of atom i is the uint16 ((uint16_t *)idx)[k * ld + i]: the position
+ * of the neighbour in its tile's staged sequence (the neighbour's image is
+ * the one its staged row and cell imply).  A tile whose staged sequence
+ * exceeds md_tile_capacity() (at most MD_TILE_SLOTS) raises MD_F_TILE_OVERFLOW
+ * (the list is then unusable: rebuild with fewer tile_cells).  Tile-local lists take one atom type
+ * (md_lj_forces returns MD_EUNSUPPORTED otherwise) and have no adjoint. */
 
 /* ------------------------------------------------------------------ structs */
 
@@ -113,12 +133,20 @@ typedef struct md_atoms {
 /* Verlet list in ELL layout, column-major so that entry k of consecutive
  * atoms is contiguous: entry k of atom i is idx[k * ld + i]. */
 typedef struct md_nlist {
-    int32_t  mode;            /* MD_HALF or MD_FULL                               */
+    int32_t  mode;            /* MD_HALF, MD_FULL or MD_TILE_FULL                 */
     int32_t  max_nbr;         /* capacity per atom (columns)                      */
     int32_t  ld;              /* leading dimension, >= N and a multiple of 64     */
-    int32_t  _pad;
+    int32_t  tile_cells;      /* MD_TILE_FULL: cells per tile, 1..MD_TILE_MAX_CELLS */
     int32_t  *count;          /* [N] true entry count (may exceed max_nbr)        */
-    uint32_t *idx;            /* [max_nbr * ld] encoded entries (see above)       */
+    uint32_t *idx;            /* [max_nbr * ld] uint32 entries; MD_TILE_FULL uses
+                                 the first half as [max_nbr * ld] uint16 entries  */
+    int32_t  n_tiles;         /* MD_TILE_FULL: tiles (md_tile_plan)               */
+    int32_t  _pad;
+    const int32_t *tile_rep;  /* MD_TILE_FULL: [n_tiles] replica of each tile     */
+    const int32_t *tile_off;  /* MD_TILE_FULL: [R+1] first tile of each replica   */
+    int32_t  *tile_need;      /* optional: largest staged count seen (overflow)   */
+    const int32_t *cell_start;/* MD_TILE_FULL: the [C+1] cell ranges the list was
+                                 built with (unchanged until the next rebuild)    */
 } md_nlist;
 
 /* Lennard-Jones parameters (Eq. lj: U = 4 eps [(sig/r)^12 - (sig/r)^6] for
@@ -153,9 +181,19 @@ const char *md_strerror(int code);
 #define MD_TUNE_PAIR_BATCH 0   /* list entries whose neighbour positions are
                                   gathered together in the force and VJP loops:
                                   1, 2, 4 or 8 (default 4)                      */
-#define MD_TUNE_NKNOBS     1
+#define MD_TUNE_TILE_THREADS 1 /* workgroup size of the tile-local kernels: 64, 128
+                                  or 256 (default 256); staged capacity 1024, 1792
+                                  or 3072 atoms (md_tile_capacity).  Change it only
+                                  before a rebuild of MD_TILE_FULL lists.        */
+#define MD_TUNE_TILE_STAGE_PACKED 2 /* 1: tile staging reads the packed copy when
+                                  present; 0 (default): the x, y, z planes      */
+#define MD_TUNE_NKNOBS     3
 int md_tune_set(int32_t knob, int32_t value);
 int md_tune_get(int32_t knob);
+/* Staged-atom capacity per tile of MD_TILE_FULL lists for the current
+ * MD_TUNE_TILE_THREADS (a tile whose staged sequence is larger raises
+ * MD_F_TILE_OVERFLOW). */
+int md_tile_capacity(void);
 
 /* Host-only planning (no GPU work).  Cells per dimension n_d = floor(L_d /
  * (rc + skin)) so that the cell edge is at least rc + skin (Sec. 2.1.2).
@@ -170,6 +208,13 @@ int md_plan_fill(int32_t R, const int32_t *h_natoms, const double *h_box,
                  double rc, double skin,
                  int32_t *h_atom_off, int32_t *h_cell_off, int32_t *h_ncell,
                  int32_t *h_unit_rep, int32_t *h_unit_off);
+
+/* Tiles of MD_TILE_FULL lists: with h_tile_rep/h_tile_off NULL returns the
+ * number of tiles for tile_cells cells per tile (h_ncell as from
+ * md_plan_fill); otherwise also fills h_tile_rep[n_tiles] and
+ * h_tile_off[R+1].  Negative MD_E* on bad arguments. */
+int md_tile_plan(int32_t R, const int32_t *h_ncell, int32_t tile_cells, int32_t *h_tile_rep,
+                 int32_t *h_tile_off);
 
 /* Bytes of the device workspace used by the calls below for this batch.
  * The workspace must be zero-filled once after allocation; every call

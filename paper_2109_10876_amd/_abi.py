@@ -24,8 +24,12 @@ MD_ERANGE = -6
 MD_F_NBR_OVERFLOW = 0x1
 MD_F_NONFINITE = 0x2
 MD_F_BOND_BROKEN = 0x4
+MD_F_TILE_OVERFLOW = 0x8
 MD_HALF = 0
 MD_FULL = 1
+MD_TILE_FULL = 2
+MD_TILE_SLOTS = 3072
+MD_TILE_MAX_CELLS = 64
 MD_FP64 = 0
 MD_FP32_MIXED = 1
 MD_UNIT_ATOMS = 256
@@ -35,9 +39,12 @@ MD_MAX_ATOMS = 0x03FFFFFF
 MD_MAX_TYPES = 8
 MD_MAX_BONDS = 4
 MD_TUNE_PAIR_BATCH = 0
+MD_TUNE_TILE_THREADS = 1
+MD_TUNE_TILE_STAGE_PACKED = 2
 
 EXPORTS = (
-    "md_abi_version", "md_strerror", "md_tune_set", "md_tune_get", "md_plan_sizes", "md_plan_fill",
+    "md_abi_version", "md_strerror", "md_tune_set", "md_tune_get", "md_tile_capacity", "md_plan_sizes", "md_plan_fill",
+    "md_tile_plan",
     "md_workspace_bytes", "md_cell_sort", "md_verlet_build", "md_lj_forces",
     "md_vv_step", "md_lj_forces_vjp", "md_fene_forces", "md_langevin",
 )
@@ -59,8 +66,9 @@ class MdAtoms(ctypes.Structure):
 
 
 class MdNlist(ctypes.Structure):
-    _fields_ = [("mode", _i32), ("max_nbr", _i32), ("ld", _i32), ("_pad", _i32),
-                ("count", _vp), ("idx", _vp)]
+    _fields_ = [("mode", _i32), ("max_nbr", _i32), ("ld", _i32), ("tile_cells", _i32),
+                ("count", _vp), ("idx", _vp), ("n_tiles", _i32), ("_pad", _i32),
+                ("tile_rep", _vp), ("tile_off", _vp), ("tile_need", _vp), ("cell_start", _vp)]
 
 
 class MdLj(ctypes.Structure):
@@ -105,6 +113,10 @@ def load():
     lib.md_plan_sizes.argtypes = [_i32, _vp, _vp, _dbl, _dbl, P(_i32), P(_i32), P(_i32)]
     lib.md_plan_fill.restype = ctypes.c_int
     lib.md_plan_fill.argtypes = [_i32, _vp, _vp, _dbl, _dbl, _vp, _vp, _vp, _vp, _vp]
+    lib.md_tile_capacity.restype = ctypes.c_int
+    lib.md_tile_capacity.argtypes = []
+    lib.md_tile_plan.restype = ctypes.c_int
+    lib.md_tile_plan.argtypes = [_i32, _vp, _i32, _vp, _vp]
     lib.md_workspace_bytes.restype = ctypes.c_size_t
     lib.md_workspace_bytes.argtypes = [P(MdBatch)]
     lib.md_cell_sort.restype = ctypes.c_int

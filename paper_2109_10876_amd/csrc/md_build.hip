@@ -208,9 +208,14 @@ extern "C" int md_verlet_build(const md_batch *b, const md_atoms *atoms,
     if (!atoms || !atoms->x || !atoms->y || !atoms->z || !cell_start || !nl || !nl->count ||
         !nl->idx)
         return MD_EINVAL;
-    if (nl->mode != MD_HALF && nl->mode != MD_FULL) return MD_EINVAL;
+    if (nl->mode != MD_HALF && nl->mode != MD_FULL && nl->mode != MD_TILE_FULL) return MD_EINVAL;
     if (nl->max_nbr < 1 || nl->ld < b->N || nl->ld % 64 != 0) return MD_EINVAL;
     if (!(rc > 0.0) || !(skin >= 0.0)) return MD_EINVAL;
+    if (nl->mode == MD_TILE_FULL) {
+        if (!tile_list_ok(b, nl) || nl->cell_start != cell_start) return MD_EINVAL;
+        return tile_build(b, atoms, cell_start, (rc + skin) * (rc + skin), nl, need, gate, status,
+                          as_stream(stream));
+    }
     BuildArgs a{b->atom_off, b->cell_off, b->ncell, b->unit_rep, b->unit_off, b->box, gate,
                 atoms->x, atoms->y, atoms->z, atoms->pos4, cell_start,
                 (rc + skin) * (rc + skin), nl->max_nbr, nl->ld, b->n_units, nl->count, nl->idx,

@@ -29,6 +29,7 @@ struct WsLayout {
     size_t slot;         // N x int32
     size_t key;          // N x int32
     size_t vjp_partial;  // n_units x 2 x MD_MAX_TYPES^2 doubles
+    size_t tile_partial; // C x 2 doubles (tiles never outnumber cells)
     size_t total;
 };
 constexpr int kPartials = 4;   // E, W, KE, max displacement^2
@@ -46,6 +47,7 @@ inline WsLayout ws_layout(const md_batch *b)
     l.slot = o;        o = align256(o + size_t(b->N) * sizeof(int32_t));
     l.key = o;         o = align256(o + size_t(b->N) * sizeof(int32_t));
     l.vjp_partial = o; o = align256(o + size_t(b->n_units) * 2 * MD_MAX_TYPES * MD_MAX_TYPES * sizeof(double));
+    l.tile_partial = o; o = align256(o + size_t(b->C) * 2 * sizeof(double));
     l.total = o;
     return l;
 }
@@ -169,6 +171,17 @@ __device__ __forceinline__ double block_max(double v, double *lds)
 }
 
 // -------------------------------------------------------------- host side
+
+// Tile-local lists (md_tile.hip).
+int tile_capacity();
+bool tile_stage_packed();
+bool tile_list_ok(const md_batch *b, const md_nlist *nl);
+int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_start, double rl2,
+               const md_nlist *nl, int32_t *need, const uint32_t *gate, uint32_t *status,
+               hipStream_t s);
+int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const md_lj *p,
+                int32_t prec, int32_t accumulate, const int32_t *cell_start, double *energy,
+                double *virial, double *tpart, int batch, uint32_t *status, hipStream_t s);
 
 // Per-replica fixed-order sums of partial slots k0 and k0+1 (md_forces.hip).
 void launch_finalize_sum2(int R, const int32_t *unit_off, const double *partial, int k0,

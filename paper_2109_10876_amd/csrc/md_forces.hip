@@ -23,7 +23,7 @@
 //
 // Energy and virial: per-unit partial sums in fixed order, then one
 // workgroup per replica sums its units in fixed order.
-#include "md_common.hpp"
+#include "md_pair.hpp"
 
 namespace md {
 namespace {
@@ -46,29 +46,6 @@ struct ForceArgs {
     uint32_t *status;
 };
 
-// Per type pair constants: 24 eps, 4 eps, sig^2, energy shift U(rc).
-struct PairConst {
-    double e24, e4, s2, ush;
-};
-
-__device__ __forceinline__ PairConst pair_const(double eps, double sig, double rc, int shift)
-{
-    PairConst p;
-    p.e24 = 24.0 * eps;
-    p.e4 = 4.0 * eps;
-    p.s2 = sig * sig;
-    double sc2 = p.s2 / (rc * rc);
-    double sc6 = sc2 * sc2 * sc2;
-    p.ush = shift ? 4.0 * eps * (sc6 * sc6 - sc6) : 0.0;
-    return p;
-}
-
-// Per-atom accumulators.  FP64 path: ed, wd; mixed path: ef, wf (single).
-struct Acc {
-    double fx, fy, fz, ed, wd;
-    float ef, wf;
-};
-
 // Neighbour position j: from the packed copy (one 32-byte load) or from the
 // three SoA planes.
 template <bool P4>
@@ -87,8 +64,8 @@ __device__ __forceinline__ void load_pos(const ForceArgs &a, int j, double &px, 
     }
 }
 
-// One list entry: displacement with the entry's periodic image, cutoff test
-// (always in double), pair force / energy / virial.
+// One list entry: displacement with the entry's periodic image, then the
+// pair terms.
 template <int PREC, bool HALF>
 __device__ __forceinline__ void pair(const ForceArgs &a, const PairConst &pc, uint32_t ent,
                                      double dx, double dy, double dz, double Lx, double Ly,
@@ -100,35 +77,12 @@ __device__ __forceinline__ void pair(const ForceArgs &a, const PairConst &pc, ui
         dy += image_shift((code >> 2) & 3u) * Ly;
         dz += image_shift((code >> 4) & 3u) * Lz;
     }
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < rc2) {
-        double fr;
-        if (PREC == MD_FP64) {
-            const double inv = rcp_f64(r2);
-            const double s2 = pc.s2 * inv;
-            const double s6 = s2 * s2 * s2;
-            fr = pc.e24 * s6 * (2.0 * s6 - 1.0) * inv;
-            c.ed += pc.e4 * s6 * (s6 - 1.0) - pc.ush;
-            c.wd += fr * r2;
-        } else {
-            const float r2f = static_cast<float>(r2);
-            const float inv = __builtin_amdgcn_rcpf(r2f);
-            const float s2 = static_cast<float>(pc.s2) * inv;
-            const float s6 = s2 * s2 * s2;
-            const float frf = static_cast<float>(pc.e24) * s6 * (2.0f * s6 - 1.0f) * inv;
-            fr = static_cast<double>(frf);
-            c.ef += static_cast<float>(pc.e4) * s6 * (s6 - 1.0f) - static_cast<float>(pc.ush);
-            c.wf += frf * r2f;
-        }
-        c.fx = fma(fr, dx, c.fx);
-        c.fy = fma(fr, dy, c.fy);
-        c.fz = fma(fr, dz, c.fz);
-        if (HALF) {
-            const int j = static_cast<int>(ent & MD_IDX_MASK);
-            atomicAdd(a.fx + j, -fr * dx);
-            atomicAdd(a.fy + j, -fr * dy);
-            atomicAdd(a.fz + j, -fr * dz);
-        }
+    const double fr = lj_pair_accumulate<PREC>(pc, dx, dy, dz, rc2, c);
+    if (HALF && fr != 0.0) {
+        const int j = static_cast<int>(ent & MD_IDX_MASK);
+        atomicAdd(a.fx + j, -fr * dx);
+        atomicAdd(a.fy + j, -fr * dy);
+        atomicAdd(a.fz + j, -fr * dz);
     }
 }
 
@@ -317,13 +271,20 @@ extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_n
     if (!atoms || !atoms->x || !atoms->y || !atoms->z || !atoms->fx || !atoms->fy ||
         !atoms->fz || !nl || !nl->count || !nl->idx || !p || !p->eps || !p->sig || !ws)
         return MD_EINVAL;
-    if (nl->mode != MD_HALF && nl->mode != MD_FULL) return MD_EINVAL;
+    if (nl->mode != MD_HALF && nl->mode != MD_FULL && nl->mode != MD_TILE_FULL) return MD_EINVAL;
     if (nl->max_nbr < 1 || nl->ld < b->N || nl->ld % 64 != 0) return MD_EINVAL;
     if (p->ntypes < 1 || p->ntypes > MD_MAX_TYPES || !(p->rc > 0.0)) return MD_EINVAL;
     if (p->ntypes > 1 && !atoms->type) return MD_EINVAL;
     if (prec != MD_FP64 && prec != MD_FP32_MIXED) return MD_EINVAL;
     const WsLayout l = ws_layout(b);
     if (ws_bytes < l.total) return MD_ENOWS;
+    if (nl->mode == MD_TILE_FULL) {
+        if (!tile_list_ok(b, nl) || !nl->cell_start) return MD_EINVAL;
+        if (p->ntypes > 1) return MD_EUNSUPPORTED;
+        return tile_forces(b, atoms, nl, p, prec, accumulate, nl->cell_start, energy, virial,
+                           ws_at<double>(ws, l.tile_partial), md_tune_get(MD_TUNE_PAIR_BATCH),
+                           status, as_stream(stream));
+    }
     ForceArgs a{b->atom_off, b->unit_rep, b->unit_off, b->box, atoms->x, atoms->y, atoms->z,
                 atoms->pos4, atoms->type, nl->count, nl->idx, nl->ld, nl->max_nbr, p->eps,
                 p->sig, p->ntypes, p->shift, p->rc, atoms->fx, atoms->fy, atoms->fz, accumulate,

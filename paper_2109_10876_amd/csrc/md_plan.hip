@@ -11,17 +11,20 @@ extern "C" {
 
 int md_abi_version(void) { return MD_ABI_VERSION; }
 
-static int32_t g_tune[MD_TUNE_NKNOBS] = {4};
+static int32_t g_tune[MD_TUNE_NKNOBS] = {4, 256, 0};
 
 int md_tune_set(int32_t knob, int32_t value)
 {
-    if (knob == MD_TUNE_PAIR_BATCH) {
-        if (value != 1 && value != 2 && value != 4 && value != 8) return MD_EINVAL;
-        g_tune[knob] = value;
-        return MD_OK;
-    }
-    return MD_EINVAL;
+    bool ok = false;
+    if (knob == MD_TUNE_PAIR_BATCH) ok = value == 1 || value == 2 || value == 4 || value == 8;
+    if (knob == MD_TUNE_TILE_THREADS) ok = value == 64 || value == 128 || value == 256;
+    if (knob == MD_TUNE_TILE_STAGE_PACKED) ok = value == 0 || value == 1;
+    if (!ok) return MD_EINVAL;
+    g_tune[knob] = value;
+    return MD_OK;
 }
+
+int md_tile_capacity(void) { return md::tile_capacity(); }
 
 int md_tune_get(int32_t knob)
 {
@@ -103,6 +106,25 @@ int md_plan_fill(int32_t R, const int32_t *h_natoms, const double *h_box, double
     h_cell_off[R] = c;
     h_unit_off[R] = u;
     return MD_OK;
+}
+
+int md_tile_plan(int32_t R, const int32_t *h_ncell, int32_t tile_cells, int32_t *h_tile_rep,
+                 int32_t *h_tile_off)
+{
+    if (R < 1 || !h_ncell || tile_cells < 1 || tile_cells > MD_TILE_MAX_CELLS) return MD_EINVAL;
+    int64_t t = 0;
+    for (int32_t r = 0; r < R; ++r) {
+        const int32_t nx = h_ncell[3 * r], ny = h_ncell[3 * r + 1], nz = h_ncell[3 * r + 2];
+        if (nx < 1 || ny < 1 || nz < 1) return MD_EINVAL;
+        const int64_t nt = int64_t(ny) * nz * ((nx + tile_cells - 1) / tile_cells);
+        if (h_tile_off) h_tile_off[r] = static_cast<int32_t>(t);
+        if (h_tile_rep)
+            for (int64_t k = 0; k < nt; ++k) h_tile_rep[t + k] = r;
+        t += nt;
+        if (t > INT32_MAX / 2) return MD_ERANGE;
+    }
+    if (h_tile_off) h_tile_off[R] = static_cast<int32_t>(t);
+    return static_cast<int>(t);
 }
 
 size_t md_workspace_bytes(const md_batch *b)

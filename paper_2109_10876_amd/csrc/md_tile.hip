@@ -1,0 +1,303 @@
+// md_tile.hip -- tile-local Verlet lists (MD_TILE_FULL): list build and LJ
+// forces with the neighbourhood of each tile staged in LDS.
+//
+// Same method as the global-index path (Sec. 2.1.2 cell stencil and Verlet
+// radius, Eq. lj pair terms); only where neighbour positions come from
+// differs.  One workgroup per tile (a run of cells along x in one row):
+//   1. stage the nine neighbouring rows x (a-1 .. b+1) into LDS, images
+//      applied (md_tile.hpp);
+//   2. build: every home atom tests the staged slots of its own 27-cell
+//      stencil -- nine contiguous slot ranges -- and records hits as 16-bit
+//      slots; forces: every home atom walks its list, reading neighbours
+//      from LDS, no periodic-image arithmetic and no L2 gathers.
+#include "md_pair.hpp"
+#include "md_tile.hpp"
+
+namespace md {
+namespace {
+
+struct TileArgs {
+    const int32_t *tile_rep, *tile_off, *ncell, *cell_off;
+    const double *box;
+    const uint32_t *gate;
+    const double *x, *y, *z, *pos4;
+    const int32_t *cell_start;
+    int32_t m, n_tiles, max_nbr, ld;
+    int32_t *count;
+    uint16_t *idx;
+    // build
+    double rl2;
+    int32_t *need, *tile_need;
+    // forces
+    const double *eps, *sig;
+    int32_t shift;
+    double rc;
+    double *fx, *fy, *fz;
+    int32_t accumulate;
+    double *tpart;    // [n_tiles * 2]
+    uint32_t *status;
+};
+
+constexpr int kCandBatch = 8;
+
+template <int TB, bool P4>
+__global__ __launch_bounds__(TB) void k_tile_build(TileArgs a)
+{
+    constexpr int CAP = TileShape<TB>::CAP;
+    __shared__ TileStage<CAP, TileShape<TB>::MAXC> st;
+    for (int lt = blockIdx.x; lt < a.n_tiles; lt += gridDim.x) {
+        const int t = xcd_swizzle(lt, a.n_tiles);
+        const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.m);
+        if (a.gate != nullptr && a.gate[s.rep] == 0u) continue;
+        const int total = stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP);
+        if (total > CAP) {
+            if (threadIdx.x == 0) {
+                if (a.status) atomicOr(a.status, MD_F_TILE_OVERFLOW);
+                if (a.tile_need) atomicMax(a.tile_need, total);
+            }
+            __syncthreads();
+            continue;
+        }
+        const int t0 = a.cell_start[s.home_rb + s.a], t1 = a.cell_start[s.home_rb + s.b + 1];
+        for (int i = t0 + threadIdx.x; i < t1; i += TB) {
+            const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
+            const int cx = min(max(cell_coord(xi, s.L[0], s.nx), s.a), s.b);
+            const int kc = cx - s.a;   // stage index of unwrapped cell cx - 1
+            const int own = st.row_slot[4] + st.cslot[4][kc + 1] +
+                            (i - a.cell_start[s.home_rb + cx]);
+            int cnt = 0;
+            for (int r = 0; r < 9; ++r) {
+                const int s0 = st.row_slot[r] + st.cslot[r][kc];
+                const int s1 = st.row_slot[r] + st.cslot[r][kc + 3];
+                for (int sb = s0; sb < s1; sb += kCandBatch) {
+                    double px[kCandBatch], py[kCandBatch], pz[kCandBatch];
+#pragma unroll
+                    for (int q = 0; q < kCandBatch; ++q) {
+                        const int sl = min(sb + q, s1 - 1);
+                        px[q] = st.x[sl];
+                        py[q] = st.y[sl];
+                        pz[q] = st.z[sl];
+                    }
+#pragma unroll
+                    for (int q = 0; q < kCandBatch; ++q) {
+                        const int sl = sb + q;
+                        const double dx = xi - px[q], dy = yi - py[q], dz = zi - pz[q];
+                        const bool take = sl < s1 && sl != own &&
+                                          dx * dx + dy * dy + dz * dz < a.rl2;
+                        if (take) {
+                            if (cnt < a.max_nbr) a.idx[size_t(cnt) * a.ld + i] = uint16_t(sl);
+                            ++cnt;
+                        }
+                    }
+                }
+            }
+            a.count[i] = cnt;
+            if (cnt > a.max_nbr) {
+                if (a.status) atomicOr(a.status, MD_F_NBR_OVERFLOW);
+                if (a.need) atomicMax(a.need, cnt);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int TB, int PREC, int U, bool P4>
+__global__ __launch_bounds__(TB) void k_tile_lj(TileArgs a)
+{
+    constexpr int CAP = TileShape<TB>::CAP;
+    __shared__ TileStage<CAP, TileShape<TB>::MAXC> st;
+    __shared__ double red[TB / kWave];
+    const int t = xcd_swizzle(blockIdx.x, gridDim.x);
+    const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.m);
+    const PairConst pc = pair_const(a.eps[0], a.sig[0], a.rc, a.shift);
+    const double rc2 = a.rc * a.rc;
+    const int total = stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP);
+    double e_acc = 0.0, w_acc = 0.0;
+    if (total > CAP) {
+        if (threadIdx.x == 0 && a.status) atomicOr(a.status, MD_F_TILE_OVERFLOW);
+    } else {
+        const int t0 = a.cell_start[s.home_rb + s.a], t1 = a.cell_start[s.home_rb + s.b + 1];
+        for (int i = t0 + threadIdx.x; i < t1; i += TB) {
+            const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
+            const int n = min(a.count[i], a.max_nbr);
+            Acc c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
+            const uint16_t *col = a.idx + i;
+            // Entries are consumed U at a time while the next U are already
+            // in flight.  Reads stay inside the allocated columns (index
+            // clamped to max_nbr - 1); entries at k >= n are masked out.
+            const int kmax = a.max_nbr - 1;
+            int cur[U], nxt[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+                cur[q] = __builtin_nontemporal_load(col + size_t(min(q, kmax)) * a.ld);
+            for (int k = 0; k < n; k += U) {
+#pragma unroll
+                for (int q = 0; q < U; ++q)
+                    nxt[q] = __builtin_nontemporal_load(col + size_t(min(k + U + q, kmax)) * a.ld);
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const int sl = min(cur[q], CAP - 1);
+                    const double rcq = k + q < n ? rc2 : 0.0;   // masked: nothing is inside 0
+                    lj_pair_accumulate<PREC>(pc, xi - st.x[sl], yi - st.y[sl], zi - st.z[sl],
+                                             rcq, c);
+                }
+#pragma unroll
+                for (int q = 0; q < U; ++q) cur[q] = nxt[q];
+            }
+            double ed = c.ed, wd = c.wd;
+            if (PREC != MD_FP64) {
+                ed = static_cast<double>(c.ef);
+                wd = static_cast<double>(c.wf);
+            }
+            e_acc += 0.5 * ed;
+            w_acc += 0.5 * wd;
+            if (a.accumulate) {
+                a.fx[i] += c.fx;
+                a.fy[i] += c.fy;
+                a.fz[i] += c.fz;
+            } else {
+                a.fx[i] = c.fx;
+                a.fy[i] = c.fy;
+                a.fz[i] = c.fz;
+            }
+            if (a.status && !isfinite(c.fx + c.fy + c.fz + ed)) atomicOr(a.status, MD_F_NONFINITE);
+        }
+    }
+    const double es = block_sum_t<TB>(e_acc, red);
+    const double ws = block_sum_t<TB>(w_acc, red);
+    if (threadIdx.x == 0) {
+        a.tpart[size_t(t) * 2 + 0] = es;
+        a.tpart[size_t(t) * 2 + 1] = ws;
+    }
+}
+
+// Per replica: fixed-order sums of its tiles' partials.
+__global__ __launch_bounds__(kUnit) void k_tile_finalize(const int32_t *tile_off,
+                                                         const double *tpart, double *energy,
+                                                         double *virial)
+{
+    __shared__ double red[kWavesPerUnit];
+    const int r = blockIdx.x;
+    double s0 = 0.0, s1 = 0.0;
+    for (int t = tile_off[r] + threadIdx.x; t < tile_off[r + 1]; t += kUnit) {
+        s0 += tpart[size_t(t) * 2];
+        s1 += tpart[size_t(t) * 2 + 1];
+    }
+    s0 = block_sum(s0, red);
+    s1 = block_sum(s1, red);
+    if (threadIdx.x == 0) {
+        if (energy) energy[r] = s0;
+        if (virial) virial[r] = s1;
+    }
+}
+
+TileArgs tile_args(const md_batch *b, const md_atoms *atoms, const md_nlist *nl)
+{
+    TileArgs a{};
+    a.tile_rep = nl->tile_rep;
+    a.tile_off = nl->tile_off;
+    a.ncell = b->ncell;
+    a.cell_off = b->cell_off;
+    a.box = b->box;
+    a.x = atoms->x;
+    a.y = atoms->y;
+    a.z = atoms->z;
+    a.pos4 = atoms->pos4;
+    a.m = nl->tile_cells;
+    a.n_tiles = nl->n_tiles;
+    a.max_nbr = nl->max_nbr;
+    a.ld = nl->ld;
+    a.count = nl->count;
+    a.idx = reinterpret_cast<uint16_t *>(nl->idx);
+    a.tile_need = nl->tile_need;
+    return a;
+}
+
+}  // namespace
+
+bool tile_stage_packed() { return md_tune_get(MD_TUNE_TILE_STAGE_PACKED) != 0; }
+
+bool tile_list_ok(const md_batch *b, const md_nlist *nl)
+{
+    return nl->n_tiles >= 1 && nl->n_tiles <= b->C && nl->tile_rep && nl->tile_off &&
+           nl->tile_cells >= 1 && nl->tile_cells <= kTileCells;
+}
+
+int tile_threads() { return md_tune_get(MD_TUNE_TILE_THREADS); }
+
+int tile_capacity()
+{
+    switch (tile_threads()) {
+    case 64: return TileShape<64>::CAP;
+    case 128: return TileShape<128>::CAP;
+    default: return TileShape<256>::CAP;
+    }
+}
+
+int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_start, double rl2,
+               const md_nlist *nl, int32_t *need, const uint32_t *gate, uint32_t *status,
+               hipStream_t s)
+{
+    TileArgs a = tile_args(b, atoms, nl);
+    a.gate = gate;
+    a.cell_start = cell_start;
+    a.rl2 = rl2;
+    a.need = need;
+    a.status = status;
+    const int tb = tile_threads();
+    const dim3 grid(gated_grid(nl->n_tiles, gate != nullptr));
+    const bool p4 = tile_stage_packed() && atoms->pos4;
+#define MD_TB_LAUNCH(TB)                                                                   \
+    do {                                                                                   \
+        if (p4) hipLaunchKernelGGL((k_tile_build<TB, true>), grid, dim3(TB), 0, s, a);     \
+        else hipLaunchKernelGGL((k_tile_build<TB, false>), grid, dim3(TB), 0, s, a);       \
+    } while (0)
+    if (tb == 64) MD_TB_LAUNCH(64);
+    else if (tb == 128) MD_TB_LAUNCH(128);
+    else MD_TB_LAUNCH(256);
+#undef MD_TB_LAUNCH
+    return launch_status();
+}
+
+int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const md_lj *p,
+                int32_t prec, int32_t accumulate, const int32_t *cell_start, double *energy,
+                double *virial, double *tpart, int batch, uint32_t *status, hipStream_t s)
+{
+    TileArgs a = tile_args(b, atoms, nl);
+    a.cell_start = cell_start;
+    a.eps = p->eps;
+    a.sig = p->sig;
+    a.shift = p->shift;
+    a.rc = p->rc;
+    a.fx = atoms->fx;
+    a.fy = atoms->fy;
+    a.fz = atoms->fz;
+    a.accumulate = accumulate;
+    a.tpart = tpart;
+    a.status = status;
+    const dim3 grid(nl->n_tiles);
+    const bool p4 = tile_stage_packed() && atoms->pos4;
+    const int tb = tile_threads();
+    const bool big = batch >= 8;
+#define MD_TILE_LAUNCH(TB, P, U)                                                              \
+    do {                                                                                      \
+        if (p4) hipLaunchKernelGGL((k_tile_lj<TB, P, U, true>), grid, dim3(TB), 0, s, a);     \
+        else hipLaunchKernelGGL((k_tile_lj<TB, P, U, false>), grid, dim3(TB), 0, s, a);       \
+    } while (0)
+#define MD_TILE_PREC(TB)                                                                      \
+    do {                                                                                      \
+        if (prec == MD_FP64) { if (big) MD_TILE_LAUNCH(TB, MD_FP64, 16); else MD_TILE_LAUNCH(TB, MD_FP64, 8); } \
+        else { if (big) MD_TILE_LAUNCH(TB, MD_FP32_MIXED, 16); else MD_TILE_LAUNCH(TB, MD_FP32_MIXED, 8); }     \
+    } while (0)
+    if (tb == 64) MD_TILE_PREC(64);
+    else if (tb == 128) MD_TILE_PREC(128);
+    else MD_TILE_PREC(256);
+#undef MD_TILE_PREC
+#undef MD_TILE_LAUNCH
+    if (energy || virial)
+        hipLaunchKernelGGL(k_tile_finalize, dim3(b->R), dim3(kUnit), 0, s, nl->tile_off, tpart,
+                           energy, virial);
+    return launch_status();
+}
+
+}  // namespace md

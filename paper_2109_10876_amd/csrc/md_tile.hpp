@@ -1,0 +1,202 @@
+// md_tile.hpp -- tile geometry and LDS staging shared by the tile-local list
+// build and the tile-local force kernel (MD_TILE_FULL).
+//
+// A tile is a run of consecutive cells a..b along x in one row of cells.
+// Every pair partner of its atoms lies in the 27-cell stencil of some home
+// cell, i.e. in nine rows x (unwrapped x = a-1 .. b+1).  That region is
+// staged into LDS once per workgroup with each cell's periodic image already
+// applied, so neighbour positions come from LDS instead of L2 gathers and
+// the list can name neighbours by a 16-bit staged slot.
+#pragma once
+
+#include "md_common.hpp"
+
+namespace md {
+
+constexpr int kTileCells = MD_TILE_MAX_CELLS;
+
+// Workgroup shapes of the tile kernels: TB threads (at most TB home atoms per
+// pass), CAP staged slots (3 x 8 CAP bytes of LDS), MAXC cells per tile.
+template <int TB>
+struct TileShape;
+template <>
+struct TileShape<64> {
+    static constexpr int CAP = 1024, MAXC = 8;
+};
+template <>
+struct TileShape<128> {
+    static constexpr int CAP = 1792, MAXC = 16;
+};
+template <>
+struct TileShape<256> {
+    static constexpr int CAP = 3072, MAXC = kTileCells;
+};
+static_assert(TileShape<256>::CAP == MD_TILE_SLOTS, "largest shape holds MD_TILE_SLOTS");
+
+// Block-wide fixed-order sum over TB threads; result valid in thread 0.
+template <int TB>
+__device__ __forceinline__ double block_sum_t(double v, double *lds)
+{
+    v = wave_sum(v);
+    if (TB == kWave) return v;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < TB / kWave; ++k) s += lds[k];
+    __syncthreads();
+    return s;
+}
+
+struct TileSpec {
+    int rep, nx, ny, nz, coff;
+    int a, b;        // home cells along x
+    int cy, cz;      // home row
+    int home_rb;     // linear index of cell (0, cy, cz)
+    double L[3];
+};
+
+__device__ __forceinline__ TileSpec tile_spec(int t, const int32_t *__restrict__ tile_rep,
+                                              const int32_t *__restrict__ tile_off,
+                                              const int32_t *__restrict__ ncell,
+                                              const int32_t *__restrict__ cell_off,
+                                              const double *__restrict__ box, int m)
+{
+    TileSpec s;
+    s.rep = tile_rep[t];
+    s.nx = ncell[3 * s.rep];
+    s.ny = ncell[3 * s.rep + 1];
+    s.nz = ncell[3 * s.rep + 2];
+    s.coff = cell_off[s.rep];
+    const int local = t - tile_off[s.rep];
+    const int tpr = (s.nx + m - 1) / m;
+    const int row = local / tpr, chunk = local % tpr;
+    s.a = chunk * m;
+    s.b = min(s.a + m, s.nx) - 1;
+    s.cy = row % s.ny;
+    s.cz = row / s.ny;
+    s.home_rb = s.coff + row * s.nx;
+    s.L[0] = box[3 * s.rep];
+    s.L[1] = box[3 * s.rep + 1];
+    s.L[2] = box[3 * s.rep + 2];
+    return s;
+}
+
+// LDS tables of one staged tile.
+template <int CAP, int MAXC>
+struct TileStage {
+    static constexpr int kRowStage = MAXC + 3;   // cell starts a-1 .. b+2 of one staged row
+    double x[CAP], y[CAP], z[CAP];
+    int row_slot[10];           // first slot of staged row r; [9] = total staged
+    int row_rb[9];              // linear index of cell (0, y, z) of staged row r
+    int row_lo[9];              // first physical cell of the row's main piece
+    int row_lw[9];              // atoms in the left wrap piece (cell nx-1 at x = -1)
+    int row_main[9];            // atoms in the main piece
+    int row_rw[9];              // atoms in the right wrap piece (cell 0 at x = nx)
+    int row_g0[9][3];           // first atom index of the three pieces
+    double row_dy[9], row_dz[9];  // position shift of the row's image
+    int cslot[9][kRowStage];    // slot (within the row) where unwrapped cell a-1+k starts
+};
+
+// Fills the staging tables and stages positions (x, y, z planes or the
+// packed copy).  All TB threads of the workgroup must call it.  Returns the
+// total staged count (may exceed cap: then nothing is staged).
+template <int TB, bool P4, class Stage>
+__device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
+                          const double *__restrict__ x, const double *__restrict__ y,
+                          const double *__restrict__ z, const double *__restrict__ pos4,
+                          Stage &st, int cap)
+{
+    const int tid = threadIdx.x;
+    __syncthreads();   // the previous tile's readers are done with st
+    if (tid < 9) {
+        const int oz = tid / 3 - 1, oy = tid % 3 - 1;
+        int az = s.cz + oz, ay = s.cy + oy;
+        double dz = 0.0, dy = 0.0;
+        // a row reached across a face holds atoms one box length away
+        if (az < 0) { az += s.nz; dz = -s.L[2]; } else if (az >= s.nz) { az -= s.nz; dz = s.L[2]; }
+        if (ay < 0) { ay += s.ny; dy = -s.L[1]; } else if (ay >= s.ny) { ay -= s.ny; dy = s.L[1]; }
+        const int rb = s.coff + (az * s.ny + ay) * s.nx;
+        const int lo = max(s.a - 1, 0), hi = min(s.b + 1, s.nx - 1);
+        st.row_rb[tid] = rb;
+        st.row_lo[tid] = lo;
+        const int c_last = cs[rb + s.nx - 1], c_end = cs[rb + s.nx];
+        const int c_first = cs[rb], c_second = cs[rb + 1];
+        const int m0 = cs[rb + lo], m1 = cs[rb + hi + 1];
+        st.row_lw[tid] = s.a - 1 < 0 ? c_end - c_last : 0;
+        st.row_main[tid] = m1 - m0;
+        st.row_rw[tid] = s.b + 1 >= s.nx ? c_second - c_first : 0;
+        st.row_g0[tid][0] = c_last;
+        st.row_g0[tid][1] = m0;
+        st.row_g0[tid][2] = c_first;
+        st.row_dy[tid] = dy;
+        st.row_dz[tid] = dz;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int r = 0; r < 9; ++r) {
+            st.row_slot[r] = acc;
+            acc += st.row_lw[r] + st.row_main[r] + st.row_rw[r];
+        }
+        st.row_slot[9] = acc;
+    }
+    // start (within the row) of unwrapped cell xu = a-1+k, k = 0 .. b-a+3
+    const int nk = s.b - s.a + 4;
+    for (int q = tid; q < 9 * nk; q += TB) {
+        const int r = q / nk, k = q % nk, xu = s.a - 1 + k;
+        const int lw = st.row_lw[r], mn = st.row_main[r];
+        int off;
+        if (xu < 0) off = 0;
+        else if (xu < s.nx) off = lw + (cs[st.row_rb[r] + xu] - cs[st.row_rb[r] + st.row_lo[r]]);
+        else if (xu == s.nx) off = lw + mn;
+        else off = lw + mn + st.row_rw[r];
+        st.cslot[r][k] = off;
+    }
+    __syncthreads();
+    const int total = st.row_slot[9];
+    if (total > cap) return total;
+    // Slots tid, tid + B, ... (B = workgroup size): locate each slot's row and
+    // piece, issue every load, then write LDS -- all loads of a thread are in
+    // flight together.
+    constexpr int kPer = (int(sizeof(decltype(st.x)) / sizeof(double)) + TB - 1) / TB;
+    double px[kPer], py[kPer], pz[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int sl = tid + k * TB;
+        if (sl < total) {
+            int r = 0;
+#pragma unroll
+            for (int q = 1; q < 9; ++q) r += sl >= st.row_slot[q] ? 1 : 0;
+            const int off = sl - st.row_slot[r];
+            const int lw = st.row_lw[r], mn = st.row_main[r];
+            const int piece = off < lw ? 0 : (off < lw + mn ? 1 : 2);
+            const int j = st.row_g0[r][piece] + off - (piece == 0 ? 0 : (piece == 1 ? lw : lw + mn));
+            const double dx = piece == 0 ? -s.L[0] : (piece == 1 ? 0.0 : s.L[0]);
+            if (P4) {
+                const double4 v = reinterpret_cast<const double4 *>(pos4)[j];
+                px[k] = v.x + dx;
+                py[k] = v.y + st.row_dy[r];
+                pz[k] = v.z + st.row_dz[r];
+            } else {
+                px[k] = x[j] + dx;
+                py[k] = y[j] + st.row_dy[r];
+                pz[k] = z[j] + st.row_dz[r];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int sl = tid + k * TB;
+        if (sl < total) {
+            st.x[sl] = px[k];
+            st.y[sl] = py[k];
+            st.z[sl] = pz[k];
+        }
+    }
+    __syncthreads();
+    return total;
+}
+
+}  // namespace md

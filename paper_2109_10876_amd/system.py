@@ -39,14 +39,14 @@ class MDSystem:
     def __init__(self, natoms, box, pos, vel, types=None, eps=1.0, sig=1.0, mass=None,
                  rc=2.5, skin=0.3, dt=0.005, shift=1, mode="full", prec="fp64",
                  max_nbr=None, pos4=True, bonds=None, fene=(30.0, 1.5), langevin=None,
-                 device="cuda"):
+                 tile_cells=None, device="cuda"):
         self.lib = abi.load()
         self.dev = torch.device(device)
         natoms = np.asarray(natoms, dtype=np.int32).ravel()
         box = np.asarray(box, dtype=np.float64).reshape(-1, 3)
         self.R = int(natoms.shape[0])
         self.rc, self.skin, self.dt, self.shift = float(rc), float(skin), float(dt), int(shift)
-        self.mode = abi.MD_FULL if mode == "full" else abi.MD_HALF
+        self.mode = {"full": abi.MD_FULL, "half": abi.MD_HALF, "tile": abi.MD_TILE_FULL}[mode]
         self.prec = abi.MD_FP64 if prec == "fp64" else abi.MD_FP32_MIXED
         eps = np.atleast_2d(np.asarray(eps, dtype=np.float64))
         sig = np.atleast_2d(np.asarray(sig, dtype=np.float64))
@@ -114,6 +114,23 @@ class MDSystem:
                            self.sig_t.data_ptr())
         self.cell_start = torch.zeros(self.C + 1, dtype=torch.int32, device=d)
         self.ld = (self.N + 63) // 64 * 64
+        self.tile_need = torch.zeros(1, dtype=torch.int32, device=d)
+        self.tile_cells, self.n_tiles = 0, 0
+        if self.mode == abi.MD_TILE_FULL:
+            if tile_cells is None:
+                # cells per tile: staged neighbourhood 9 (m + 2) nu within 92% of
+                # the staging capacity and about one home atom per thread,
+                # nu = mean atoms per cell of the densest replica; then balanced
+                # along each row
+                nu = float(np.max(natoms / np.prod(self.h_ncell, axis=1)))
+                cap = self.lib.md_tile_capacity()
+                tb = self.lib.md_tune_get(abi.MD_TUNE_TILE_THREADS)
+                m = int(min(0.92 * cap / (9 * nu) - 2, 1.02 * tb / nu))
+                m = max(1, min(m, abi.MD_TILE_MAX_CELLS, int(self.h_ncell[:, 0].max())))
+                nx = int(self.h_ncell[:, 0].max())
+                m = -(-nx // -(-nx // m))
+                tile_cells = m
+            self._plan_tiles(int(tile_cells))
         if max_nbr is None:
             # ideal-gas estimate of neighbours within rc + skin, with margin
             rho = float(np.max(natoms / np.prod(box, axis=1)))
@@ -169,12 +186,33 @@ class MDSystem:
                            s.where.data_ptr(),
                            s.pos4.data_ptr() if s.pos4 is not None else None)
 
+    def _plan_tiles(self, m):
+        ncell = np.ascontiguousarray(self.h_ncell.ravel(), dtype=np.int32)
+        n = self.lib.md_tile_plan(self.R, ncell.ctypes.data, m, None, None)
+        if n < 1:
+            raise abi.MDError("md_tile_plan", n)
+        rep = np.zeros(n, np.int32)
+        off = np.zeros(self.R + 1, np.int32)
+        check("md_tile_plan", min(0, self.lib.md_tile_plan(self.R, ncell.ctypes.data, m,
+                                                           rep.ctypes.data, off.ctypes.data)))
+        self.tile_cells, self.n_tiles = m, n
+        self.tile_rep = torch.as_tensor(rep).to(self.dev)
+        self.tile_off = torch.as_tensor(off).to(self.dev)
+
     def _alloc_list(self, max_nbr):
         self.max_nbr = int(max_nbr)
         self.count = torch.zeros(self.N, dtype=torch.int32, device=self.dev)
         self.idx = torch.zeros(self.max_nbr * self.ld, dtype=torch.int32, device=self.dev)
-        self.nlist = abi.MdNlist(self.mode, self.max_nbr, self.ld, 0, self.count.data_ptr(),
-                                 self.idx.data_ptr())
+        self._set_nlist()
+
+    def _set_nlist(self):
+        tiled = self.mode == abi.MD_TILE_FULL
+        self.nlist = abi.MdNlist(
+            self.mode, self.max_nbr, self.ld, self.tile_cells if tiled else 0,
+            self.count.data_ptr(), self.idx.data_ptr(), self.n_tiles if tiled else 0, 0,
+            self.tile_rep.data_ptr() if tiled else None,
+            self.tile_off.data_ptr() if tiled else None,
+            self.tile_need.data_ptr(), self.cell_start.data_ptr() if tiled else None)
 
     @property
     def stream(self):
@@ -245,6 +283,17 @@ class MDSystem:
         """Synchronise; on list overflow grow max_nbr and rebuild every replica."""
         torch.cuda.synchronize(self.dev)
         st = int(self.status.item())
+        while st & abi.MD_F_TILE_OVERFLOW:
+            if self.tile_cells <= 1:
+                raise RuntimeError("a single-cell tile exceeds the LDS staging capacity")
+            self._plan_tiles(max(1, self.tile_cells - max(1, self.tile_cells // 4)))
+            self._set_nlist()
+            self._graph = None
+            self.status.zero_()
+            self.tile_need.zero_()
+            self.build(gated=False)
+            torch.cuda.synchronize(self.dev)
+            st = int(self.status.item())
         if st & abi.MD_F_NBR_OVERFLOW:
             need = int(self.need.item())
             self._alloc_list(int(need * 1.2) + 8)
@@ -327,8 +376,51 @@ class MDSystem:
     def forces_np(self):
         return self._by_id(self.fx, self.fy, self.fz)
 
+    def tile_slot_table(self):
+        """For MD_TILE_FULL lists: per tile, the global index of every staged
+        slot, following the staged order documented in md.h."""
+        cs = self.cell_start.cpu().numpy()
+        rep = self.tile_rep.cpu().numpy()
+        toff = self.tile_off.cpu().numpy()
+        coff = np.concatenate([[0], np.cumsum(np.prod(self.h_ncell, axis=1))])
+        m = self.tile_cells
+        tables = []
+        for t in range(self.n_tiles):
+            r = rep[t]
+            nx, ny, nz = self.h_ncell[r]
+            tpr = -(-nx // m)
+            local = t - toff[r]
+            row, chunk = divmod(local, tpr)
+            a = chunk * m
+            b = min(a + m, nx) - 1
+            cy, cz = row % ny, row // ny
+            slots = []
+            for oz in (-1, 0, 1):
+                for oy in (-1, 0, 1):
+                    rb = coff[r] + (((cz + oz) % nz) * ny + (cy + oy) % ny) * nx
+                    for xu in range(a - 1, b + 2):
+                        c = rb + xu % nx
+                        slots.extend(range(cs[c], cs[c + 1]))
+            t0 = cs[coff[r] + row * nx + a]
+            t1 = cs[coff[r] + row * nx + b + 1]
+            tables.append((t0, t1, np.array(slots, dtype=np.int64)))
+        return tables
+
     def list_pairs(self):
-        """Verlet list as (id_i, id_j) pairs [P,2] plus decoded image codes."""
+        """Verlet list as (id_i, id_j) pairs [P,2] plus decoded image codes
+        (image codes are not decoded for tile-local lists: None)."""
+        if self.mode == abi.MD_TILE_FULL:
+            cnt = self.count.cpu().numpy()
+            idx = self.idx.cpu().numpy().view(np.uint16)[:self.max_nbr * self.ld]
+            idx = idx.reshape(self.max_nbr, self.ld)
+            ids = self.id.cpu().numpy()
+            out = []
+            for t0, t1, slots in self.tile_slot_table():
+                for i in range(t0, t1):
+                    n = min(cnt[i], self.max_nbr)
+                    js = slots[idx[:n, i].astype(np.int64)]
+                    out.append(np.stack([np.full(n, ids[i]), ids[js]], 1))
+            return np.concatenate(out), None
         cnt = self.count.cpu().numpy()
         n = np.minimum(cnt, self.max_nbr)
         idx = self.idx.cpu().numpy().view(np.uint32).reshape(self.max_nbr, self.ld)[:, :self.N]

@@ -40,6 +40,19 @@ def test_header_constants_match_binding():
         assert int(m.group(1), 0) == getattr(abi, name), name
 
 
+def test_tile_plan():
+    lib = abi.load()
+    ncell = np.array([38, 38, 38, 2, 3, 5], np.int32)
+    n = lib.md_tile_plan(2, ncell.ctypes.data, 10, None, None)
+    assert n == 38 * 38 * 4 + 3 * 5 * 1
+    rep = np.zeros(n, np.int32)
+    off = np.zeros(3, np.int32)
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 10, rep.ctypes.data, off.ctypes.data) == n
+    assert list(off) == [0, 5776, 5791] and rep[5775] == 0 and rep[5776] == 1
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 0, None, None) == abi.MD_EINVAL
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 65, None, None) == abi.MD_EINVAL
+
+
 def test_tuning_knobs():
     lib = abi.load()
     assert lib.md_tune_get(abi.MD_TUNE_PAIR_BATCH) == 4
@@ -47,6 +60,13 @@ def test_tuning_knobs():
         assert lib.md_tune_set(abi.MD_TUNE_PAIR_BATCH, v) == abi.MD_OK
         assert lib.md_tune_get(abi.MD_TUNE_PAIR_BATCH) == v
     assert lib.md_tune_set(abi.MD_TUNE_PAIR_BATCH, 3) == abi.MD_EINVAL
+    assert lib.md_tune_get(abi.MD_TUNE_TILE_THREADS) == 256
+    assert lib.md_tile_capacity() == abi.MD_TILE_SLOTS
+    for tb, cap in ((64, 1024), (128, 1792), (256, 3072)):
+        assert lib.md_tune_set(abi.MD_TUNE_TILE_THREADS, tb) == abi.MD_OK
+        assert lib.md_tile_capacity() == cap
+    assert lib.md_tune_set(abi.MD_TUNE_TILE_THREADS, 96) == abi.MD_EINVAL
+    assert lib.md_tune_set(abi.MD_TUNE_TILE_STAGE_PACKED, 2) == abi.MD_EINVAL
     assert lib.md_tune_set(99, 1) == abi.MD_EINVAL
     assert lib.md_tune_get(99) == abi.MD_EINVAL
 
@@ -115,13 +135,13 @@ def test_calls_reject_bad_arguments_without_a_gpu():
     # on bad modes and on a short workspace, before anything is launched
     ok = abi.MdBatch(1, 1000, 27, 4, 8, 8, 8, 8, 8, 8)
     assert lib.md_workspace_bytes(P(ok)) > 0
-    nl = abi.MdNlist(7, 64, 1024, 0, 8, 8)
+    nl = abi.MdNlist(7, 64, 1024, 0, 8, 8, 0, 0, None, None, None, None)
     assert lib.md_verlet_build(P(ok), P(atoms), 8, 2.5, 0.3, P(nl), None, None, None, None) == abi.MD_EINVAL
     full = abi.MdAtoms(*([8] * 17))
-    nl = abi.MdNlist(abi.MD_HALF, 64, 1000, 0, 8, 8)   # ld not a multiple of 64
+    nl = abi.MdNlist(abi.MD_HALF, 64, 1000, 0, 8, 8, 0, 0, None, None, None, None)   # ld % 64
     lj1 = abi.MdLj(1, 1, 2.5, 8, 8)
     assert lib.md_lj_forces(P(ok), P(full), P(nl), P(lj1), 0, 0, None, None, 8, 1 << 30, None, None) == abi.MD_EINVAL
-    nl = abi.MdNlist(abi.MD_HALF, 64, 1024, 0, 8, 8)
+    nl = abi.MdNlist(abi.MD_HALF, 64, 1024, 0, 8, 8, 0, 0, None, None, None, None)
     assert lib.md_lj_forces(P(ok), P(full), P(nl), P(lj1), 5, 0, None, None, 8, 1 << 30, None, None) == abi.MD_EINVAL
     assert lib.md_lj_forces(P(ok), P(full), P(nl), P(lj1), 0, 0, None, None, 8, 16, None, None) == abi.MD_ENOWS
     assert lib.md_lj_forces_vjp(P(ok), P(full), P(nl), P(lj1), 0, 8, 8, 8, None, 8, None, None,

@@ -42,7 +42,7 @@ def c1_snapshot():
     return md_inputs.lj_fluid(10, temperature=0.72, seed=1, jitter_amp=0.1)
 
 
-@pytest.mark.parametrize("mode", ["full", "half"])
+@pytest.mark.parametrize("mode", ["full", "half", "tile"])
 def test_forces_fp64_match_oracle(c1_snapshot, mode):
     cfg = c1_snapshot
     say(f"case: forces fp64 {mode} N={cfg.n}")
@@ -57,7 +57,7 @@ def test_forces_fp64_match_oracle(c1_snapshot, mode):
     assert float(s.virial[0]) == pytest.approx(w, rel=1e-12)
 
 
-@pytest.mark.parametrize("mode", ["full", "half"])
+@pytest.mark.parametrize("mode", ["full", "half", "tile"])
 def test_forces_mixed_within_bound(c1_snapshot, mode):
     cfg = c1_snapshot
     say(f"case: forces mixed {mode} N={cfg.n}")
@@ -115,7 +115,7 @@ def _unordered(pairs):
     return set(map(tuple, np.unique(p, axis=0)))
 
 
-@pytest.mark.parametrize("mode", ["full", "half"])
+@pytest.mark.parametrize("mode", ["full", "half", "tile"])
 def test_verlet_list_is_the_skin_pair_set(c1_snapshot, mode):
     cfg = c1_snapshot
     say(f"case: list set {mode}")
@@ -125,7 +125,7 @@ def test_verlet_list_is_the_skin_pair_set(c1_snapshot, mode):
     # each unordered pair exactly twice (full) or once (half)
     p = np.sort(pairs, axis=1)
     _, mult = np.unique(p, axis=0, return_counts=True)
-    assert np.all(mult == (2 if mode == "full" else 1))
+    assert np.all(mult == (1 if mode == "half" else 2))
     got = _unordered(pairs)
     rl = RC + SKIN
     ref = oracle.pairs_cells(cfg.pos, cfg.box[0], rl)
@@ -142,22 +142,23 @@ def test_verlet_list_is_the_skin_pair_set(c1_snapshot, mode):
 def test_fcc_lattice_exact_counts():
     cfg = md_inputs.lj_fluid(10, temperature=0.72, seed=1)
     say("case: fcc counts")
-    for mode, per in (("full", 78), ("half", 39)):
+    for mode, per in (("full", 78), ("half", 39), ("tile", 78)):
         s = _system(cfg, mode=mode)
         s.setup()
         cnt = s.count.cpu().numpy()
-        if mode == "full":
+        if mode != "half":
             assert np.all(cnt == per)
         else:
             assert cnt.sum() == per * cfg.n
         assert np.abs(s.forces_np()).max() < 1e-10
 
 
-def test_trajectory_matches_oracle_100_steps():
+@pytest.mark.parametrize("mode", ["full", "tile"])
+def test_trajectory_matches_oracle_100_steps(mode):
     # the 4000-atom parity workload: T = 0.72, 100 NVE steps, FP64
     cfg = md_inputs.lj_fluid(10, temperature=0.72, seed=1)
-    say("case: trajectory 100 steps fp64")
-    s = _system(cfg, mode="full", prec="fp64")
+    say(f"case: trajectory 100 steps fp64 {mode}")
+    s = _system(cfg, mode=mode, prec="fp64")
     s.setup()
     flags, ek, ep = [], [], []
     for t in range(cfg.steps):
@@ -321,13 +322,14 @@ def test_vjp_matches_oracle(prec):
     np.testing.assert_allclose(gsig.cpu().numpy().reshape(2, 2), gs_ref, rtol=tol * 10)
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_full_size_sampled_forces(prec):
+@pytest.mark.parametrize("prec,mode", [("mixed", "full"), ("fp64", "full"),
+                                       ("mixed", "tile"), ("fp64", "tile")])
+def test_full_size_sampled_forces(prec, mode):
     # the 1,048,576-atom workload, in the configuration the benchmark times,
     # jittered so forces are non-zero; 48 sampled atoms by O(N) oracle loops
     cfg = md_inputs.lj_fluid(64, temperature=1.0, seed=2, jitter_amp=0.1)
-    say(f"case: 1M sampled {prec}")
-    s = _system(cfg, mode="full", prec=prec)
+    say(f"case: 1M sampled {prec} {mode}")
+    s = _system(cfg, mode=mode, prec=prec)
     s.setup()
     s.ensure_list()
     f = s.forces_np()
@@ -342,3 +344,62 @@ def test_full_size_sampled_forces(prec):
     # the list at t=0 holds every pair within rc + skin: FCC-perturbed counts
     cnt = s.count.cpu().numpy()
     assert cnt.min() > 40 and cnt.max() < s.max_nbr
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_tile_lists_in_two_cell_boxes(m):
+    # 256 atoms in a 6.72 box: two cells per dimension, so every staged row
+    # wraps on both sides and holds cells twice under different images
+    cfg = md_inputs.lj_fluid(4, temperature=1.0, seed=17, jitter_amp=0.1)
+    say(f"case: tile two-cell box m={m}")
+    s = _system(cfg, mode="tile", tile_cells=m)
+    s.setup()
+    assert s.ensure_list() == 0
+    ref, e, w = oracle.lj_forces(cfg.pos, cfg.box[0], RC, shift=1)
+    assert np.abs(s.forces_np() - ref).max() < 1e-10
+    assert float(s.energy[0]) == pytest.approx(e, rel=1e-12)
+    got = _unordered(s.list_pairs()[0])
+    exp = set(map(tuple, oracle.pairs_cells(cfg.pos, cfg.box[0], RC + SKIN)))
+    assert got == exp
+
+
+def test_tile_overflow_is_flagged_and_recovered():
+    from paper_2109_10876_amd import _abi as abi
+    import torch
+    # 87,808 atoms, 16 cells per row of ~21.4 atoms: a 16-cell tile stages
+    # 9 rows x 18 cells x 21.4 ~ 3470 atoms > 3072 slots
+    cfg = md_inputs.lj_fluid(28, temperature=1.0, seed=19, jitter_amp=0.1)
+    say("case: tile overflow")
+    s = _system(cfg, mode="tile", tile_cells=16)
+    s.sort(gated=False)
+    s.build(gated=False)
+    torch.cuda.synchronize()
+    assert int(s.status.item()) & abi.MD_F_TILE_OVERFLOW
+    assert int(s.tile_need.item()) > abi.MD_TILE_SLOTS
+    s.ensure_list()
+    assert s.tile_cells < 16
+    s.forces()
+    f = s.forces_np()
+    planes = tuple(np.ascontiguousarray(cfg.pos[:, k]) for k in range(3))
+    for i in np.random.default_rng(0).choice(cfg.n, 24, replace=False):
+        ref = oracle.lj_force_one(i, None, cfg.box[0], RC, planes=planes)[0]
+        assert np.abs(f[i] - ref).max() < 1e-10
+
+
+def test_tile_graph_replays_match_eager():
+    cfg = md_inputs.lj_fluid(8, temperature=1.5, seed=23)
+    say("case: tile graph vs eager")
+    a = _system(cfg, mode="tile")
+    a.setup()
+    a.run(30, check_every=0)
+    b = _system(cfg, mode="tile")
+    b.setup()
+    b.run_graphed(30, k=4)
+    a.ensure_list()
+    b.ensure_list()
+    assert np.array_equal(a.positions(), b.positions())
+    f = _system(cfg, mode="full")
+    f.setup()
+    f.run(30, check_every=0)
+    f.ensure_list()
+    assert np.abs(f.positions() - a.positions()).max() < 1e-10
