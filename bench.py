@@ -28,15 +28,20 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
 # HBM bytes per md_lj_forces launch on this workload from rocprofv3 FETCH_SIZE
 # and WRITE_SIZE (calibrated against a plain copy), valid only for the kernel
 # source they were taken on (profiles/lj_forces_lj1m_hbm_counters.md).
-COUNTED_TRAFFIC = {"src_sha256_16": "fc65f92f8a9bfda0",
-                   "bytes_per_launch": {"mixed": 208596.2 * 1024 * 2.0 + 24721.2 * 1024,
-                                        "fp64": 208608.7 * 1024 * 2.0 + 24723.3 * 1024}}
+# keyed by list form; each entry: source hash of the kernel's files and
+# calibrated bytes per launch for the FP32-mixed and FP64 paths
+COUNTED_TRAFFIC = {}
+
+FORCE_KERNEL_SOURCES = {
+    "full": ("md_forces.hip", "md_pair.hpp", "md_common.hpp"),
+    "tile": ("md_tile.hip", "md_tile.hpp", "md_pair.hpp", "md_common.hpp"),
+}
 
 
-def force_kernel_src_hash():
+def force_kernel_src_hash(mode):
     import hashlib
     h = hashlib.sha256()
-    for f in ("md_forces.hip", "md_common.hpp"):
+    for f in FORCE_KERNEL_SOURCES.get(mode, ()):
         with open(os.path.join(ROOT, "paper_2109_10876_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -47,45 +52,38 @@ def log(msg):
 
 
 def pairs_within_rc(s):
-    """Unordered pairs within rc at the current positions, counted from the
-    full list with torch ops (measurement only, outside the timed region)."""
-    import torch
-    N, K = s.N, s.max_nbr
-    idx = s.idx.view(K, s.ld)[:, :N].long() & 0xFFFFFFFF
-    j = idx & 0x03FFFFFF
-    code = idx >> 26
-    cnt = s.count.long()
-    valid = torch.arange(K, device=s.dev)[:, None] < cnt[None, :]
-    L = s.box.view(-1, 3)[0]
-    tot = 0
-    for k, (p, Ld) in enumerate(((s.x, L[0]), (s.y, L[1]), (s.z, L[2]))):
-        c = (code >> (2 * k)) & 3
-        sh = torch.where(c == 1, 1.0, torch.where(c == 2, -1.0, 0.0)).double()
-        d = p[None, :] - p[j] + sh * Ld
-        tot = tot + d * d
-    inside = (tot < s.rc * s.rc) & valid
-    return int(inside.sum().item()) // 2
+    """Unordered pairs within rc at the current positions: a full list of
+    radius rc (skin 0) built by libmd itself from the current state
+    (measurement only, outside the timed region)."""
+    from paper_2109_10876_amd import MDSystem
+    t = MDSystem(s.h_atom_off[1:] - s.h_atom_off[:-1], s.h_box, s.positions(),
+                 s.velocities(), rc=s.rc, skin=0.0, dt=s.dt, shift=s.shift, mode="full")
+    t.setup()
+    t.ensure_list()
+    n = int(t.count.sum().item()) // 2
+    del t
+    return n
 
 
-def sampled_force_error(s, nsample=32, seed=0):
-    """Normwise relative force error of the GPU forces against the FP64
-    oracle (O(N) loop per atom) on sampled atoms of the current state."""
+def sampled_force_error(pos, f, box, rc, nsample=32, seed=0):
+    """Normwise relative force error of GPU forces ``f`` (by atom id) against
+    the FP64 oracle's O(N) loop on sampled atoms (CPU-baseline leg)."""
     import oracle
     rng = np.random.default_rng(seed)
-    pos = s.positions()
-    f = s.forces_np()
     planes = tuple(np.ascontiguousarray(pos[:, k]) for k in range(3))
-    smp = rng.choice(s.N, nsample, replace=False)
-    ref = np.array([oracle.lj_force_one(i, None, s.h_box[0], s.rc, planes=planes)[0]
-                    for i in smp])
+    smp = rng.choice(pos.shape[0], nsample, replace=False)
+    ref = np.array([oracle.lj_force_one(i, None, box, rc, planes=planes)[0] for i in smp])
     return float(np.linalg.norm(f[smp] - ref) / np.linalg.norm(ref))
 
 
-def time_path(cfg, prec, steps, warmup, mode, graph_k=50):
+def time_path(cfg, prec, steps, warmup, tuned, graph_k=50):
     import torch
-    from paper_2109_10876_amd import MDSystem
+    from paper_2109_10876_amd import MDSystem, autotune
+    autotune.apply(tuned)
     s = MDSystem(cfg.natoms, cfg.box, cfg.pos, cfg.vel, rc=cfg.rc, skin=cfg.skin, dt=cfg.dt,
-                 shift=cfg.shift, mode=mode, prec=prec)
+                 shift=cfg.shift, mode=tuned["mode"], prec=prec,
+                 tile_cells=tuned.get("tile_cells"),
+                 tile_rows=tuple(tuned.get("tile_rows", (1, 1))))
     s.setup()
     s.ensure_list()
     if warmup:
@@ -121,8 +119,8 @@ def time_path(cfg, prec, steps, warmup, mode, graph_k=50):
     f_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     mean_k = float(s.count.double().mean().item())
     npairs = pairs_within_rc(s)
-    err = sampled_force_error(s)
-    return s, ms, f_ms, mean_k, npairs, err
+    snap = (s.positions(), s.forces_np())
+    return s, ms, f_ms, mean_k, npairs, snap
 
 
 def time_workload(name, steps, warmup=10):
@@ -197,7 +195,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--mode", default="full", choices=["full", "half"])
+    ap.add_argument("--mode", default="auto", choices=["auto", "full", "half", "tile"],
+                    help="list form; auto = chosen by the autotuner (untimed)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the melt / slab / replica-batch throughput lines")
@@ -222,31 +221,47 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 8, "launches": 5}))
         return
     cfg = md_inputs.CONFIGS["lj1m"]()
-    out = {}
+    from paper_2109_10876_amd import MDSystem, autotune
+    if args.mode == "auto":
+        def make(mode, tile_cells, tile_rows=(1, 1)):
+            return MDSystem(cfg.natoms, cfg.box, cfg.pos, cfg.vel, rc=cfg.rc, skin=cfg.skin,
+                            dt=cfg.dt, shift=cfg.shift, mode=mode, prec="mixed",
+                            tile_cells=tile_cells, tile_rows=tile_rows)
+        key = autotune.signature(cfg.natoms, cfg.box, cfg.rc, cfg.skin, 1)
+        tuned, _ = autotune.tune(make, key, steps=40, warmup=10, cache=None, log=log)
+    else:
+        tuned = {"mode": args.mode, "batch": 4, "tile_threads": 256, "tile_cells": None,
+                 "tile_rows": [2, 2]}
+    log(f"configuration: {json.dumps(tuned)}")
+    out, snaps = {}, {}
     for prec in ("mixed", "fp64"):
         log(f"[{prec}] timing {args.steps} steps after {args.warmup} warm-up steps")
-        s, ms, f_ms, mean_k, npairs, err = time_path(cfg, prec, args.steps, args.warmup,
-                                                     args.mode)
+        s, ms, f_ms, mean_k, npairs, snap = time_path(cfg, prec, args.steps, args.warmup, tuned)
+        snaps[prec] = snap
         # algorithmic bytes of one md_lj_forces launch: per atom the list
-        # column (4 B x entries), count (4 B), own position (24 B) and force
-        # write (24 B); neighbour positions are cache-resident gathers
-        bytes_launch = s.N * (4.0 * mean_k + 4 + 24 + 24)
+        # column (4 B per entry, 2 B for tile-local lists), count (4 B), own
+        # position (24 B) and force write (24 B); neighbour positions are
+        # cache- or LDS-resident
+        ebytes = 2.0 if tuned["mode"] == "tile" else 4.0
+        bytes_launch = s.N * (ebytes * mean_k + 4 + 24 + 24)
         gbs = bytes_launch / (f_ms * 1e-3) / 1e9
         traffic = None
-        if force_kernel_src_hash() == COUNTED_TRAFFIC["src_sha256_16"]:
-            traffic = COUNTED_TRAFFIC["bytes_per_launch"][prec] / (f_ms * 1e-3) / 1e9
+        counted = COUNTED_TRAFFIC.get(tuned["mode"])
+        if counted and force_kernel_src_hash(tuned["mode"]) == counted["src_sha256_16"]:
+            traffic = counted["bytes_per_launch"][prec] / (f_ms * 1e-3) / 1e9
         out[prec] = {
             "ms_per_step": ms / args.steps,
             "atom_steps_per_s": s.N * args.steps / (ms * 1e-3),
             "pair_evals_per_s": npairs * args.steps / (ms * 1e-3),
             "pairs_within_rc": npairs,
             "mean_list_entries": mean_k,
-            "force_err_rel": err,
+            "force_err_rel": None,
             "forces_kernel_ms": f_ms,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
                          "bytes_per_launch": bytes_launch,
-                         "kernel": "md_lj_forces (k_lj)"},
+                         "kernel": "md_lj_forces (%s)" % ("k_tile_lj" if tuned["mode"] == "tile"
+                                                          else "k_lj")},
         }
         log(f"[{prec}] {json.dumps(out[prec])}")
         del s
@@ -262,7 +277,7 @@ def main():
         "dtype": "f32/f64",
         "data": "synthetic",
         "config": {"workload": "LJ fluid FCC 64^3x4 N=1048576 rho=0.8442 T=1.0 rc=2.5 "
-                               "skin=0.3 dt=0.005 NVE", "list": args.mode, "N": cfg.n},
+                               "skin=0.3 dt=0.005 NVE", "N": cfg.n, "launch": tuned},
         "pair_evals_per_s": m["pair_evals_per_s"],
         "force_err_rel": m["force_err_rel"],
         "roofline": m["roofline"],
@@ -281,8 +296,15 @@ def main():
             log(f"[{name}] {json.dumps(other[name])}")
         line["workloads"] = other
     if not args.no_cpu:
+        # the oracle leg: CPU timing, and the force error of both GPU paths
+        # on their final states against the oracle's O(N) loop
         log("cpu baseline: oracle, one step of the full system")
         line["cpu_baseline"] = cpu_baseline(cfg)
+        for prec in ("mixed", "fp64"):
+            pos, f = snaps[prec]
+            out[prec]["force_err_rel"] = sampled_force_error(pos, f, cfg.box[0], cfg.rc)
+        line["force_err_rel"] = out["mixed"]["force_err_rel"]
+        line["fp64"]["force_err_rel"] = out["fp64"]["force_err_rel"]
     print(json.dumps(line), flush=True)
 
 

@@ -71,6 +71,7 @@ extern "C" {
 #define MD_MAX_BONDS  4             /* bonds per atom                             */
 #define MD_TILE_SLOTS 3072          /* staged atoms per tile (MD_TILE_FULL)       */
 #define MD_TILE_MAX_CELLS 64        /* cells per tile along x                     */
+#define MD_TILE_MAX_ROWS  2         /* cell rows per tile along y and along z     */
 
 /* Verlet-list entry encoding.  Entry e of atom i names atom j = e & MD_IDX_MASK
  * and the periodic image under which j is i's neighbour: for dimension d
@@ -80,20 +81,21 @@ extern "C" {
  * The image is fixed when the list is built and stays valid until the next
  * rebuild because positions are only wrapped into the box at rebuild time. */
 
-/* Tile-local lists (mode MD_TILE_FULL).  Each row of cells (fixed y, z cell
- * coordinates) of a replica is cut into tiles of tile_cells consecutive
- * cells along x (the last tile of a row may be shorter); tiles are numbered
- * replica by replica, row by row (row = cz * ny + cy), then along x.  The
- * staged neighbourhood of a tile whose cells are a..b is, for oz = -1, 0, 1
- * and within it oy = -1, 0, 1 (nine rows, wrapped periodically with the
- * image the wrap implies), the cells of unwrapped x = a-1 .. b+1 of that row
- * (x = -1 is cell nx-1 one box length to the left, x = nx is cell 0 one box
- * length to the right), each cell's atoms in index order, concatenated.
- * Entry k of atom i is the uint16 ((uint16_t *)idx)[k * ld + i]: the position
- * of the neighbour in its tile's staged sequence (the neighbour's image is
- * the one its staged row and cell imply).  A tile whose staged sequence
- * exceeds md_tile_capacity() (at most MD_TILE_SLOTS) raises MD_F_TILE_OVERFLOW
- * (the list is then unusable: rebuild with fewer tile_cells).  Tile-local lists take one atom type
+/* Tile-local lists (mode MD_TILE_FULL).  The cells of each replica are cut
+ * into tiles of tile_cells x tile_py x tile_pz cells along x, y, z (tiles at
+ * the high end of a dimension may be smaller), numbered replica by replica,
+ * then z-block, y-block, x-block (x fastest).  For a tile with home cells
+ * x in a..b, y in y0..y1, z in z0..z1, the staged neighbourhood is, for z
+ * from z0-1 to z1+1 and within it y from y0-1 to y1+1 (each wrapped
+ * periodically with the image the wrap implies), the cells of unwrapped
+ * x = a-1 .. b+1 of that row (x = -1 is cell nx-1 one box length to the
+ * left, x = nx is cell 0 one box length to the right), each cell's atoms in
+ * index order, concatenated.  Entry k of atom i is the uint16
+ * ((uint16_t *)idx)[k * ld + i]: the position of the neighbour in its tile's
+ * staged sequence (its image is the one its staged row and cell imply).  A
+ * tile whose staged sequence exceeds md_tile_capacity() (at most
+ * MD_TILE_SLOTS) raises MD_F_TILE_OVERFLOW (the list is then unusable:
+ * rebuild with smaller tiles).  Tile-local lists take one atom type
  * (md_lj_forces returns MD_EUNSUPPORTED otherwise) and have no adjoint. */
 
 /* ------------------------------------------------------------------ structs */
@@ -141,6 +143,8 @@ typedef struct md_nlist {
     uint32_t *idx;            /* [max_nbr * ld] uint32 entries; MD_TILE_FULL uses
                                  the first half as [max_nbr * ld] uint16 entries  */
     int32_t  n_tiles;         /* MD_TILE_FULL: tiles (md_tile_plan)               */
+    int32_t  tile_py;         /* MD_TILE_FULL: cell rows per tile along y, 1..2   */
+    int32_t  tile_pz;         /* MD_TILE_FULL: cell rows per tile along z, 1..2   */
     int32_t  _pad;
     const int32_t *tile_rep;  /* MD_TILE_FULL: [n_tiles] replica of each tile     */
     const int32_t *tile_off;  /* MD_TILE_FULL: [R+1] first tile of each replica   */
@@ -210,11 +214,11 @@ int md_plan_fill(int32_t R, const int32_t *h_natoms, const double *h_box,
                  int32_t *h_unit_rep, int32_t *h_unit_off);
 
 /* Tiles of MD_TILE_FULL lists: with h_tile_rep/h_tile_off NULL returns the
- * number of tiles for tile_cells cells per tile (h_ncell as from
+ * number of tiles of tile_cells x tile_py x tile_pz cells (h_ncell as from
  * md_plan_fill); otherwise also fills h_tile_rep[n_tiles] and
  * h_tile_off[R+1].  Negative MD_E* on bad arguments. */
-int md_tile_plan(int32_t R, const int32_t *h_ncell, int32_t tile_cells, int32_t *h_tile_rep,
-                 int32_t *h_tile_off);
+int md_tile_plan(int32_t R, const int32_t *h_ncell, int32_t tile_cells, int32_t tile_py,
+                 int32_t tile_pz, int32_t *h_tile_rep, int32_t *h_tile_off);
 
 /* Bytes of the device workspace used by the calls below for this batch.
  * The workspace must be zero-filled once after allocation; every call

@@ -30,6 +30,7 @@ MD_FULL = 1
 MD_TILE_FULL = 2
 MD_TILE_SLOTS = 3072
 MD_TILE_MAX_CELLS = 64
+MD_TILE_MAX_ROWS = 2
 MD_FP64 = 0
 MD_FP32_MIXED = 1
 MD_UNIT_ATOMS = 256
@@ -67,7 +68,8 @@ class MdAtoms(ctypes.Structure):
 
 class MdNlist(ctypes.Structure):
     _fields_ = [("mode", _i32), ("max_nbr", _i32), ("ld", _i32), ("tile_cells", _i32),
-                ("count", _vp), ("idx", _vp), ("n_tiles", _i32), ("_pad", _i32),
+                ("count", _vp), ("idx", _vp), ("n_tiles", _i32), ("tile_py", _i32),
+                ("tile_pz", _i32), ("_pad", _i32),
                 ("tile_rep", _vp), ("tile_off", _vp), ("tile_need", _vp), ("cell_start", _vp)]
 
 
@@ -116,7 +118,7 @@ def load():
     lib.md_tile_capacity.restype = ctypes.c_int
     lib.md_tile_capacity.argtypes = []
     lib.md_tile_plan.restype = ctypes.c_int
-    lib.md_tile_plan.argtypes = [_i32, _vp, _i32, _vp, _vp]
+    lib.md_tile_plan.argtypes = [_i32, _vp, _i32, _i32, _i32, _vp, _vp]
     lib.md_workspace_bytes.restype = ctypes.c_size_t
     lib.md_workspace_bytes.argtypes = [P(MdBatch)]
     lib.md_cell_sort.restype = ctypes.c_int

@@ -3,11 +3,12 @@
 //
 // Same method as the global-index path (Sec. 2.1.2 cell stencil and Verlet
 // radius, Eq. lj pair terms); only where neighbour positions come from
-// differs.  One workgroup per tile (a run of cells along x in one row):
-//   1. stage the nine neighbouring rows x (a-1 .. b+1) into LDS, images
-//      applied (md_tile.hpp);
+// differs.  One workgroup per tile (a block of m x py x pz cells):
+//   1. stage the neighbouring rows x (a-1 .. b+1) into LDS, images applied
+//      (md_tile.hpp);
 //   2. build: every home atom tests the staged slots of its own 27-cell
-//      stencil -- nine contiguous slot ranges -- and records hits as 16-bit
+//      stencil -- nine contiguous slot ranges, one per stencil row -- and
+//      records hits as 16-bit
 //      slots; forces: every home atom walks its list, reading neighbours
 //      from LDS, no periodic-image arithmetic and no L2 gathers.
 #include "md_pair.hpp"
@@ -22,7 +23,8 @@ struct TileArgs {
     const uint32_t *gate;
     const double *x, *y, *z, *pos4;
     const int32_t *cell_start;
-    int32_t m, n_tiles, max_nbr, ld;
+    TileGrid g;
+    int32_t n_tiles, max_nbr, ld;
     int32_t *count;
     uint16_t *idx;
     // build
@@ -47,7 +49,7 @@ __global__ __launch_bounds__(TB) void k_tile_build(TileArgs a)
     __shared__ TileStage<CAP, TileShape<TB>::MAXC> st;
     for (int lt = blockIdx.x; lt < a.n_tiles; lt += gridDim.x) {
         const int t = xcd_swizzle(lt, a.n_tiles);
-        const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.m);
+        const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
         if (a.gate != nullptr && a.gate[s.rep] == 0u) continue;
         const int total = stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP);
         if (total > CAP) {
@@ -58,15 +60,19 @@ __global__ __launch_bounds__(TB) void k_tile_build(TileArgs a)
             __syncthreads();
             continue;
         }
-        const int t0 = a.cell_start[s.home_rb + s.a], t1 = a.cell_start[s.home_rb + s.b + 1];
-        for (int i = t0 + threadIdx.x; i < t1; i += TB) {
+        const int nh = st.home_start[s.hy * s.hz];
+        for (int hk = threadIdx.x; hk < nh; hk += TB) {
+            int dy, dz;
+            const int i = home_atom(s, st, hk, dy, dz);
             const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
             const int cx = min(max(cell_coord(xi, s.L[0], s.nx), s.a), s.b);
             const int kc = cx - s.a;   // stage index of unwrapped cell cx - 1
-            const int own = st.row_slot[4] + st.cslot[4][kc + 1] +
-                            (i - a.cell_start[s.home_rb + cx]);
+            const int qc = staged_row(s, dy, dz);
+            const int own = st.row_slot[qc] + st.cslot[qc][kc + 1] +
+                            (i - a.cell_start[st.row_rb[qc] + cx]);
             int cnt = 0;
-            for (int r = 0; r < 9; ++r) {
+            for (int r9 = 0; r9 < 9; ++r9) {
+                const int r = staged_row(s, dy + r9 % 3 - 1, dz + r9 / 3 - 1);
                 const int s0 = st.row_slot[r] + st.cslot[r][kc];
                 const int s1 = st.row_slot[r] + st.cslot[r][kc + 3];
                 for (int sb = s0; sb < s1; sb += kCandBatch) {
@@ -108,7 +114,7 @@ __global__ __launch_bounds__(TB) void k_tile_lj(TileArgs a)
     __shared__ TileStage<CAP, TileShape<TB>::MAXC> st;
     __shared__ double red[TB / kWave];
     const int t = xcd_swizzle(blockIdx.x, gridDim.x);
-    const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.m);
+    const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
     const PairConst pc = pair_const(a.eps[0], a.sig[0], a.rc, a.shift);
     const double rc2 = a.rc * a.rc;
     const int total = stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP);
@@ -116,8 +122,10 @@ __global__ __launch_bounds__(TB) void k_tile_lj(TileArgs a)
     if (total > CAP) {
         if (threadIdx.x == 0 && a.status) atomicOr(a.status, MD_F_TILE_OVERFLOW);
     } else {
-        const int t0 = a.cell_start[s.home_rb + s.a], t1 = a.cell_start[s.home_rb + s.b + 1];
-        for (int i = t0 + threadIdx.x; i < t1; i += TB) {
+        const int nh = st.home_start[s.hy * s.hz];
+        for (int hk = threadIdx.x; hk < nh; hk += TB) {
+            int dy, dz;
+            const int i = home_atom(s, st, hk, dy, dz);
             const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
             const int n = min(a.count[i], a.max_nbr);
             Acc c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
@@ -203,7 +211,7 @@ TileArgs tile_args(const md_batch *b, const md_atoms *atoms, const md_nlist *nl)
     a.y = atoms->y;
     a.z = atoms->z;
     a.pos4 = atoms->pos4;
-    a.m = nl->tile_cells;
+    a.g = TileGrid{nl->tile_cells, nl->tile_py, nl->tile_pz};
     a.n_tiles = nl->n_tiles;
     a.max_nbr = nl->max_nbr;
     a.ld = nl->ld;
@@ -220,7 +228,8 @@ bool tile_stage_packed() { return md_tune_get(MD_TUNE_TILE_STAGE_PACKED) != 0; }
 bool tile_list_ok(const md_batch *b, const md_nlist *nl)
 {
     return nl->n_tiles >= 1 && nl->n_tiles <= b->C && nl->tile_rep && nl->tile_off &&
-           nl->tile_cells >= 1 && nl->tile_cells <= kTileCells;
+           nl->tile_cells >= 1 && nl->tile_cells <= kTileCells && nl->tile_py >= 1 &&
+           nl->tile_py <= MD_TILE_MAX_ROWS && nl->tile_pz >= 1 && nl->tile_pz <= MD_TILE_MAX_ROWS;
 }
 
 int tile_threads() { return md_tune_get(MD_TUNE_TILE_THREADS); }

@@ -1,12 +1,13 @@
 // md_tile.hpp -- tile geometry and LDS staging shared by the tile-local list
 // build and the tile-local force kernel (MD_TILE_FULL).
 //
-// A tile is a run of consecutive cells a..b along x in one row of cells.
-// Every pair partner of its atoms lies in the 27-cell stencil of some home
-// cell, i.e. in nine rows x (unwrapped x = a-1 .. b+1).  That region is
-// staged into LDS once per workgroup with each cell's periodic image already
-// applied, so neighbour positions come from LDS instead of L2 gathers and
-// the list can name neighbours by a 16-bit staged slot.
+// A tile is a block of cells: x in a..b (at most m cells), y in y0..y1 and
+// z in z0..z1 (at most py and pz rows).  Every pair partner of its atoms lies
+// in the 27-cell stencil of some home cell, i.e. in the staged rows
+// (y0-1..y1+1) x (z0-1..z1+1), each over unwrapped x = a-1 .. b+1.  That
+// region is staged into LDS once per workgroup with each cell's periodic
+// image already applied, so neighbour positions come from LDS instead of L2
+// gathers and the list names neighbours by a 16-bit staged slot.
 #pragma once
 
 #include "md_common.hpp"
@@ -14,6 +15,8 @@
 namespace md {
 
 constexpr int kTileCells = MD_TILE_MAX_CELLS;
+constexpr int kMaxHomeRows = MD_TILE_MAX_ROWS * MD_TILE_MAX_ROWS;             // py pz
+constexpr int kMaxStagedRows = (MD_TILE_MAX_ROWS + 2) * (MD_TILE_MAX_ROWS + 2);
 
 // Workgroup shapes of the tile kernels: TB threads (at most TB home atoms per
 // pass), CAP staged slots (3 x 8 CAP bytes of LDS), MAXC cells per tile.
@@ -52,16 +55,21 @@ __device__ __forceinline__ double block_sum_t(double v, double *lds)
 struct TileSpec {
     int rep, nx, ny, nz, coff;
     int a, b;        // home cells along x
-    int cy, cz;      // home row
-    int home_rb;     // linear index of cell (0, cy, cz)
+    int y0, hy;      // home rows y0 .. y0 + hy - 1
+    int z0, hz;      // home layers z0 .. z0 + hz - 1
+    int nrows;       // staged rows (hy + 2)(hz + 2)
     double L[3];
+};
+
+struct TileGrid {
+    int m, py, pz;
 };
 
 __device__ __forceinline__ TileSpec tile_spec(int t, const int32_t *__restrict__ tile_rep,
                                               const int32_t *__restrict__ tile_off,
                                               const int32_t *__restrict__ ncell,
                                               const int32_t *__restrict__ cell_off,
-                                              const double *__restrict__ box, int m)
+                                              const double *__restrict__ box, TileGrid g)
 {
     TileSpec s;
     s.rep = tile_rep[t];
@@ -70,13 +78,16 @@ __device__ __forceinline__ TileSpec tile_spec(int t, const int32_t *__restrict__
     s.nz = ncell[3 * s.rep + 2];
     s.coff = cell_off[s.rep];
     const int local = t - tile_off[s.rep];
-    const int tpr = (s.nx + m - 1) / m;
-    const int row = local / tpr, chunk = local % tpr;
-    s.a = chunk * m;
-    s.b = min(s.a + m, s.nx) - 1;
-    s.cy = row % s.ny;
-    s.cz = row / s.ny;
-    s.home_rb = s.coff + row * s.nx;
+    const int tx = (s.nx + g.m - 1) / g.m, ty = (s.ny + g.py - 1) / g.py;
+    const int bx = local % tx, rest = local / tx;
+    const int by = rest % ty, bz = rest / ty;
+    s.a = bx * g.m;
+    s.b = min(s.a + g.m, s.nx) - 1;
+    s.y0 = by * g.py;
+    s.hy = min(s.y0 + g.py, s.ny) - s.y0;
+    s.z0 = bz * g.pz;
+    s.hz = min(s.z0 + g.pz, s.nz) - s.z0;
+    s.nrows = (s.hy + 2) * (s.hz + 2);
     s.L[0] = box[3 * s.rep];
     s.L[1] = box[3 * s.rep + 1];
     s.L[2] = box[3 * s.rep + 2];
@@ -88,16 +99,24 @@ template <int CAP, int MAXC>
 struct TileStage {
     static constexpr int kRowStage = MAXC + 3;   // cell starts a-1 .. b+2 of one staged row
     double x[CAP], y[CAP], z[CAP];
-    int row_slot[10];           // first slot of staged row r; [9] = total staged
-    int row_rb[9];              // linear index of cell (0, y, z) of staged row r
-    int row_lo[9];              // first physical cell of the row's main piece
-    int row_lw[9];              // atoms in the left wrap piece (cell nx-1 at x = -1)
-    int row_main[9];            // atoms in the main piece
-    int row_rw[9];              // atoms in the right wrap piece (cell 0 at x = nx)
-    int row_g0[9][3];           // first atom index of the three pieces
-    double row_dy[9], row_dz[9];  // position shift of the row's image
-    int cslot[9][kRowStage];    // slot (within the row) where unwrapped cell a-1+k starts
+    int row_slot[kMaxStagedRows + 1];  // first slot of staged row q; [nrows] = total
+    int row_rb[kMaxStagedRows];        // linear index of cell (0, y, z) of staged row q
+    int row_lo[kMaxStagedRows];        // first physical cell of the row's main piece
+    int row_lw[kMaxStagedRows];        // atoms in the left wrap piece (cell nx-1 at x = -1)
+    int row_main[kMaxStagedRows];      // atoms in the main piece
+    int row_rw[kMaxStagedRows];        // atoms in the right wrap piece (cell 0 at x = nx)
+    int row_g0[kMaxStagedRows][3];     // first atom index of the three pieces
+    double row_dy[kMaxStagedRows], row_dz[kMaxStagedRows];  // shift of the row's image
+    int cslot[kMaxStagedRows][kRowStage];  // start (within the row) of unwrapped cell a-1+k
+    int home_start[kMaxHomeRows + 1];  // prefix of home atoms over the home rows
+    int home_g0[kMaxHomeRows];         // first atom of each home row's run a..b
 };
+
+// Staged row of home row offsets (dy, dz) moved by (oy, oz) in -1..1.
+__device__ __forceinline__ int staged_row(const TileSpec &s, int dy, int dz)
+{
+    return (dz + 1) * (s.hy + 2) + (dy + 1);
+}
 
 // Fills the staging tables and stages positions (x, y, z planes or the
 // packed copy).  All TB threads of the workgroup must call it.  Returns the
@@ -109,21 +128,22 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
                           Stage &st, int cap)
 {
     const int tid = threadIdx.x;
-    __syncthreads();   // the previous tile's readers are done with st
-    if (tid < 9) {
-        const int oz = tid / 3 - 1, oy = tid % 3 - 1;
-        int az = s.cz + oz, ay = s.cy + oy;
+    const int nhome = s.hy * s.hz;
+    __syncthreads();   // readers of the previous tile are done with st
+    if (tid < s.nrows) {
+        const int zr = tid / (s.hy + 2), yr = tid % (s.hy + 2);
+        int az = s.z0 - 1 + zr, ay = s.y0 - 1 + yr;
         double dz = 0.0, dy = 0.0;
         // a row reached across a face holds atoms one box length away
         if (az < 0) { az += s.nz; dz = -s.L[2]; } else if (az >= s.nz) { az -= s.nz; dz = s.L[2]; }
         if (ay < 0) { ay += s.ny; dy = -s.L[1]; } else if (ay >= s.ny) { ay -= s.ny; dy = s.L[1]; }
         const int rb = s.coff + (az * s.ny + ay) * s.nx;
         const int lo = max(s.a - 1, 0), hi = min(s.b + 1, s.nx - 1);
-        st.row_rb[tid] = rb;
-        st.row_lo[tid] = lo;
         const int c_last = cs[rb + s.nx - 1], c_end = cs[rb + s.nx];
         const int c_first = cs[rb], c_second = cs[rb + 1];
         const int m0 = cs[rb + lo], m1 = cs[rb + hi + 1];
+        st.row_rb[tid] = rb;
+        st.row_lo[tid] = lo;
         st.row_lw[tid] = s.a - 1 < 0 ? c_end - c_last : 0;
         st.row_main[tid] = m1 - m0;
         st.row_rw[tid] = s.b + 1 >= s.nx ? c_second - c_first : 0;
@@ -132,19 +152,30 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
         st.row_g0[tid][2] = c_first;
         st.row_dy[tid] = dy;
         st.row_dz[tid] = dz;
+    } else if (tid >= kMaxStagedRows && tid < kMaxStagedRows + nhome) {
+        const int h = tid - kMaxStagedRows;
+        const int rb = s.coff + ((s.z0 + h / s.hy) * s.ny + (s.y0 + h % s.hy)) * s.nx;
+        const int g0 = cs[rb + s.a];
+        st.home_g0[h] = g0;
+        st.home_start[h + 1] = cs[rb + s.b + 1] - g0;   // count, summed below
     }
     __syncthreads();
     if (tid == 0) {
         int acc = 0;
-        for (int r = 0; r < 9; ++r) {
-            st.row_slot[r] = acc;
-            acc += st.row_lw[r] + st.row_main[r] + st.row_rw[r];
+        for (int q = 0; q < s.nrows; ++q) {
+            st.row_slot[q] = acc;
+            acc += st.row_lw[q] + st.row_main[q] + st.row_rw[q];
         }
-        st.row_slot[9] = acc;
+        st.row_slot[s.nrows] = acc;
+        int hacc = 0;
+        st.home_start[0] = 0;
+        for (int h = 0; h < nhome; ++h) {
+            hacc += st.home_start[h + 1];
+            st.home_start[h + 1] = hacc;
+        }
     }
-    // start (within the row) of unwrapped cell xu = a-1+k, k = 0 .. b-a+3
     const int nk = s.b - s.a + 4;
-    for (int q = tid; q < 9 * nk; q += TB) {
+    for (int q = tid; q < s.nrows * nk; q += TB) {
         const int r = q / nk, k = q % nk, xu = s.a - 1 + k;
         const int lw = st.row_lw[r], mn = st.row_main[r];
         int off;
@@ -155,11 +186,10 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
         st.cslot[r][k] = off;
     }
     __syncthreads();
-    const int total = st.row_slot[9];
+    const int total = st.row_slot[s.nrows];
     if (total > cap) return total;
-    // Slots tid, tid + B, ... (B = workgroup size): locate each slot's row and
-    // piece, issue every load, then write LDS -- all loads of a thread are in
-    // flight together.
+    // Slots tid, tid + TB, ...: locate each slot's row and piece, issue every
+    // load, then write LDS -- all loads of a thread are in flight together.
     constexpr int kPer = (int(sizeof(decltype(st.x)) / sizeof(double)) + TB - 1) / TB;
     double px[kPer], py[kPer], pz[kPer];
 #pragma unroll
@@ -168,7 +198,8 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
         if (sl < total) {
             int r = 0;
 #pragma unroll
-            for (int q = 1; q < 9; ++q) r += sl >= st.row_slot[q] ? 1 : 0;
+            for (int q = 1; q < kMaxStagedRows; ++q)
+                r += (q < s.nrows && sl >= st.row_slot[q]) ? 1 : 0;
             const int off = sl - st.row_slot[r];
             const int lw = st.row_lw[r], mn = st.row_main[r];
             const int piece = off < lw ? 0 : (off < lw + mn ? 1 : 2);
@@ -197,6 +228,20 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
     }
     __syncthreads();
     return total;
+}
+
+// Home atom number k of the tile (0 .. home_start[hy hz]): its index and home
+// row offsets (dy, dz) relative to (y0, z0).
+template <class Stage>
+__device__ __forceinline__ int home_atom(const TileSpec &s, const Stage &st, int k, int &dy,
+                                         int &dz)
+{
+    const int nhome = s.hy * s.hz;
+    int h = 0;
+    for (int q = 1; q < nhome; ++q) h += k >= st.home_start[q] ? 1 : 0;
+    dy = h % s.hy;
+    dz = h / s.hy;
+    return st.home_g0[h] + (k - st.home_start[h]);
 }
 
 }  // namespace md

@@ -39,7 +39,7 @@ class MDSystem:
     def __init__(self, natoms, box, pos, vel, types=None, eps=1.0, sig=1.0, mass=None,
                  rc=2.5, skin=0.3, dt=0.005, shift=1, mode="full", prec="fp64",
                  max_nbr=None, pos4=True, bonds=None, fene=(30.0, 1.5), langevin=None,
-                 tile_cells=None, device="cuda"):
+                 tile_cells=None, tile_rows=(1, 1), device="cuda"):
         self.lib = abi.load()
         self.dev = torch.device(device)
         natoms = np.asarray(natoms, dtype=np.int32).ravel()
@@ -116,6 +116,7 @@ class MDSystem:
         self.ld = (self.N + 63) // 64 * 64
         self.tile_need = torch.zeros(1, dtype=torch.int32, device=d)
         self.tile_cells, self.n_tiles = 0, 0
+        self.tile_py, self.tile_pz = (int(tile_rows[0]), int(tile_rows[1]))
         if self.mode == abi.MD_TILE_FULL:
             if tile_cells is None:
                 # cells per tile: staged neighbourhood 9 (m + 2) nu within 92% of
@@ -125,7 +126,9 @@ class MDSystem:
                 nu = float(np.max(natoms / np.prod(self.h_ncell, axis=1)))
                 cap = self.lib.md_tile_capacity()
                 tb = self.lib.md_tune_get(abi.MD_TUNE_TILE_THREADS)
-                m = int(min(0.92 * cap / (9 * nu) - 2, 1.02 * tb / nu))
+                py, pz = self.tile_py, self.tile_pz
+                m = int(min(0.92 * cap / ((py + 2) * (pz + 2) * nu) - 2,
+                            1.02 * tb / (py * pz * nu)))
                 m = max(1, min(m, abi.MD_TILE_MAX_CELLS, int(self.h_ncell[:, 0].max())))
                 nx = int(self.h_ncell[:, 0].max())
                 m = -(-nx // -(-nx // m))
@@ -188,12 +191,13 @@ class MDSystem:
 
     def _plan_tiles(self, m):
         ncell = np.ascontiguousarray(self.h_ncell.ravel(), dtype=np.int32)
-        n = self.lib.md_tile_plan(self.R, ncell.ctypes.data, m, None, None)
+        py, pz = self.tile_py, self.tile_pz
+        n = self.lib.md_tile_plan(self.R, ncell.ctypes.data, m, py, pz, None, None)
         if n < 1:
             raise abi.MDError("md_tile_plan", n)
         rep = np.zeros(n, np.int32)
         off = np.zeros(self.R + 1, np.int32)
-        check("md_tile_plan", min(0, self.lib.md_tile_plan(self.R, ncell.ctypes.data, m,
+        check("md_tile_plan", min(0, self.lib.md_tile_plan(self.R, ncell.ctypes.data, m, py, pz,
                                                            rep.ctypes.data, off.ctypes.data)))
         self.tile_cells, self.n_tiles = m, n
         self.tile_rep = torch.as_tensor(rep).to(self.dev)
@@ -209,8 +213,8 @@ class MDSystem:
         tiled = self.mode == abi.MD_TILE_FULL
         self.nlist = abi.MdNlist(
             self.mode, self.max_nbr, self.ld, self.tile_cells if tiled else 0,
-            self.count.data_ptr(), self.idx.data_ptr(), self.n_tiles if tiled else 0, 0,
-            self.tile_rep.data_ptr() if tiled else None,
+            self.count.data_ptr(), self.idx.data_ptr(), self.n_tiles if tiled else 0,
+            self.tile_py, self.tile_pz, 0, self.tile_rep.data_ptr() if tiled else None,
             self.tile_off.data_ptr() if tiled else None,
             self.tile_need.data_ptr(), self.cell_start.data_ptr() if tiled else None)
 
@@ -377,33 +381,37 @@ class MDSystem:
         return self._by_id(self.fx, self.fy, self.fz)
 
     def tile_slot_table(self):
-        """For MD_TILE_FULL lists: per tile, the global index of every staged
-        slot, following the staged order documented in md.h."""
+        """For MD_TILE_FULL lists: per tile, the global indices of its home
+        atoms and of every staged slot, in the staged order documented in md.h."""
         cs = self.cell_start.cpu().numpy()
         rep = self.tile_rep.cpu().numpy()
         toff = self.tile_off.cpu().numpy()
         coff = np.concatenate([[0], np.cumsum(np.prod(self.h_ncell, axis=1))])
-        m = self.tile_cells
+        m, py, pz = self.tile_cells, self.tile_py, self.tile_pz
         tables = []
         for t in range(self.n_tiles):
             r = rep[t]
             nx, ny, nz = self.h_ncell[r]
-            tpr = -(-nx // m)
+            tx, ty = -(-nx // m), -(-ny // py)
             local = t - toff[r]
-            row, chunk = divmod(local, tpr)
-            a = chunk * m
-            b = min(a + m, nx) - 1
-            cy, cz = row % ny, row // ny
+            bx, rest = local % tx, local // tx
+            by, bz = rest % ty, rest // ty
+            a, b = bx * m, min(bx * m + m, nx) - 1
+            y0, y1 = by * py, min(by * py + py, ny) - 1
+            z0, z1 = bz * pz, min(bz * pz + pz, nz) - 1
             slots = []
-            for oz in (-1, 0, 1):
-                for oy in (-1, 0, 1):
-                    rb = coff[r] + (((cz + oz) % nz) * ny + (cy + oy) % ny) * nx
+            for zz in range(z0 - 1, z1 + 2):
+                for yy in range(y0 - 1, y1 + 2):
+                    rb = coff[r] + ((zz % nz) * ny + yy % ny) * nx
                     for xu in range(a - 1, b + 2):
                         c = rb + xu % nx
                         slots.extend(range(cs[c], cs[c + 1]))
-            t0 = cs[coff[r] + row * nx + a]
-            t1 = cs[coff[r] + row * nx + b + 1]
-            tables.append((t0, t1, np.array(slots, dtype=np.int64)))
+            home = []
+            for zz in range(z0, z1 + 1):
+                for yy in range(y0, y1 + 1):
+                    rb = coff[r] + (zz * ny + yy) * nx
+                    home.extend(range(cs[rb + a], cs[rb + b + 1]))
+            tables.append((np.array(home, dtype=np.int64), np.array(slots, dtype=np.int64)))
         return tables
 
     def list_pairs(self):
@@ -415,8 +423,8 @@ class MDSystem:
             idx = idx.reshape(self.max_nbr, self.ld)
             ids = self.id.cpu().numpy()
             out = []
-            for t0, t1, slots in self.tile_slot_table():
-                for i in range(t0, t1):
+            for home, slots in self.tile_slot_table():
+                for i in home:
                     n = min(cnt[i], self.max_nbr)
                     js = slots[idx[:n, i].astype(np.int64)]
                     out.append(np.stack([np.full(n, ids[i]), ids[js]], 1))

@@ -43,14 +43,17 @@ def test_header_constants_match_binding():
 def test_tile_plan():
     lib = abi.load()
     ncell = np.array([38, 38, 38, 2, 3, 5], np.int32)
-    n = lib.md_tile_plan(2, ncell.ctypes.data, 10, None, None)
+    n = lib.md_tile_plan(2, ncell.ctypes.data, 10, 1, 1, None, None)
     assert n == 38 * 38 * 4 + 3 * 5 * 1
     rep = np.zeros(n, np.int32)
     off = np.zeros(3, np.int32)
-    assert lib.md_tile_plan(2, ncell.ctypes.data, 10, rep.ctypes.data, off.ctypes.data) == n
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 10, 1, 1, rep.ctypes.data, off.ctypes.data) == n
     assert list(off) == [0, 5776, 5791] and rep[5775] == 0 and rep[5776] == 1
-    assert lib.md_tile_plan(2, ncell.ctypes.data, 0, None, None) == abi.MD_EINVAL
-    assert lib.md_tile_plan(2, ncell.ctypes.data, 65, None, None) == abi.MD_EINVAL
+    # 2 x 2 rows per tile: 19 x 19 row blocks; odd counts leave a short block
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 3, 2, 2, None, None) == 13 * 19 * 19 + 1 * 2 * 3
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 0, 1, 1, None, None) == abi.MD_EINVAL
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 65, 1, 1, None, None) == abi.MD_EINVAL
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 4, 3, 1, None, None) == abi.MD_EINVAL
 
 
 def test_tuning_knobs():
@@ -135,13 +138,13 @@ def test_calls_reject_bad_arguments_without_a_gpu():
     # on bad modes and on a short workspace, before anything is launched
     ok = abi.MdBatch(1, 1000, 27, 4, 8, 8, 8, 8, 8, 8)
     assert lib.md_workspace_bytes(P(ok)) > 0
-    nl = abi.MdNlist(7, 64, 1024, 0, 8, 8, 0, 0, None, None, None, None)
+    nl = abi.MdNlist(7, 64, 1024, 0, 8, 8, 0, 1, 1, 0, None, None, None, None)
     assert lib.md_verlet_build(P(ok), P(atoms), 8, 2.5, 0.3, P(nl), None, None, None, None) == abi.MD_EINVAL
     full = abi.MdAtoms(*([8] * 17))
-    nl = abi.MdNlist(abi.MD_HALF, 64, 1000, 0, 8, 8, 0, 0, None, None, None, None)   # ld % 64
+    nl = abi.MdNlist(abi.MD_HALF, 64, 1000, 0, 8, 8, 0, 1, 1, 0, None, None, None, None)   # ld % 64
     lj1 = abi.MdLj(1, 1, 2.5, 8, 8)
     assert lib.md_lj_forces(P(ok), P(full), P(nl), P(lj1), 0, 0, None, None, 8, 1 << 30, None, None) == abi.MD_EINVAL
-    nl = abi.MdNlist(abi.MD_HALF, 64, 1024, 0, 8, 8, 0, 0, None, None, None, None)
+    nl = abi.MdNlist(abi.MD_HALF, 64, 1024, 0, 8, 8, 0, 1, 1, 0, None, None, None, None)
     assert lib.md_lj_forces(P(ok), P(full), P(nl), P(lj1), 5, 0, None, None, 8, 1 << 30, None, None) == abi.MD_EINVAL
     assert lib.md_lj_forces(P(ok), P(full), P(nl), P(lj1), 0, 0, None, None, 8, 16, None, None) == abi.MD_ENOWS
     assert lib.md_lj_forces_vjp(P(ok), P(full), P(nl), P(lj1), 0, 8, 8, 8, None, 8, None, None,

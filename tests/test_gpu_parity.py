@@ -42,11 +42,12 @@ def c1_snapshot():
     return md_inputs.lj_fluid(10, temperature=0.72, seed=1, jitter_amp=0.1)
 
 
-@pytest.mark.parametrize("mode", ["full", "half", "tile"])
-def test_forces_fp64_match_oracle(c1_snapshot, mode):
+@pytest.mark.parametrize("mode,rows", [("full", None), ("half", None), ("tile", (1, 1)),
+                                       ("tile", (2, 1)), ("tile", (2, 2))])
+def test_forces_fp64_match_oracle(c1_snapshot, mode, rows):
     cfg = c1_snapshot
-    say(f"case: forces fp64 {mode} N={cfg.n}")
-    s = _system(cfg, mode=mode, prec="fp64")
+    say(f"case: forces fp64 {mode} {rows} N={cfg.n}")
+    s = _system(cfg, mode=mode, prec="fp64", **({"tile_rows": rows} if rows else {}))
     s.setup()
     assert s.ensure_list() == 0
     f = s.forces_np()
@@ -115,11 +116,12 @@ def _unordered(pairs):
     return set(map(tuple, np.unique(p, axis=0)))
 
 
-@pytest.mark.parametrize("mode", ["full", "half", "tile"])
-def test_verlet_list_is_the_skin_pair_set(c1_snapshot, mode):
+@pytest.mark.parametrize("mode,rows", [("full", None), ("half", None), ("tile", (1, 1)),
+                                       ("tile", (2, 2))])
+def test_verlet_list_is_the_skin_pair_set(c1_snapshot, mode, rows):
     cfg = c1_snapshot
-    say(f"case: list set {mode}")
-    s = _system(cfg, mode=mode)
+    say(f"case: list set {mode} {rows}")
+    s = _system(cfg, mode=mode, **({"tile_rows": rows} if rows else {}))
     s.setup()
     pairs, codes = s.list_pairs()
     # each unordered pair exactly twice (full) or once (half)
@@ -153,12 +155,12 @@ def test_fcc_lattice_exact_counts():
         assert np.abs(s.forces_np()).max() < 1e-10
 
 
-@pytest.mark.parametrize("mode", ["full", "tile"])
-def test_trajectory_matches_oracle_100_steps(mode):
+@pytest.mark.parametrize("mode,rows", [("full", None), ("tile", (1, 1)), ("tile", (2, 2))])
+def test_trajectory_matches_oracle_100_steps(mode, rows):
     # the 4000-atom parity workload: T = 0.72, 100 NVE steps, FP64
     cfg = md_inputs.lj_fluid(10, temperature=0.72, seed=1)
-    say(f"case: trajectory 100 steps fp64 {mode}")
-    s = _system(cfg, mode=mode, prec="fp64")
+    say(f"case: trajectory 100 steps fp64 {mode} {rows}")
+    s = _system(cfg, mode=mode, prec="fp64", **({"tile_rows": rows} if rows else {}))
     s.setup()
     flags, ek, ep = [], [], []
     for t in range(cfg.steps):
@@ -322,14 +324,15 @@ def test_vjp_matches_oracle(prec):
     np.testing.assert_allclose(gsig.cpu().numpy().reshape(2, 2), gs_ref, rtol=tol * 10)
 
 
-@pytest.mark.parametrize("prec,mode", [("mixed", "full"), ("fp64", "full"),
-                                       ("mixed", "tile"), ("fp64", "tile")])
-def test_full_size_sampled_forces(prec, mode):
+@pytest.mark.parametrize("prec,mode,rows", [("mixed", "full", None), ("fp64", "full", None),
+                                            ("mixed", "tile", (1, 1)), ("fp64", "tile", (2, 2)),
+                                            ("mixed", "tile", (2, 1))])
+def test_full_size_sampled_forces(prec, mode, rows):
     # the 1,048,576-atom workload, in the configuration the benchmark times,
     # jittered so forces are non-zero; 48 sampled atoms by O(N) oracle loops
     cfg = md_inputs.lj_fluid(64, temperature=1.0, seed=2, jitter_amp=0.1)
-    say(f"case: 1M sampled {prec} {mode}")
-    s = _system(cfg, mode=mode, prec=prec)
+    say(f"case: 1M sampled {prec} {mode} {rows}")
+    s = _system(cfg, mode=mode, prec=prec, **({"tile_rows": rows} if rows else {}))
     s.setup()
     s.ensure_list()
     f = s.forces_np()
@@ -346,13 +349,14 @@ def test_full_size_sampled_forces(prec, mode):
     assert cnt.min() > 40 and cnt.max() < s.max_nbr
 
 
-@pytest.mark.parametrize("m", [1, 2, 3])
-def test_tile_lists_in_two_cell_boxes(m):
+@pytest.mark.parametrize("m,rows", [(1, (1, 1)), (2, (1, 1)), (3, (1, 1)), (1, (2, 2)),
+                                    (2, (2, 1)), (3, (1, 2))])
+def test_tile_lists_in_two_cell_boxes(m, rows):
     # 256 atoms in a 6.72 box: two cells per dimension, so every staged row
     # wraps on both sides and holds cells twice under different images
     cfg = md_inputs.lj_fluid(4, temperature=1.0, seed=17, jitter_amp=0.1)
-    say(f"case: tile two-cell box m={m}")
-    s = _system(cfg, mode="tile", tile_cells=m)
+    say(f"case: tile two-cell box m={m} rows={rows}")
+    s = _system(cfg, mode="tile", tile_cells=m, tile_rows=rows)
     s.setup()
     assert s.ensure_list() == 0
     ref, e, w = oracle.lj_forces(cfg.pos, cfg.box[0], RC, shift=1)
