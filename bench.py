@@ -197,6 +197,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--mode", default="auto", choices=["auto", "full", "half", "tile"],
                     help="list form; auto = chosen by the autotuner (untimed)")
+    ap.add_argument("--tile-cells", type=int, default=None,
+                    help="tile lists: cells per tile along x (default: largest that fits)")
+    ap.add_argument("--tile-rows", type=int, nargs=2, default=[2, 2], metavar=("PY", "PZ"),
+                    help="tile lists: rows per tile along y and z")
+    ap.add_argument("--tile-threads", type=int, default=256, choices=[64, 128, 256])
+    ap.add_argument("--tile-slots", type=int, default=2048, choices=[0, 1536, 2048, 3072],
+                    help="tile lists: staged capacity of the 256-thread shape")
+    ap.add_argument("--batch", type=int, default=4, choices=[1, 2, 4, 8],
+                    help="neighbour gathers issued together")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the melt / slab / replica-batch throughput lines")
@@ -230,8 +239,9 @@ def main():
         key = autotune.signature(cfg.natoms, cfg.box, cfg.rc, cfg.skin, 1)
         tuned, _ = autotune.tune(make, key, steps=40, warmup=10, cache=None, log=log)
     else:
-        tuned = {"mode": args.mode, "batch": 4, "tile_threads": 256, "tile_cells": None,
-                 "tile_rows": [2, 2]}
+        tuned = {"mode": args.mode, "batch": args.batch, "tile_threads": args.tile_threads,
+                 "tile_slots": args.tile_slots, "tile_cells": args.tile_cells,
+                 "tile_rows": list(args.tile_rows)}
     log(f"configuration: {json.dumps(tuned)}")
     out, snaps = {}, {}
     for prec in ("mixed", "fp64"):

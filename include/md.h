@@ -138,7 +138,7 @@ typedef struct md_nlist {
     int32_t  mode;            /* MD_HALF, MD_FULL or MD_TILE_FULL                 */
     int32_t  max_nbr;         /* capacity per atom (columns)                      */
     int32_t  ld;              /* leading dimension, >= N and a multiple of 64     */
-    int32_t  tile_cells;      /* MD_TILE_FULL: cells per tile, 1..MD_TILE_MAX_CELLS */
+    int32_t  tile_cells;      /* MD_TILE_FULL: cells per tile, 1..md_tile_max_cells() */
     int32_t  *count;          /* [N] true entry count (may exceed max_nbr)        */
     uint32_t *idx;            /* [max_nbr * ld] uint32 entries; MD_TILE_FULL uses
                                  the first half as [max_nbr * ld] uint16 entries  */
@@ -191,13 +191,22 @@ const char *md_strerror(int code);
                                   before a rebuild of MD_TILE_FULL lists.        */
 #define MD_TUNE_TILE_STAGE_PACKED 2 /* 1: tile staging reads the packed copy when
                                   present; 0 (default): the x, y, z planes      */
-#define MD_TUNE_NKNOBS     3
+#define MD_TUNE_TILE_SLOTS 3   /* staged capacity of the 256-thread tile shape:
+                                  0 (default) or 3072 (up to 64 cells per tile),
+                                  2048 (16 cells) or 1536 (8 cells).  Less LDS
+                                  per workgroup lets more of them share a CU.
+                                  Change it only before a rebuild of
+                                  MD_TILE_FULL lists.                           */
+#define MD_TUNE_NKNOBS     4
 int md_tune_set(int32_t knob, int32_t value);
 int md_tune_get(int32_t knob);
 /* Staged-atom capacity per tile of MD_TILE_FULL lists for the current
- * MD_TUNE_TILE_THREADS (a tile whose staged sequence is larger raises
- * MD_F_TILE_OVERFLOW). */
+ * MD_TUNE_TILE_THREADS and MD_TUNE_TILE_SLOTS (a tile whose staged sequence
+ * is larger raises MD_F_TILE_OVERFLOW). */
 int md_tile_capacity(void);
+/* Largest tile_cells the current tile shape accepts (a list with more makes
+ * md_verlet_build and md_lj_forces return MD_EINVAL). */
+int md_tile_max_cells(void);
 
 /* Host-only planning (no GPU work).  Cells per dimension n_d = floor(L_d /
  * (rc + skin)) so that the cell edge is at least rc + skin (Sec. 2.1.2).

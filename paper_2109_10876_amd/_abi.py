@@ -42,9 +42,10 @@ MD_MAX_BONDS = 4
 MD_TUNE_PAIR_BATCH = 0
 MD_TUNE_TILE_THREADS = 1
 MD_TUNE_TILE_STAGE_PACKED = 2
+MD_TUNE_TILE_SLOTS = 3
 
 EXPORTS = (
-    "md_abi_version", "md_strerror", "md_tune_set", "md_tune_get", "md_tile_capacity", "md_plan_sizes", "md_plan_fill",
+    "md_abi_version", "md_strerror", "md_tune_set", "md_tune_get", "md_tile_capacity", "md_tile_max_cells", "md_plan_sizes", "md_plan_fill",
     "md_tile_plan",
     "md_workspace_bytes", "md_cell_sort", "md_verlet_build", "md_lj_forces",
     "md_vv_step", "md_lj_forces_vjp", "md_fene_forces", "md_langevin",
@@ -117,6 +118,8 @@ def load():
     lib.md_plan_fill.argtypes = [_i32, _vp, _vp, _dbl, _dbl, _vp, _vp, _vp, _vp, _vp]
     lib.md_tile_capacity.restype = ctypes.c_int
     lib.md_tile_capacity.argtypes = []
+    lib.md_tile_max_cells.restype = ctypes.c_int
+    lib.md_tile_max_cells.argtypes = []
     lib.md_tile_plan.restype = ctypes.c_int
     lib.md_tile_plan.argtypes = [_i32, _vp, _i32, _i32, _i32, _vp, _vp]
     lib.md_workspace_bytes.restype = ctypes.c_size_t

@@ -6,7 +6,8 @@ dropping (Sec. 3.3).  The GPU counterpart here tunes, per workload, by
 timing a short graphed run of the real step for each candidate:
 
   * list form: global-index full list or tile-local full list;
-  * tile-local lists: workgroup size (MD_TUNE_TILE_THREADS), rows per tile
+  * tile-local lists: workgroup size (MD_TUNE_TILE_THREADS), staged
+    capacity (MD_TUNE_TILE_SLOTS: less LDS, more workgroups per CU), rows per tile
     (1 x 1, 2 x 1 or 2 x 2 in y x z) and cells per tile along x, the last
     swept the paper's way -- from the fewest (largest) tiles that fit, make
     tiles smaller (more of them) while the time keeps dropping;
@@ -50,6 +51,7 @@ def signature(natoms, box, rc, skin, ntypes):
 def _apply(lib, cand):
     lib.md_tune_set(abi.MD_TUNE_PAIR_BATCH, int(cand.get("batch", 4)))
     lib.md_tune_set(abi.MD_TUNE_TILE_THREADS, int(cand.get("tile_threads", 256)))
+    lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, int(cand.get("tile_slots", 0)))
 
 
 def _time(make, cand, steps, warmup):
@@ -104,10 +106,12 @@ def tune(make, key, steps=40, warmup=10, cache=DEFAULT_CACHE, retune=False, log=
 
     for batch in (2, 4, 8):
         run({"mode": "full", "batch": batch})
-    for tb, rows in ((256, [1, 1]), (256, [2, 1]), (256, [2, 2]), (128, [2, 2])):
+    for tb, slots, rows in ((256, 0, [1, 1]), (256, 0, [2, 2]), (256, 2048, [2, 1]),
+                            (256, 2048, [2, 2]), (256, 1536, [2, 2]), (128, 0, [2, 2])):
         # cells per tile: the largest that fits (automatic), then smaller ones
         # while that helps; mirrors the paper's grow-until-no-gain sweep
-        base = {"mode": "tile", "batch": 4, "tile_threads": tb, "tile_rows": rows}
+        base = {"mode": "tile", "batch": 4, "tile_threads": tb, "tile_slots": slots,
+                "tile_rows": rows}
         best_ms = run(dict(base, tile_cells=None))
         m = trials[-1][0]["tile_cells"]
         while m and m > 2:

@@ -174,6 +174,7 @@ __device__ __forceinline__ double block_max(double v, double *lds)
 
 // Tile-local lists (md_tile.hip).
 int tile_capacity();
+int tile_max_cells();
 bool tile_stage_packed();
 bool tile_list_ok(const md_batch *b, const md_nlist *nl);
 int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_start, double rl2,

@@ -69,4 +69,39 @@ __device__ __forceinline__ double lj_pair_accumulate(const PairConst &pc, double
     return fr;
 }
 
+// Same terms as lj_pair_accumulate, evaluated for every entry and masked
+// with a select instead of a branch (for loops where most entries of a
+// wavefront fall inside the cutoff anyway).  A masked entry adds exact
+// zeros; its arithmetic may overflow (r2 = 0) but is never selected.
+template <int PREC>
+__device__ __forceinline__ void lj_pair_accumulate_masked(const PairConst &pc, double dx,
+                                                          double dy, double dz, double rc2,
+                                                          Acc &c)
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const bool in = r2 < rc2;
+    double fr;
+    if (PREC == MD_FP64) {
+        const double inv = rcp_f64(r2);
+        const double s2 = pc.s2 * inv;
+        const double s6 = s2 * s2 * s2;
+        fr = in ? pc.e24 * s6 * (2.0 * s6 - 1.0) * inv : 0.0;
+        c.ed += in ? pc.e4 * s6 * (s6 - 1.0) - pc.ush : 0.0;
+        c.wd += fr * r2;
+    } else {
+        const float r2f = static_cast<float>(r2);
+        const float inv = __builtin_amdgcn_rcpf(r2f);
+        const float s2 = static_cast<float>(pc.s2) * inv;
+        const float s6 = s2 * s2 * s2;
+        const float frf = in ? static_cast<float>(pc.e24) * s6 * (2.0f * s6 - 1.0f) * inv : 0.0f;
+        fr = static_cast<double>(frf);
+        c.ef += in ? static_cast<float>(pc.e4) * s6 * (s6 - 1.0f) - static_cast<float>(pc.ush)
+                   : 0.0f;
+        c.wf += frf * r2f;
+    }
+    c.fx = fma(fr, dx, c.fx);
+    c.fy = fma(fr, dy, c.fy);
+    c.fz = fma(fr, dz, c.fz);
+}
+
 }  // namespace md

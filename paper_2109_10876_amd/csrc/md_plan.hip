@@ -11,7 +11,7 @@ extern "C" {
 
 int md_abi_version(void) { return MD_ABI_VERSION; }
 
-static int32_t g_tune[MD_TUNE_NKNOBS] = {4, 256, 0};
+static int32_t g_tune[MD_TUNE_NKNOBS] = {4, 256, 0, 0};
 
 int md_tune_set(int32_t knob, int32_t value)
 {
@@ -19,12 +19,16 @@ int md_tune_set(int32_t knob, int32_t value)
     if (knob == MD_TUNE_PAIR_BATCH) ok = value == 1 || value == 2 || value == 4 || value == 8;
     if (knob == MD_TUNE_TILE_THREADS) ok = value == 64 || value == 128 || value == 256;
     if (knob == MD_TUNE_TILE_STAGE_PACKED) ok = value == 0 || value == 1;
+    if (knob == MD_TUNE_TILE_SLOTS)
+        ok = value == 0 || value == 1536 || value == 2048 || value == MD_TILE_SLOTS;
     if (!ok) return MD_EINVAL;
     g_tune[knob] = value;
     return MD_OK;
 }
 
 int md_tile_capacity(void) { return md::tile_capacity(); }
+
+int md_tile_max_cells(void) { return md::tile_max_cells(); }
 
 int md_tune_get(int32_t knob)
 {

@@ -42,11 +42,11 @@ struct TileArgs {
 
 constexpr int kCandBatch = 8;
 
-template <int TB, bool P4>
-__global__ __launch_bounds__(TB) void k_tile_build(TileArgs a)
+template <class SH, bool P4>
+__global__ __launch_bounds__(SH::TB) void k_tile_build(TileArgs a)
 {
-    constexpr int CAP = TileShape<TB>::CAP;
-    __shared__ TileStage<CAP, TileShape<TB>::MAXC> st;
+    constexpr int TB = SH::TB, CAP = SH::CAP;
+    __shared__ TileStage<CAP, SH::MAXC> st;
     for (int lt = blockIdx.x; lt < a.n_tiles; lt += gridDim.x) {
         const int t = xcd_swizzle(lt, a.n_tiles);
         const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
@@ -107,11 +107,11 @@ __global__ __launch_bounds__(TB) void k_tile_build(TileArgs a)
     }
 }
 
-template <int TB, int PREC, int U, bool P4>
-__global__ __launch_bounds__(TB) void k_tile_lj(TileArgs a)
+template <class SH, int PREC, int U, bool P4>
+__global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
 {
-    constexpr int CAP = TileShape<TB>::CAP;
-    __shared__ TileStage<CAP, TileShape<TB>::MAXC> st;
+    constexpr int TB = SH::TB, CAP = SH::CAP;
+    __shared__ TileStage<CAP, SH::MAXC> st;
     __shared__ double red[TB / kWave];
     const int t = xcd_swizzle(blockIdx.x, gridDim.x);
     const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
@@ -142,12 +142,20 @@ __global__ __launch_bounds__(TB) void k_tile_lj(TileArgs a)
 #pragma unroll
                 for (int q = 0; q < U; ++q)
                     nxt[q] = __builtin_nontemporal_load(col + size_t(min(k + U + q, kmax)) * a.ld);
+                // all U staged positions are read before any is used
+                double px[U], py[U], pz[U];
 #pragma unroll
                 for (int q = 0; q < U; ++q) {
                     const int sl = min(cur[q], CAP - 1);
+                    px[q] = st.x[sl];
+                    py[q] = st.y[sl];
+                    pz[q] = st.z[sl];
+                }
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
                     const double rcq = k + q < n ? rc2 : 0.0;   // masked: nothing is inside 0
-                    lj_pair_accumulate<PREC>(pc, xi - st.x[sl], yi - st.y[sl], zi - st.z[sl],
-                                             rcq, c);
+                    lj_pair_accumulate_masked<PREC>(pc, xi - px[q], yi - py[q], zi - pz[q], rcq,
+                                                    c);
                 }
 #pragma unroll
                 for (int q = 0; q < U; ++q) cur[q] = nxt[q];
@@ -228,19 +236,45 @@ bool tile_stage_packed() { return md_tune_get(MD_TUNE_TILE_STAGE_PACKED) != 0; }
 bool tile_list_ok(const md_batch *b, const md_nlist *nl)
 {
     return nl->n_tiles >= 1 && nl->n_tiles <= b->C && nl->tile_rep && nl->tile_off &&
-           nl->tile_cells >= 1 && nl->tile_cells <= kTileCells && nl->tile_py >= 1 &&
+           nl->tile_cells >= 1 && nl->tile_cells <= tile_max_cells() && nl->tile_py >= 1 &&
            nl->tile_py <= MD_TILE_MAX_ROWS && nl->tile_pz >= 1 && nl->tile_pz <= MD_TILE_MAX_ROWS;
 }
 
 int tile_threads() { return md_tune_get(MD_TUNE_TILE_THREADS); }
 
+namespace {
+
+// Calls f with the shape selected by MD_TUNE_TILE_THREADS and
+// MD_TUNE_TILE_SLOTS: the largest capacity of that workgroup size not above
+// the requested slot count (0: the largest there is).
+template <class F>
+void with_tile_shape(F &&f)
+{
+    const int slots = md_tune_get(MD_TUNE_TILE_SLOTS);
+    switch (tile_threads()) {
+    case 64: f(TileShape64{}); break;
+    case 128: f(TileShape128{}); break;
+    default:
+        if (slots == 0 || slots >= TileShape256::CAP) f(TileShape256{});
+        else if (slots >= TileShape256S2048::CAP) f(TileShape256S2048{});
+        else f(TileShape256S1536{});
+    }
+}
+
+}  // namespace
+
 int tile_capacity()
 {
-    switch (tile_threads()) {
-    case 64: return TileShape<64>::CAP;
-    case 128: return TileShape<128>::CAP;
-    default: return TileShape<256>::CAP;
-    }
+    int cap = 0;
+    with_tile_shape([&](auto sh) { cap = decltype(sh)::CAP; });
+    return cap;
+}
+
+int tile_max_cells()
+{
+    int mc = 0;
+    with_tile_shape([&](auto sh) { mc = decltype(sh)::MAXC; });
+    return mc;
 }
 
 int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_start, double rl2,
@@ -253,18 +287,13 @@ int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_sta
     a.rl2 = rl2;
     a.need = need;
     a.status = status;
-    const int tb = tile_threads();
     const dim3 grid(gated_grid(nl->n_tiles, gate != nullptr));
     const bool p4 = tile_stage_packed() && atoms->pos4;
-#define MD_TB_LAUNCH(TB)                                                                   \
-    do {                                                                                   \
-        if (p4) hipLaunchKernelGGL((k_tile_build<TB, true>), grid, dim3(TB), 0, s, a);     \
-        else hipLaunchKernelGGL((k_tile_build<TB, false>), grid, dim3(TB), 0, s, a);       \
-    } while (0)
-    if (tb == 64) MD_TB_LAUNCH(64);
-    else if (tb == 128) MD_TB_LAUNCH(128);
-    else MD_TB_LAUNCH(256);
-#undef MD_TB_LAUNCH
+    with_tile_shape([&](auto sh) {
+        using SH = decltype(sh);
+        if (p4) hipLaunchKernelGGL((k_tile_build<SH, true>), grid, dim3(SH::TB), 0, s, a);
+        else hipLaunchKernelGGL((k_tile_build<SH, false>), grid, dim3(SH::TB), 0, s, a);
+    });
     return launch_status();
 }
 
@@ -286,23 +315,24 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
     a.status = status;
     const dim3 grid(nl->n_tiles);
     const bool p4 = tile_stage_packed() && atoms->pos4;
-    const int tb = tile_threads();
     const bool big = batch >= 8;
-#define MD_TILE_LAUNCH(TB, P, U)                                                              \
-    do {                                                                                      \
-        if (p4) hipLaunchKernelGGL((k_tile_lj<TB, P, U, true>), grid, dim3(TB), 0, s, a);     \
-        else hipLaunchKernelGGL((k_tile_lj<TB, P, U, false>), grid, dim3(TB), 0, s, a);       \
+    with_tile_shape([&](auto sh) {
+        using SH = decltype(sh);
+        const dim3 blk(SH::TB);
+#define MD_TILE_LAUNCH(P, U)                                                          \
+    do {                                                                              \
+        if (p4) hipLaunchKernelGGL((k_tile_lj<SH, P, U, true>), grid, blk, 0, s, a);  \
+        else hipLaunchKernelGGL((k_tile_lj<SH, P, U, false>), grid, blk, 0, s, a);    \
     } while (0)
-#define MD_TILE_PREC(TB)                                                                      \
-    do {                                                                                      \
-        if (prec == MD_FP64) { if (big) MD_TILE_LAUNCH(TB, MD_FP64, 16); else MD_TILE_LAUNCH(TB, MD_FP64, 8); } \
-        else { if (big) MD_TILE_LAUNCH(TB, MD_FP32_MIXED, 16); else MD_TILE_LAUNCH(TB, MD_FP32_MIXED, 8); }     \
-    } while (0)
-    if (tb == 64) MD_TILE_PREC(64);
-    else if (tb == 128) MD_TILE_PREC(128);
-    else MD_TILE_PREC(256);
-#undef MD_TILE_PREC
+        if (prec == MD_FP64) {
+            if (big) MD_TILE_LAUNCH(MD_FP64, 16);
+            else MD_TILE_LAUNCH(MD_FP64, 8);
+        } else {
+            if (big) MD_TILE_LAUNCH(MD_FP32_MIXED, 16);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8);
+        }
 #undef MD_TILE_LAUNCH
+    });
     if (energy || virial)
         hipLaunchKernelGGL(k_tile_finalize, dim3(b->R), dim3(kUnit), 0, s, nl->tile_off, tpart,
                            energy, virial);

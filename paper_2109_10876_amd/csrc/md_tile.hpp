@@ -10,6 +10,8 @@
 // gathers and the list names neighbours by a 16-bit staged slot.
 #pragma once
 
+#include <climits>
+
 #include "md_common.hpp"
 
 namespace md {
@@ -19,22 +21,20 @@ constexpr int kMaxHomeRows = MD_TILE_MAX_ROWS * MD_TILE_MAX_ROWS;             //
 constexpr int kMaxStagedRows = (MD_TILE_MAX_ROWS + 2) * (MD_TILE_MAX_ROWS + 2);
 
 // Workgroup shapes of the tile kernels: TB threads (at most TB home atoms per
-// pass), CAP staged slots (3 x 8 CAP bytes of LDS), MAXC cells per tile.
-template <int TB>
-struct TileShape;
-template <>
-struct TileShape<64> {
-    static constexpr int CAP = 1024, MAXC = 8;
+// pass), CAP staged slots (3 x 8 CAP bytes of LDS), MAXC cells per tile
+// along x.  LDS per workgroup bounds how many workgroups share a CU (160 KiB
+// each): the 3072-slot shape fits two, the 2048-slot shape three and the
+// 1536-slot shape four.
+template <int TB_, int CAP_, int MAXC_>
+struct TileShape {
+    static constexpr int TB = TB_, CAP = CAP_, MAXC = MAXC_;
 };
-template <>
-struct TileShape<128> {
-    static constexpr int CAP = 1792, MAXC = 16;
-};
-template <>
-struct TileShape<256> {
-    static constexpr int CAP = 3072, MAXC = kTileCells;
-};
-static_assert(TileShape<256>::CAP == MD_TILE_SLOTS, "largest shape holds MD_TILE_SLOTS");
+using TileShape64 = TileShape<64, 1024, 8>;
+using TileShape128 = TileShape<128, 1792, 16>;
+using TileShape256 = TileShape<256, 3072, kTileCells>;
+using TileShape256S2048 = TileShape<256, 2048, 16>;
+using TileShape256S1536 = TileShape<256, 1536, 8>;
+static_assert(TileShape256::CAP == MD_TILE_SLOTS, "largest shape holds MD_TILE_SLOTS");
 
 // Block-wide fixed-order sum over TB threads; result valid in thread 0.
 template <int TB>
@@ -188,42 +188,54 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
     __syncthreads();
     const int total = st.row_slot[s.nrows];
     if (total > cap) return total;
-    // Slots tid, tid + TB, ...: locate each slot's row and piece, issue every
-    // load, then write LDS -- all loads of a thread are in flight together.
-    constexpr int kPer = (int(sizeof(decltype(st.x)) / sizeof(double)) + TB - 1) / TB;
-    double px[kPer], py[kPer], pz[kPer];
+    if (total > 0) {
+        // Row starts are the same for the whole workgroup: keep them in
+        // scalar registers and find a slot's row by counting starts <= slot.
+        int rs[kMaxStagedRows];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int sl = tid + k * TB;
-        if (sl < total) {
+        for (int q = 1; q < kMaxStagedRows; ++q)
+            rs[q] = q < s.nrows ? __builtin_amdgcn_readfirstlane(st.row_slot[q]) : INT_MAX;
+        // Slots tid, tid + TB, ...: first resolve every slot's source atom and
+        // image shift, then issue all loads together (lanes past the end
+        // re-read the last slot's atom), then write LDS.
+        constexpr int kPer = (int(sizeof(decltype(st.x)) / sizeof(double)) + TB - 1) / TB;
+        int src[kPer], rowof[kPer];
+        double sxk[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int sl = min(tid + k * TB, total - 1);
             int r = 0;
 #pragma unroll
-            for (int q = 1; q < kMaxStagedRows; ++q)
-                r += (q < s.nrows && sl >= st.row_slot[q]) ? 1 : 0;
+            for (int q = 1; q < kMaxStagedRows; ++q) r += sl >= rs[q] ? 1 : 0;
             const int off = sl - st.row_slot[r];
             const int lw = st.row_lw[r], mn = st.row_main[r];
             const int piece = off < lw ? 0 : (off < lw + mn ? 1 : 2);
-            const int j = st.row_g0[r][piece] + off - (piece == 0 ? 0 : (piece == 1 ? lw : lw + mn));
-            const double dx = piece == 0 ? -s.L[0] : (piece == 1 ? 0.0 : s.L[0]);
+            src[k] = st.row_g0[r][piece] + off - (piece == 0 ? 0 : (piece == 1 ? lw : lw + mn));
+            sxk[k] = piece == 0 ? -s.L[0] : (piece == 1 ? 0.0 : s.L[0]);
+            rowof[k] = r;
+        }
+        double px[kPer], py[kPer], pz[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
             if (P4) {
-                const double4 v = reinterpret_cast<const double4 *>(pos4)[j];
-                px[k] = v.x + dx;
-                py[k] = v.y + st.row_dy[r];
-                pz[k] = v.z + st.row_dz[r];
+                const double4 v = reinterpret_cast<const double4 *>(pos4)[src[k]];
+                px[k] = v.x;
+                py[k] = v.y;
+                pz[k] = v.z;
             } else {
-                px[k] = x[j] + dx;
-                py[k] = y[j] + st.row_dy[r];
-                pz[k] = z[j] + st.row_dz[r];
+                px[k] = x[src[k]];
+                py[k] = y[src[k]];
+                pz[k] = z[src[k]];
             }
         }
-    }
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int sl = tid + k * TB;
-        if (sl < total) {
-            st.x[sl] = px[k];
-            st.y[sl] = py[k];
-            st.z[sl] = pz[k];
+        for (int k = 0; k < kPer; ++k) {
+            const int sl = tid + k * TB;
+            if (sl < total) {
+                st.x[sl] = px[k] + sxk[k];
+                st.y[sl] = py[k] + st.row_dy[rowof[k]];
+                st.z[sl] = pz[k] + st.row_dz[rowof[k]];
+            }
         }
     }
     __syncthreads();

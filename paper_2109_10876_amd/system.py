@@ -129,7 +129,7 @@ class MDSystem:
                 py, pz = self.tile_py, self.tile_pz
                 m = int(min(0.92 * cap / ((py + 2) * (pz + 2) * nu) - 2,
                             1.02 * tb / (py * pz * nu)))
-                m = max(1, min(m, abi.MD_TILE_MAX_CELLS, int(self.h_ncell[:, 0].max())))
+                m = max(1, min(m, self.lib.md_tile_max_cells(), int(self.h_ncell[:, 0].max())))
                 nx = int(self.h_ncell[:, 0].max())
                 m = -(-nx // -(-nx // m))
                 tile_cells = m

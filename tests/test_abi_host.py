@@ -65,9 +65,16 @@ def test_tuning_knobs():
     assert lib.md_tune_set(abi.MD_TUNE_PAIR_BATCH, 3) == abi.MD_EINVAL
     assert lib.md_tune_get(abi.MD_TUNE_TILE_THREADS) == 256
     assert lib.md_tile_capacity() == abi.MD_TILE_SLOTS
-    for tb, cap in ((64, 1024), (128, 1792), (256, 3072)):
+    assert lib.md_tile_max_cells() == abi.MD_TILE_MAX_CELLS
+    for tb, cap, mc in ((64, 1024, 8), (128, 1792, 16), (256, 3072, 64)):
         assert lib.md_tune_set(abi.MD_TUNE_TILE_THREADS, tb) == abi.MD_OK
-        assert lib.md_tile_capacity() == cap
+        assert lib.md_tile_capacity() == cap and lib.md_tile_max_cells() == mc
+    # smaller staged capacity at 256 threads (less LDS per workgroup)
+    for slots, cap, mc in ((2048, 2048, 16), (1536, 1536, 8), (3072, 3072, 64), (0, 3072, 64)):
+        assert lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, slots) == abi.MD_OK
+        assert lib.md_tile_capacity() == cap and lib.md_tile_max_cells() == mc
+    assert lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, 1000) == abi.MD_EINVAL
+    assert lib.md_tune_get(abi.MD_TUNE_TILE_SLOTS) == 0
     assert lib.md_tune_set(abi.MD_TUNE_TILE_THREADS, 96) == abi.MD_EINVAL
     assert lib.md_tune_set(abi.MD_TUNE_TILE_STAGE_PACKED, 2) == abi.MD_EINVAL
     assert lib.md_tune_set(99, 1) == abi.MD_EINVAL

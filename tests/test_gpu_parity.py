@@ -407,3 +407,51 @@ def test_tile_graph_replays_match_eager():
     f.run(30, check_every=0)
     f.ensure_list()
     assert np.abs(f.positions() - a.positions()).max() < 1e-10
+
+
+@pytest.mark.parametrize("tb,slots,rows", [(256, 2048, (2, 2)), (256, 1536, (2, 1)),
+                                           (256, 1536, (1, 1)), (128, 0, (2, 1)),
+                                           (64, 0, (1, 1))])
+def test_tile_shapes_match_oracle(c1_snapshot, tb, slots, rows):
+    # every workgroup shape (threads x staged capacity) gives the oracle's
+    # forces and the skin pair set; tile size chosen automatically per shape.
+    # (5 cells of ~32 atoms per side: 2 x 2 rows would stage ~1536 atoms even
+    # for one-cell tiles, which the 1536-slot shape cannot hold)
+    from paper_2109_10876_amd import _abi as abi
+    lib = abi.load()
+    cfg = c1_snapshot
+    say(f"case: tile shape tb={tb} slots={slots} rows={rows}")
+    assert lib.md_tune_set(abi.MD_TUNE_TILE_THREADS, tb) == 0
+    assert lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, slots) == 0
+    try:
+        s = _system(cfg, mode="tile", prec="fp64", tile_rows=rows)
+        assert 1 <= s.tile_cells <= lib.md_tile_max_cells()
+        s.setup()
+        assert s.ensure_list() == 0
+        ref, e, w = oracle.lj_forces(cfg.pos, cfg.box[0], RC, shift=1)
+        assert np.abs(s.forces_np() - ref).max() < 1e-10
+        assert float(s.energy[0]) == pytest.approx(e, rel=1e-12)
+        assert float(s.virial[0]) == pytest.approx(w, rel=1e-12)
+        got = _unordered(s.list_pairs()[0])
+        exp = set(map(tuple, oracle.pairs_cells(cfg.pos, cfg.box[0], RC + SKIN)))
+        assert got == exp
+    finally:
+        lib.md_tune_set(abi.MD_TUNE_TILE_THREADS, 256)
+        lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, 0)
+
+
+def test_tile_cells_beyond_the_shape_are_rejected():
+    # the 64-thread shape holds at most 8 cells per tile along x: a 9-cell
+    # tile is refused on the host before any launch
+    from paper_2109_10876_amd import _abi as abi
+    lib = abi.load()
+    cfg = md_inputs.lj_fluid(16, temperature=1.0, seed=23, jitter_amp=0.05)
+    say("case: tile cells beyond the shape")
+    assert lib.md_tune_set(abi.MD_TUNE_TILE_THREADS, 64) == 0
+    try:
+        s = _system(cfg, mode="tile", tile_cells=9)
+        s.sort(gated=False)
+        with pytest.raises(abi.MDError):
+            s.build(gated=False)
+    finally:
+        lib.md_tune_set(abi.MD_TUNE_TILE_THREADS, 256)
