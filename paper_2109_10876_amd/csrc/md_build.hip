@@ -33,6 +33,7 @@ struct BuildArgs {
     uint32_t *idx;
     int32_t *need;
     uint32_t *status;
+    int32_t R;
 };
 
 // Neighbour offsets along one dimension, each distinct cell once:
@@ -185,6 +186,7 @@ __device__ __forceinline__ void build_atom(const BuildArgs &a, const Unit &w, in
 template <bool HALF, bool P4>
 __global__ __launch_bounds__(kUnit) void k_build(BuildArgs a)
 {
+    if (sole_replica_gated_off(a.gate, a.R)) return;
     for (int lb = blockIdx.x; lb < a.n_units; lb += gridDim.x) {
         const int u = xcd_swizzle(lb, a.n_units);
         const Unit w = unit_of(u, a.unit_rep, a.unit_off, a.atom_off);
@@ -219,7 +221,7 @@ extern "C" int md_verlet_build(const md_batch *b, const md_atoms *atoms,
     BuildArgs a{b->atom_off, b->cell_off, b->ncell, b->unit_rep, b->unit_off, b->box, gate,
                 atoms->x, atoms->y, atoms->z, atoms->pos4, cell_start,
                 (rc + skin) * (rc + skin), nl->max_nbr, nl->ld, b->n_units, nl->count, nl->idx,
-                need, status};
+                need, status, b->R};
     hipStream_t s = as_stream(stream);
     const dim3 grid(gated_grid(b->n_units, gate != nullptr)), block(kUnit);
     const bool p4 = atoms->pos4 != nullptr;

@@ -99,6 +99,13 @@ __device__ __forceinline__ int cell_coord(double w, double L, int n)
     return c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
 }
 
+// True when the batch is one replica whose rebuild gate is 0: gated
+// kernels then leave at once instead of visiting every work unit.
+__device__ __forceinline__ bool sole_replica_gated_off(const uint32_t *gate, int R)
+{
+    return gate != nullptr && R == 1 && gate[0] == 0u;
+}
+
 // Wrap x into [0, L); returns the number of box lengths removed.
 __device__ __forceinline__ double wrap_coord(double x, double L, int *shift)
 {

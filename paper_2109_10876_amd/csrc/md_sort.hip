@@ -23,13 +23,13 @@ struct BatchArgs {
     const int32_t *atom_off, *cell_off, *ncell, *unit_rep, *unit_off;
     const double *box;
     const uint32_t *gate;
-    int32_t n_units;
+    int32_t n_units, R;
 };
 
 BatchArgs batch_args(const md_batch *b, const uint32_t *gate)
 {
     return BatchArgs{b->atom_off, b->cell_off, b->ncell, b->unit_rep, b->unit_off, b->box, gate,
-                     b->n_units};
+                     b->n_units, b->R};
 }
 
 __device__ __forceinline__ bool gated_off(const BatchArgs &a, int rep)
@@ -60,8 +60,10 @@ __device__ __forceinline__ int aggregated_slot(int32_t *count, int c, bool activ
 }
 
 // Grid-stride loop over work units; a unit whose replica's gate is 0 is
-// skipped, so a skipped rebuild costs one short launch.
+// skipped, so a skipped rebuild costs one short launch (one load per
+// workgroup for a single replica).
 #define MD_FOR_UNITS(a, w)                                                          \
+    if (!sole_replica_gated_off((a).gate, (a).R))                                  \
     for (int lb_ = blockIdx.x; lb_ < (a).n_units; lb_ += gridDim.x)                \
         if (const Unit w = unit_of(lb_, (a).unit_rep, (a).unit_off, (a).atom_off); \
             !gated_off((a), w.rep))

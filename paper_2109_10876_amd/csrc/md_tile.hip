@@ -38,6 +38,7 @@ struct TileArgs {
     int32_t accumulate;
     double *tpart;    // [n_tiles * 2]
     uint32_t *status;
+    int32_t R;
 };
 
 constexpr int kCandBatch = 8;
@@ -47,6 +48,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_build(TileArgs a)
 {
     constexpr int TB = SH::TB, CAP = SH::CAP;
     __shared__ TileStage<CAP, SH::MAXC> st;
+    if (sole_replica_gated_off(a.gate, a.R)) return;
     for (int lt = blockIdx.x; lt < a.n_tiles; lt += gridDim.x) {
         const int t = xcd_swizzle(lt, a.n_tiles);
         const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
@@ -61,6 +63,12 @@ __global__ __launch_bounds__(SH::TB) void k_tile_build(TileArgs a)
             continue;
         }
         const int nh = st.home_start[s.hy * s.hz];
+        const double hx = s.L[0] / s.nx, hy = s.L[1] / s.ny, hz = s.L[2] / s.nz;
+        // a neighbour cell is skipped when the distance from the atom to the
+        // cell's box is at least r_l (with a relative margin far above
+        // rounding, so no pair inside r_l is ever dropped)
+        const double cull2 = a.rl2 * (1.0 + 1e-10);
+        const uint32_t lastoff = uint32_t(a.max_nbr - 1) * uint32_t(a.ld);
         for (int hk = threadIdx.x; hk < nh; hk += TB) {
             int dy, dz;
             const int i = home_atom(s, st, hk, dy, dz);
@@ -70,11 +78,25 @@ __global__ __launch_bounds__(SH::TB) void k_tile_build(TileArgs a)
             const int qc = staged_row(s, dy, dz);
             const int own = st.row_slot[qc] + st.cslot[qc][kc + 1] +
                             (i - a.cell_start[st.row_rb[qc] + cx]);
+            // squared gaps to the lower / upper faces of the atom's cell
+            const double gxl = fmax(xi - cx * hx, 0.0), gxr = fmax((cx + 1) * hx - xi, 0.0);
+            const int cy = s.y0 + dy, cz = s.z0 + dz;
+            const double gyl = fmax(yi - cy * hy, 0.0), gyr = fmax((cy + 1) * hy - yi, 0.0);
+            const double gzl = fmax(zi - cz * hz, 0.0), gzr = fmax((cz + 1) * hz - zi, 0.0);
+            uint16_t *col = a.idx + i;
+            uint32_t off = 0;   // element offset of the next entry, clamped to the last column
             int cnt = 0;
             for (int r9 = 0; r9 < 9; ++r9) {
-                const int r = staged_row(s, dy + r9 % 3 - 1, dz + r9 / 3 - 1);
-                const int s0 = st.row_slot[r] + st.cslot[r][kc];
-                const int s1 = st.row_slot[r] + st.cslot[r][kc + 3];
+                const int oy = r9 % 3 - 1, oz = r9 / 3 - 1;
+                const double gy = oy < 0 ? gyl : (oy > 0 ? gyr : 0.0);
+                const double gz = oz < 0 ? gzl : (oz > 0 ? gzr : 0.0);
+                const double g2 = gy * gy + gz * gz;
+                if (g2 >= cull2) continue;
+                const int r = staged_row(s, dy + oy, dz + oz);
+                const int k0 = kc + (g2 + gxl * gxl < cull2 ? 0 : 1);
+                const int k1 = kc + (g2 + gxr * gxr < cull2 ? 3 : 2);
+                const int s0 = st.row_slot[r] + st.cslot[r][k0];
+                const int s1 = st.row_slot[r] + st.cslot[r][k1];
                 for (int sb = s0; sb < s1; sb += kCandBatch) {
                     double px[kCandBatch], py[kCandBatch], pz[kCandBatch];
 #pragma unroll
@@ -87,13 +109,14 @@ __global__ __launch_bounds__(SH::TB) void k_tile_build(TileArgs a)
 #pragma unroll
                     for (int q = 0; q < kCandBatch; ++q) {
                         const int sl = sb + q;
-                        const double dx = xi - px[q], dy = yi - py[q], dz = zi - pz[q];
-                        const bool take = sl < s1 && sl != own &&
-                                          dx * dx + dy * dy + dz * dz < a.rl2;
-                        if (take) {
-                            if (cnt < a.max_nbr) a.idx[size_t(cnt) * a.ld + i] = uint16_t(sl);
-                            ++cnt;
-                        }
+                        const double dx = xi - px[q], dy2 = yi - py[q], dz2 = zi - pz[q];
+                        const bool take = (sl < s1) & (sl != own) &
+                                          (dx * dx + dy2 * dy2 + dz2 * dz2 < a.rl2);
+                        // past max_nbr entries land in the last column (the
+                        // count still grows and flags the overflow)
+                        if (take) col[off] = uint16_t(sl);
+                        cnt += take ? 1 : 0;
+                        off = take ? min(off + uint32_t(a.ld), lastoff) : off;
                     }
                 }
             }
@@ -226,6 +249,7 @@ TileArgs tile_args(const md_batch *b, const md_atoms *atoms, const md_nlist *nl)
     a.count = nl->count;
     a.idx = reinterpret_cast<uint16_t *>(nl->idx);
     a.tile_need = nl->tile_need;
+    a.R = b->R;
     return a;
 }
 

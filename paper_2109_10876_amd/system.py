@@ -38,7 +38,7 @@ class MDSystem:
 
     def __init__(self, natoms, box, pos, vel, types=None, eps=1.0, sig=1.0, mass=None,
                  rc=2.5, skin=0.3, dt=0.005, shift=1, mode="full", prec="fp64",
-                 max_nbr=None, pos4=True, bonds=None, fene=(30.0, 1.5), langevin=None,
+                 max_nbr=None, pos4=None, bonds=None, fene=(30.0, 1.5), langevin=None,
                  tile_cells=None, tile_rows=(1, 1), device="cuda"):
         self.lib = abi.load()
         self.dev = torch.device(device)
@@ -94,6 +94,11 @@ class MDSystem:
         self.img = torch.zeros(3 * self.N, dtype=torch.int32, device=d)
         self.where = torch.arange(self.N, dtype=torch.int32, device=d)
         # packed (x, y, z, 0) gather copy, maintained by the re-sort and the integrator
+        if pos4 is None:
+            # the packed copy feeds the global-list gathers, and tile staging
+            # only when MD_TUNE_TILE_STAGE_PACKED is set
+            pos4 = (mode != "tile" or
+                    self.lib.md_tune_get(abi.MD_TUNE_TILE_STAGE_PACKED) == 1)
         self.pos4 = torch.zeros(4 * self.N, dtype=torch.float64, device=d) if pos4 else None
         self.atoms = self._atoms_struct(self)
         # re-sort scratch planes
