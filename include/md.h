@@ -91,12 +91,15 @@ extern "C" {
  * x = a-1 .. b+1 of that row (x = -1 is cell nx-1 one box length to the
  * left, x = nx is cell 0 one box length to the right), each cell's atoms in
  * index order, concatenated.  Entry k of atom i is the uint16
- * ((uint16_t *)idx)[k * ld + i]: the position of the neighbour in its tile's
- * staged sequence (its image is the one its staged row and cell imply).  A
- * tile whose staged sequence exceeds md_tile_capacity() (at most
- * MD_TILE_SLOTS) raises MD_F_TILE_OVERFLOW (the list is then unusable:
- * rebuild with smaller tiles).  Tile-local lists take one atom type
- * (md_lj_forces returns MD_EUNSUPPORTED otherwise) and have no adjoint. */
+ * ((uint16_t *)idx)[k * ld + i] = 8 p, where p is the position of the
+ * neighbour in its tile's staged sequence (its image is the one its staged
+ * row and cell imply).  Entries count[i] .. (count[i] rounded up to 16) - 1
+ * hold 8 md_tile_capacity(), a pad slot far from every atom, so max_nbr
+ * must be a multiple of 16 (MD_EINVAL otherwise).  A tile whose staged
+ * sequence exceeds md_tile_capacity() (at most MD_TILE_SLOTS) raises
+ * MD_F_TILE_OVERFLOW (the list is then unusable: rebuild with smaller
+ * tiles).  Tile-local lists take one atom type (md_lj_forces returns
+ * MD_EUNSUPPORTED otherwise) and have no adjoint. */
 
 /* ------------------------------------------------------------------ structs */
 

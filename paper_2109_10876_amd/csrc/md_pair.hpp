@@ -69,35 +69,60 @@ __device__ __forceinline__ double lj_pair_accumulate(const PairConst &pc, double
     return fr;
 }
 
-// Same terms as lj_pair_accumulate, evaluated for every entry and masked
-// with a select instead of a branch (for loops where most entries of a
-// wavefront fall inside the cutoff anyway).  A masked entry adds exact
-// zeros; its arithmetic may overflow (r2 = 0) but is never selected.
+// Constants of the LJ terms written in powers of q = 1/r^2: with
+// q3 = q^3, the virial term w = fr r^2 = q3 (A q3 - B) and the energy
+// U = q3 (C q3 - D) - U(rc), where A = 48 eps sig^12, B = 24 eps sig^6,
+// C = 4 eps sig^12, D = 4 eps sig^6 (the same Eq. lj terms as PairConst).
+struct PolyConst {
+    double A, B, C, D, ush;
+    float Af, Bf, Cf, Df, ushf;
+};
+
+__device__ __forceinline__ PolyConst poly_const(double eps, double sig, double rc, int shift)
+{
+    PolyConst p;
+    const double s6 = sig * sig * sig * sig * sig * sig;
+    p.A = 48.0 * eps * s6 * s6;
+    p.B = 24.0 * eps * s6;
+    p.C = 4.0 * eps * s6 * s6;
+    p.D = 4.0 * eps * s6;
+    const double q = 1.0 / (rc * rc), q3 = q * q * q;
+    p.ush = shift ? q3 * (p.C * q3 - p.D) : 0.0;
+    p.Af = static_cast<float>(p.A);
+    p.Bf = static_cast<float>(p.B);
+    p.Cf = static_cast<float>(p.C);
+    p.Df = static_cast<float>(p.D);
+    p.ushf = static_cast<float>(p.ush);
+    return p;
+}
+
+// Pair terms of one displacement evaluated unconditionally and masked with
+// selects (no branch: in a wavefront most entries fall inside the cutoff
+// anyway).  The cutoff test is in double.  A masked entry adds exact zeros;
+// its own arithmetic may overflow but is never selected.
 template <int PREC>
-__device__ __forceinline__ void lj_pair_accumulate_masked(const PairConst &pc, double dx,
-                                                          double dy, double dz, double rc2,
-                                                          Acc &c)
+__device__ __forceinline__ void lj_pair_masked(const PolyConst &pc, double dx, double dy,
+                                               double dz, double rc2, Acc &c)
 {
     const double r2 = dx * dx + dy * dy + dz * dz;
     const bool in = r2 < rc2;
     double fr;
     if (PREC == MD_FP64) {
-        const double inv = rcp_f64(r2);
-        const double s2 = pc.s2 * inv;
-        const double s6 = s2 * s2 * s2;
-        fr = in ? pc.e24 * s6 * (2.0 * s6 - 1.0) * inv : 0.0;
-        c.ed += in ? pc.e4 * s6 * (s6 - 1.0) - pc.ush : 0.0;
-        c.wd += fr * r2;
+        const double q = rcp_f64(r2);
+        const double q3 = q * q * q;
+        const double w = q3 * (pc.A * q3 - pc.B);
+        fr = in ? w * q : 0.0;
+        c.ed += in ? q3 * (pc.C * q3 - pc.D) - pc.ush : 0.0;
+        c.wd = fma(fr, r2, c.wd);
     } else {
         const float r2f = static_cast<float>(r2);
-        const float inv = __builtin_amdgcn_rcpf(r2f);
-        const float s2 = static_cast<float>(pc.s2) * inv;
-        const float s6 = s2 * s2 * s2;
-        const float frf = in ? static_cast<float>(pc.e24) * s6 * (2.0f * s6 - 1.0f) * inv : 0.0f;
+        const float q = __builtin_amdgcn_rcpf(r2f);
+        const float q3 = q * q * q;
+        const float w = q3 * fmaf(pc.Af, q3, -pc.Bf);
+        const float frf = in ? w * q : 0.0f;
+        c.ef += in ? fmaf(q3, fmaf(pc.Cf, q3, -pc.Df), -pc.ushf) : 0.0f;
+        c.wf = fmaf(frf, r2f, c.wf);
         fr = static_cast<double>(frf);
-        c.ef += in ? static_cast<float>(pc.e4) * s6 * (s6 - 1.0f) - static_cast<float>(pc.ush)
-                   : 0.0f;
-        c.wf += frf * r2f;
     }
     c.fx = fma(fr, dx, c.fx);
     c.fy = fma(fr, dy, c.fy);

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_build(TileArgs a)
                                           (dx * dx + dy2 * dy2 + dz2 * dz2 < a.rl2);
                         // past max_nbr entries land in the last column (the
                         // count still grows and flags the overflow)
-                        if (take) col[off] = uint16_t(sl);
+                        if (take) col[off] = uint16_t(sl * 8);
                         cnt += take ? 1 : 0;
                         off = take ? min(off + uint32_t(a.ld), lastoff) : off;
                     }
@@ -124,6 +124,11 @@ __global__ __launch_bounds__(SH::TB) void k_tile_build(TileArgs a)
             if (cnt > a.max_nbr) {
                 if (a.status) atomicOr(a.status, MD_F_NBR_OVERFLOW);
                 if (a.need) atomicMax(a.need, cnt);
+            } else {
+                // pad to a multiple of 16 entries (max_nbr is one) with the
+                // pad slot, so force loops need no tail mask
+                const int padded = (cnt + 15) & ~15;
+                for (int k = cnt; k < padded; ++k) col[size_t(k) * a.ld] = uint16_t(CAP * 8);
             }
         }
         __syncthreads();
@@ -138,7 +143,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
     __shared__ double red[TB / kWave];
     const int t = xcd_swizzle(blockIdx.x, gridDim.x);
     const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
-    const PairConst pc = pair_const(a.eps[0], a.sig[0], a.rc, a.shift);
+    const PolyConst pc = poly_const(a.eps[0], a.sig[0], a.rc, a.shift);
     const double rc2 = a.rc * a.rc;
     const int total = stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP);
     double e_acc = 0.0, w_acc = 0.0;
@@ -146,40 +151,43 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
         if (threadIdx.x == 0 && a.status) atomicOr(a.status, MD_F_TILE_OVERFLOW);
     } else {
         const int nh = st.home_start[s.hy * s.hz];
+        const char *stb = reinterpret_cast<const char *>(st.x);
+        constexpr int kY = int(sizeof(double)) * decltype(st)::kStride;
         for (int hk = threadIdx.x; hk < nh; hk += TB) {
             int dy, dz;
             const int i = home_atom(s, st, hk, dy, dz);
             const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
             const int n = min(a.count[i], a.max_nbr);
             Acc c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
-            const uint16_t *col = a.idx + i;
-            // Entries are consumed U at a time while the next U are already
-            // in flight.  Reads stay inside the allocated columns (index
-            // clamped to max_nbr - 1); entries at k >= n are masked out.
+            // Entries are LDS byte offsets, consumed U at a time while the
+            // next U are in flight; a list is padded with the pad slot to a
+            // multiple of 16 entries, so no entry needs a mask.  Column
+            // reads stay inside the allocation (index clamped to
+            // max_nbr - 1) and LDS reads inside the staging planes (offset
+            // clamped to the pad slot).
             const int kmax = a.max_nbr - 1;
+            const unsigned ui = unsigned(i);
             int cur[U], nxt[U];
 #pragma unroll
             for (int q = 0; q < U; ++q)
-                cur[q] = __builtin_nontemporal_load(col + size_t(min(q, kmax)) * a.ld);
+                cur[q] = __builtin_nontemporal_load(a.idx + size_t(min(q, kmax)) * a.ld + ui);
             for (int k = 0; k < n; k += U) {
 #pragma unroll
                 for (int q = 0; q < U; ++q)
-                    nxt[q] = __builtin_nontemporal_load(col + size_t(min(k + U + q, kmax)) * a.ld);
+                    nxt[q] = __builtin_nontemporal_load(
+                        a.idx + size_t(min(k + U + q, kmax)) * a.ld + ui);
                 // all U staged positions are read before any is used
                 double px[U], py[U], pz[U];
 #pragma unroll
                 for (int q = 0; q < U; ++q) {
-                    const int sl = min(cur[q], CAP - 1);
-                    px[q] = st.x[sl];
-                    py[q] = st.y[sl];
-                    pz[q] = st.z[sl];
+                    const char *pq = stb + min(unsigned(cur[q]), unsigned(CAP * 8));
+                    px[q] = *reinterpret_cast<const double *>(pq);
+                    py[q] = *reinterpret_cast<const double *>(pq + kY);
+                    pz[q] = *reinterpret_cast<const double *>(pq + 2 * kY);
                 }
 #pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    const double rcq = k + q < n ? rc2 : 0.0;   // masked: nothing is inside 0
-                    lj_pair_accumulate_masked<PREC>(pc, xi - px[q], yi - py[q], zi - pz[q], rcq,
-                                                    c);
-                }
+                for (int q = 0; q < U; ++q)
+                    lj_pair_masked<PREC>(pc, xi - px[q], yi - py[q], zi - pz[q], rc2, c);
 #pragma unroll
                 for (int q = 0; q < U; ++q) cur[q] = nxt[q];
             }
@@ -260,6 +268,7 @@ bool tile_stage_packed() { return md_tune_get(MD_TUNE_TILE_STAGE_PACKED) != 0; }
 bool tile_list_ok(const md_batch *b, const md_nlist *nl)
 {
     return nl->n_tiles >= 1 && nl->n_tiles <= b->C && nl->tile_rep && nl->tile_off &&
+           nl->max_nbr % 16 == 0 &&
            nl->tile_cells >= 1 && nl->tile_cells <= tile_max_cells() && nl->tile_py >= 1 &&
            nl->tile_py <= MD_TILE_MAX_ROWS && nl->tile_pz >= 1 && nl->tile_pz <= MD_TILE_MAX_ROWS;
 }

@@ -94,11 +94,16 @@ __device__ __forceinline__ TileSpec tile_spec(int t, const int32_t *__restrict__
     return s;
 }
 
-// LDS tables of one staged tile.
+// LDS tables of one staged tile.  Positions of staged slot s sit at
+// x[s], y[s], z[s]; slot CAP is the pad slot (a position far outside any
+// box) that padded list entries name.  The planes are kStride apart, a
+// multiple of 64 doubles, so one ds_read2st64 fetches x and y together.
 template <int CAP, int MAXC>
 struct TileStage {
+    static constexpr int kCap = CAP;
+    static constexpr int kStride = (CAP + 1 + 63) / 64 * 64;
     static constexpr int kRowStage = MAXC + 3;   // cell starts a-1 .. b+2 of one staged row
-    double x[CAP], y[CAP], z[CAP];
+    double x[kStride], y[kStride], z[kStride];
     int row_slot[kMaxStagedRows + 1];  // first slot of staged row q; [nrows] = total
     int row_rb[kMaxStagedRows];        // linear index of cell (0, y, z) of staged row q
     int row_lo[kMaxStagedRows];        // first physical cell of the row's main piece
@@ -111,6 +116,10 @@ struct TileStage {
     int home_start[kMaxHomeRows + 1];  // prefix of home atoms over the home rows
     int home_g0[kMaxHomeRows];         // first atom of each home row's run a..b
 };
+
+// Coordinate of the pad slot: every distance to it is far beyond any cutoff
+// and its pair terms stay finite in single precision.
+constexpr double kPadCoord = 1.0e15;
 
 // Staged row of home row offsets (dy, dz) moved by (oy, oz) in -1..1.
 __device__ __forceinline__ int staged_row(const TileSpec &s, int dy, int dz)
@@ -130,6 +139,11 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
     const int tid = threadIdx.x;
     const int nhome = s.hy * s.hz;
     __syncthreads();   // readers of the previous tile are done with st
+    if (tid == TB - 1) {
+        st.x[Stage::kCap] = kPadCoord;
+        st.y[Stage::kCap] = kPadCoord;
+        st.z[Stage::kCap] = kPadCoord;
+    }
     if (tid < s.nrows) {
         const int zr = tid / (s.hy + 2), yr = tid % (s.hy + 2);
         int az = s.z0 - 1 + zr, ay = s.y0 - 1 + yr;
@@ -198,7 +212,7 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
         // Slots tid, tid + TB, ...: first resolve every slot's source atom and
         // image shift, then issue all loads together (lanes past the end
         // re-read the last slot's atom), then write LDS.
-        constexpr int kPer = (int(sizeof(decltype(st.x)) / sizeof(double)) + TB - 1) / TB;
+        constexpr int kPer = (Stage::kCap + TB - 1) / TB;
         int src[kPer], rowof[kPer];
         double sxk[kPer];
 #pragma unroll

@@ -209,7 +209,7 @@ class MDSystem:
         self.tile_off = torch.as_tensor(off).to(self.dev)
 
     def _alloc_list(self, max_nbr):
-        self.max_nbr = int(max_nbr)
+        self.max_nbr = (int(max_nbr) + 15) // 16 * 16   # tile lists pad to 16 entries
         self.count = torch.zeros(self.N, dtype=torch.int32, device=self.dev)
         self.idx = torch.zeros(self.max_nbr * self.ld, dtype=torch.int32, device=self.dev)
         self._set_nlist()
@@ -431,7 +431,7 @@ class MDSystem:
             for home, slots in self.tile_slot_table():
                 for i in home:
                     n = min(cnt[i], self.max_nbr)
-                    js = slots[idx[:n, i].astype(np.int64)]
+                    js = slots[idx[:n, i].astype(np.int64) // 8]
                     out.append(np.stack([np.full(n, ids[i]), ids[js]], 1))
             return np.concatenate(out), None
         cnt = self.count.cpu().numpy()

@@ -455,3 +455,33 @@ def test_tile_cells_beyond_the_shape_are_rejected():
             s.build(gated=False)
     finally:
         lib.md_tune_set(abi.MD_TUNE_TILE_THREADS, 256)
+
+
+def test_tile_list_padding_and_neighbour_overflow(c1_snapshot):
+    # tile lists: entries past the count, up to a multiple of 16, name the pad
+    # slot; a too-small max_nbr is flagged, regrown, and forces recover
+    from paper_2109_10876_amd import _abi as abi
+    import torch
+    lib = abi.load()
+    cfg = c1_snapshot
+    say("case: tile padding and neighbour overflow")
+    s = _system(cfg, mode="tile", prec="fp64", max_nbr=16)
+    assert s.max_nbr == 16
+    s.sort(gated=False)
+    s.build(gated=False)
+    torch.cuda.synchronize()
+    assert int(s.status.item()) & abi.MD_F_NBR_OVERFLOW
+    s.ensure_list()
+    assert s.max_nbr % 16 == 0 and s.max_nbr >= int(s.count.max().item())
+    cnt = s.count.cpu().numpy()
+    idx = s.idx.cpu().numpy().view(np.uint16)[:s.max_nbr * s.ld].reshape(s.max_nbr, s.ld)
+    pad = 8 * lib.md_tile_capacity()
+    for i in range(0, s.N, 97):
+        n = int(cnt[i])
+        top = (n + 15) // 16 * 16
+        assert np.all(idx[n:top, i] == pad)
+        assert np.all(idx[:n, i] < pad) and np.all(idx[:n, i] % 8 == 0)
+    s.forces()
+    ref, e, _ = oracle.lj_forces(cfg.pos, cfg.box[0], RC, shift=1)
+    assert np.abs(s.forces_np() - ref).max() < 1e-10
+    assert float(s.energy[0]) == pytest.approx(e, rel=1e-12)
