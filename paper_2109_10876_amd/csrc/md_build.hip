@@ -128,8 +128,9 @@ __device__ __forceinline__ void build_atom(const BuildArgs &a, const Unit &w, in
     const int nx = a.ncell[3 * w.rep], ny = a.ncell[3 * w.rep + 1], nz = a.ncell[3 * w.rep + 2];
     const int coff = a.cell_off[w.rep];
     const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
-    const int cx = cell_coord(xi, L[0], nx), cy = cell_coord(yi, L[1], ny);
-    const int cz = cell_coord(zi, L[2], nz);
+    const int cx = cell_coord(xi, cells_per_length(nx, L[0]), nx);
+    const int cy = cell_coord(yi, cells_per_length(ny, L[1]), ny);
+    const int cz = cell_coord(zi, cells_per_length(nz, L[2]), nz);
     int cnt = 0;
 
     if (nx >= 3 && ny >= 3 && nz >= 3) {

@@ -27,7 +27,7 @@ struct WsLayout {
     size_t cell_count;   // C x int32
     size_t cell_of;      // N x int32
     size_t slot;         // N x int32
-    size_t key;          // N x int32
+    size_t key;          // N (+16 padding) x int32
     size_t vjp_partial;  // n_units x 2 x MD_MAX_TYPES^2 doubles
     size_t tile_partial; // C x 2 doubles (tiles never outnumber cells)
     size_t total;
@@ -45,7 +45,7 @@ inline WsLayout ws_layout(const md_batch *b)
     l.cell_count = o;  o = align256(o + size_t(b->C) * sizeof(int32_t));
     l.cell_of = o;     o = align256(o + size_t(b->N) * sizeof(int32_t));
     l.slot = o;        o = align256(o + size_t(b->N) * sizeof(int32_t));
-    l.key = o;         o = align256(o + size_t(b->N) * sizeof(int32_t));
+    l.key = o;         o = align256(o + (size_t(b->N) + 16) * sizeof(int32_t));   // 16 B reads may pass the end
     l.vjp_partial = o; o = align256(o + size_t(b->n_units) * 2 * MD_MAX_TYPES * MD_MAX_TYPES * sizeof(double));
     l.tile_partial = o; o = align256(o + size_t(b->C) * 2 * sizeof(double));
     l.total = o;
@@ -90,12 +90,17 @@ __device__ __forceinline__ Unit unit_of(int u, const int32_t *__restrict__ unit_
 
 // ---------------------------------------------------------------- geometry
 
-// Cell coordinate of a wrapped coordinate w in [0, L): floor(w n / L), clamped
-// to [0, n-1].  Binning and list build both call this on the same stored
-// value, so an atom is always searched from the cell it was binned into.
-__device__ __forceinline__ int cell_coord(double w, double L, int n)
+// Cell coordinate of a wrapped coordinate w in [0, L): floor(w inv) with
+// inv = n / L (cells_per_length), clamped to [0, n-1].  Binning and list
+// build both call this with the same stored value and the same inv, so an
+// atom is always searched from the cell it was binned into.
+__device__ __forceinline__ double cells_per_length(int n, double L)
 {
-    int c = static_cast<int>(floor(w * static_cast<double>(n) / L));
+    return static_cast<double>(n) / L;
+}
+__device__ __forceinline__ int cell_coord(double w, double inv, int n)
+{
+    int c = static_cast<int>(floor(w * inv));
     return c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
 }
 
@@ -106,9 +111,16 @@ __device__ __forceinline__ bool sole_replica_gated_off(const uint32_t *gate, int
     return gate != nullptr && R == 1 && gate[0] == 0u;
 }
 
-// Wrap x into [0, L); returns the number of box lengths removed.
+// Wrap x into [0, L); returns the number of box lengths removed.  A
+// coordinate already inside [0, L) is returned as is (the general formula
+// gives the same value there), so only atoms that left the box pay for the
+// division.
 __device__ __forceinline__ double wrap_coord(double x, double L, int *shift)
 {
+    if (x >= 0.0 && x < L) {
+        *shift = 0;
+        return x;
+    }
     double f = floor(x / L);
     double w = x - L * f;
     if (w >= L) { w -= L; f += 1.0; }

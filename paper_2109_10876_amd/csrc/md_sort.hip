@@ -39,24 +39,30 @@ __device__ __forceinline__ bool gated_off(const BatchArgs &a, int rep)
 
 // Lanes of a wave that fall into the same cell take their slots with one
 // atomic add per distinct cell (consecutive atoms are mostly cell-mates).
-// Must be reached by every lane of the wave.
+// The groups are found first; then every group leader issues its add in one
+// instruction, so the wave waits for a single atomic round trip.  Must be
+// reached by every lane of the wave.
 __device__ __forceinline__ int aggregated_slot(int32_t *count, int c, bool active)
 {
     const int lane = __lane_id();
     unsigned long long todo = __ballot(active);
-    int slot = 0;
+    int leader_of_mine = lane, prefix = 0, group_size = 0;
     while (todo) {
         const int leader = __ffsll(static_cast<long long>(todo)) - 1;
         const int cl = __shfl(c, leader, kWave);
         const bool mine = active && c == cl;
         const unsigned long long grp = __ballot(mine);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(count + cl, __popcll(grp));
-        base = __shfl(base, leader, kWave);
-        if (mine) slot = base + __popcll(grp & ((1ull << lane) - 1ull));
+        if (mine) {
+            leader_of_mine = leader;
+            prefix = __popcll(grp & ((1ull << lane) - 1ull));
+        }
+        if (lane == leader) group_size = __popcll(grp);
         todo &= ~grp;
     }
-    return slot;
+    int base = 0;
+    if (group_size > 0) base = atomicAdd(count + c, group_size);
+    base = __shfl(base, leader_of_mine, kWave);
+    return base + prefix;
 }
 
 // Grid-stride loop over work units; a unit whose replica's gate is 0 is
@@ -83,9 +89,9 @@ __global__ __launch_bounds__(kUnit) void k_bin(BatchArgs a, const double *__rest
             const double *L = a.box + 3 * w.rep;
             const int32_t *n = a.ncell + 3 * w.rep;
             int s;
-            const int cx = cell_coord(wrap_coord(x[i], L[0], &s), L[0], n[0]);
-            const int cy = cell_coord(wrap_coord(y[i], L[1], &s), L[1], n[1]);
-            const int cz = cell_coord(wrap_coord(z[i], L[2], &s), L[2], n[2]);
+            const int cx = cell_coord(wrap_coord(x[i], L[0], &s), cells_per_length(n[0], L[0]), n[0]);
+            const int cy = cell_coord(wrap_coord(y[i], L[1], &s), cells_per_length(n[1], L[1]), n[1]);
+            const int cz = cell_coord(wrap_coord(z[i], L[2], &s), cells_per_length(n[2], L[2]), n[2]);
             c = a.cell_off[w.rep] + (cz * n[1] + cy) * n[0] + cx;
         }
         const int sl = aggregated_slot(cell_count, c, active);
@@ -96,9 +102,15 @@ __global__ __launch_bounds__(kUnit) void k_bin(BatchArgs a, const double *__rest
     }
 }
 
-// One workgroup of kScan threads per replica scans its cells in chunks of
-// 4 * kScan cells.
+// One workgroup of kScan threads per replica scans its cells in passes of
+// kScanPer * kScan cells.  Counts are read and starts written coalesced,
+// through LDS; each thread scans kScanPer consecutive cells from LDS (the
+// LDS index is skewed by one word per 32 so those reads do not collide).
 constexpr int kScan = 1024;
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kScanPer * kScan;
+
+__device__ __forceinline__ int scan_skew(int e) { return e + (e >> 5); }
 
 __global__ __launch_bounds__(kScan) void k_scan(BatchArgs a, int32_t *__restrict__ cell_count,
                                                 int32_t *__restrict__ cell_start)
@@ -107,16 +119,25 @@ __global__ __launch_bounds__(kScan) void k_scan(BatchArgs a, int32_t *__restrict
     if (gated_off(a, r)) return;
     constexpr int kW = kScan / kWave;
     __shared__ int32_t wsum[kW];
+    __shared__ int32_t buf[kScanTile + kScanTile / 32];
     const int c0 = a.cell_off[r], c1 = a.cell_off[r + 1];
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
     int32_t carry = a.atom_off[r];
-    for (int base = c0; base < c1; base += 4 * kScan) {
-        const int c = base + 4 * threadIdx.x;
-        int32_t v[4];
+    for (int base = c0; base < c1; base += kScanTile) {
+        int32_t g[kScanPer];
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const int c = base + k * kScan + tid;
+            g[k] = c < c1 ? cell_count[c] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) buf[scan_skew(k * kScan + tid)] = g[k];
+        __syncthreads();
+        int32_t v[kScanPer];
         int32_t t = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            v[k] = (c + k < c1) ? cell_count[c + k] : 0;
+        for (int k = 0; k < kScanPer; ++k) {
+            v[k] = buf[scan_skew(kScanPer * tid + k)];
             t += v[k];
         }
         int32_t inc = t;   // inclusive wave scan of the per-thread totals
@@ -128,6 +149,7 @@ __global__ __launch_bounds__(kScan) void k_scan(BatchArgs a, int32_t *__restrict
         if (lane == kWave - 1) wsum[wid] = inc;
         __syncthreads();
         int32_t before = 0, total = 0;
+#pragma unroll
         for (int k = 0; k < kW; ++k) {
             const int32_t ws = wsum[k];
             before += k < wid ? ws : 0;
@@ -135,14 +157,20 @@ __global__ __launch_bounds__(kScan) void k_scan(BatchArgs a, int32_t *__restrict
         }
         int32_t run = carry + before + inc - t;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (c + k < c1) {
-                cell_start[c + k] = run;
-                cell_count[c + k] = 0;
-            }
+        for (int k = 0; k < kScanPer; ++k) {
+            buf[scan_skew(kScanPer * tid + k)] = run;
             run += v[k];
         }
         carry += total;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const int c = base + k * kScan + tid;
+            if (c < c1) {
+                cell_start[c] = buf[scan_skew(k * kScan + tid)];
+                cell_count[c] = 0;
+            }
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) cell_start[c1] = a.atom_off[r + 1];
@@ -172,9 +200,17 @@ __global__ __launch_bounds__(kUnit) void k_gather(BatchArgs a, md_atoms in, md_a
         const int c = cell_of[i];
         const int s = cell_start[c], e = cell_start[c + 1];
         const int32_t me = in.id[i];
+        // rank among the cell's ids, read 16 bytes at a time from the
+        // 16-byte-aligned start at or below s (the key buffer is padded)
         int rank = 0;
-#pragma unroll 4
-        for (int m = s; m < e; ++m) rank += key[m] < me ? 1 : 0;
+        for (int m = s & ~3; m < e; m += 8) {
+            const int4 k0 = *reinterpret_cast<const int4 *>(key + m);
+            const int4 k1 = *reinterpret_cast<const int4 *>(key + m + 4);
+            const int kk[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                rank += (m + q >= s && m + q < e && kk[q] < me) ? 1 : 0;
+        }
         const int dst = s + rank;
         const double *L = a.box + 3 * w.rep;
         int sx, sy, sz;

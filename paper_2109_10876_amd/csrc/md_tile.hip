@@ -73,7 +73,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_build(TileArgs a)
             int dy, dz;
             const int i = home_atom(s, st, hk, dy, dz);
             const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
-            const int cx = min(max(cell_coord(xi, s.L[0], s.nx), s.a), s.b);
+            const int cx = min(max(cell_coord(xi, cells_per_length(s.nx, s.L[0]), s.nx), s.a), s.b);
             const int kc = cx - s.a;   // stage index of unwrapped cell cx - 1
             const int qc = staged_row(s, dy, dz);
             const int own = st.row_slot[qc] + st.cslot[qc][kc + 1] +
