@@ -2,7 +2,9 @@
 on one MI355X through libmd.
 
 Workload: FCC 64^3 x 4 sites at density 0.8442, Maxwell velocities at T = 1.0,
-rc = 2.5, skin = 0.3, dt = 0.005, energy-shifted LJ, full Verlet list.
+rc = 2.5, skin = 0.3, dt = 0.005, energy-shifted LJ, full Verlet list
+(the list form and launch shape chosen by the autotuner, untimed, unless
+--mode names one).
 One step = Integrate1 + skin test + (gated) re-sort and list build + forces
 with energy and virial + Integrate2 with kinetic energy -- every kernel of
 the path, nothing skipped.  Both pair-arithmetic precisions are run on the
@@ -24,13 +26,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+# MI355X vector peak, FMA counted as 2 flops: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 x 2.4 GHz.  FP64 runs at this rate, and so does FP32 issued one value per
+# lane (the 157.3 TFLOP/s FP32 figure needs packed two-wide FP32, which this
+# code does not use).
+VALU_PEAK_TFLOPS = 78.6
+# Algorithmic flops of the pair loop: every list entry pays the displacement
+# (3), r^2 (5) and the cutoff test (1); every pair inside rc the LJ terms:
+# 1/r^2 (1), q^3 (2), w = q^3 (A q^3 - B) (3), fr = w q (1), force
+# accumulation (6), energy (5) and virial (2).
+FLOPS_PER_ENTRY = 9
+FLOPS_PER_PAIR_IN_RC = 20
 
-# HBM bytes per md_lj_forces launch on this workload from rocprofv3 FETCH_SIZE
-# and WRITE_SIZE (calibrated against a plain copy), valid only for the kernel
-# source they were taken on (profiles/lj_forces_lj1m_hbm_counters.md).
+# Memory bytes per md_lj_forces launch on this workload from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (FETCH x 2.0, WRITE x 1.0: the factors a plain
+# 512 MiB device copy needs to read back its true size), valid only for the
+# kernel source they were taken on (profiles/k_tile_lj_lj1m_hbm_counters.md).
 # keyed by list form; each entry: source hash of the kernel's files and
 # calibrated bytes per launch for the FP32-mixed and FP64 paths
-COUNTED_TRAFFIC = {}
+COUNTED_TRAFFIC = {
+    "tile": {"src_sha256_16": "0e53ccb63ddc7c74",
+             "bytes_per_launch": {"mixed": 327786496, "fp64": 327941632}},
+}
 
 FORCE_KERNEL_SOURCES = {
     "full": ("md_forces.hip", "md_pair.hpp", "md_common.hpp"),
@@ -131,11 +148,24 @@ def time_workload(name, steps, warmup=10):
     import torch
     import md_inputs
     from paper_2109_10876_amd import MDSystem
+    from paper_2109_10876_amd import autotune
     cfg = md_inputs.CONFIGS[name]()
     lang = {"kg_melt": (0.5, 1.0, 3), "lj_slab": (1.0, 0.85, 4)}.get(name)
-    s = MDSystem(cfg.natoms, cfg.box, cfg.pos, cfg.vel, cfg.types, cfg.eps, cfg.sig, cfg.mass,
-                 rc=cfg.rc, skin=cfg.skin, dt=cfg.dt, shift=cfg.shift, bonds=cfg.bonds,
-                 langevin=lang, prec="mixed")
+    ntypes = int(np.atleast_2d(np.asarray(cfg.eps)).shape[0])
+
+    def make(mode="full", tile_cells=None, tile_rows=(1, 1)):
+        return MDSystem(cfg.natoms, cfg.box, cfg.pos, cfg.vel, cfg.types, cfg.eps, cfg.sig,
+                        cfg.mass, rc=cfg.rc, skin=cfg.skin, dt=cfg.dt, shift=cfg.shift,
+                        bonds=cfg.bonds, langevin=lang, prec="mixed", mode=mode,
+                        tile_cells=tile_cells, tile_rows=tile_rows)
+    if ntypes == 1:
+        # tile-local lists take one atom type: let the autotuner pick (untimed)
+        key = autotune.signature(cfg.natoms, cfg.box, cfg.rc, cfg.skin, ntypes)
+        tuned, _ = autotune.tune(make, key, steps=30, warmup=5, cache=None)
+    else:
+        tuned = {"mode": "full", "batch": 4}
+    autotune.apply(tuned)
+    s = make(tuned["mode"], tuned.get("tile_cells"), tuple(tuned.get("tile_rows", (1, 1))))
     s.setup()
     s.ensure_list()
     s.run_graphed(warmup, k=25)
@@ -148,7 +178,7 @@ def time_workload(name, steps, warmup=10):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     st = s.ensure_list()
-    out = {"N": s.N, "R": s.R, "steps": steps, "ms_per_step": ms / steps,
+    out = {"N": s.N, "R": s.R, "steps": steps, "ms_per_step": ms / steps, "launch": tuned,
            "atom_steps_per_s": s.N * steps / (ms * 1e-3), "status": st,
            "mean_list_entries": float(s.count.double().mean().item())}
     if name == "replicas":
@@ -255,10 +285,28 @@ def main():
         ebytes = 2.0 if tuned["mode"] == "tile" else 4.0
         bytes_launch = s.N * (ebytes * mean_k + 4 + 24 + 24)
         gbs = bytes_launch / (f_ms * 1e-3) / 1e9
-        traffic = None
+        # algorithmic flops of one launch: full list, so every unordered pair
+        # inside rc is visited from both ends
+        flops_launch = s.N * mean_k * FLOPS_PER_ENTRY + 2 * npairs * FLOPS_PER_PAIR_IN_RC
+        tfs = flops_launch / (f_ms * 1e-3) / 1e12
+        traffic = traffic_bytes = None
         counted = COUNTED_TRAFFIC.get(tuned["mode"])
         if counted and force_kernel_src_hash(tuned["mode"]) == counted["src_sha256_16"]:
-            traffic = counted["bytes_per_launch"][prec] / (f_ms * 1e-3) / 1e9
+            traffic_bytes = counted["bytes_per_launch"][prec]
+            traffic = traffic_bytes / (f_ms * 1e-3) / 1e9
+        kernel = "md_lj_forces (%s)" % ("k_tile_lj" if tuned["mode"] == "tile" else "k_lj")
+        hbm_view = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                    "bytes_per_launch": bytes_launch, "kernel": kernel}
+        if tuned["mode"] == "tile":
+            # LDS-staged neighbours: the pair loop is bound by vector issue
+            roof = {"bound": "alu", "achieved": tfs, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tfs / VALU_PEAK_TFLOPS, "traffic": traffic,
+                    "traffic_unit": "GB/s", "traffic_bytes_per_launch": traffic_bytes,
+                    "flops_per_launch": flops_launch, "kernel": kernel,
+                    "hbm_view": {k: hbm_view[k] for k in ("achieved", "frac", "bytes_per_launch")}}
+        else:
+            roof = hbm_view
         out[prec] = {
             "ms_per_step": ms / args.steps,
             "atom_steps_per_s": s.N * args.steps / (ms * 1e-3),
@@ -267,11 +315,7 @@ def main():
             "mean_list_entries": mean_k,
             "force_err_rel": None,
             "forces_kernel_ms": f_ms,
-            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
-                         "bytes_per_launch": bytes_launch,
-                         "kernel": "md_lj_forces (%s)" % ("k_tile_lj" if tuned["mode"] == "tile"
-                                                          else "k_lj")},
+            "roofline": roof,
         }
         log(f"[{prec}] {json.dumps(out[prec])}")
         del s
@@ -289,6 +333,7 @@ def main():
         "config": {"workload": "LJ fluid FCC 64^3x4 N=1048576 rho=0.8442 T=1.0 rc=2.5 "
                                "skin=0.3 dt=0.005 NVE", "N": cfg.n, "launch": tuned},
         "pair_evals_per_s": m["pair_evals_per_s"],
+        "forces_kernel_ms": m["forces_kernel_ms"],
         "force_err_rel": m["force_err_rel"],
         "roofline": m["roofline"],
         "fp64": {k: out["fp64"][k] for k in ("atom_steps_per_s", "pair_evals_per_s",
