@@ -95,7 +95,7 @@ extern "C" {
  * neighbour in its tile's staged sequence (its image is the one its staged
  * row and cell imply).  Entries count[i] .. (count[i] rounded up to 16) - 1
  * hold 8 md_tile_capacity(), a pad slot far from every atom, so max_nbr
- * must be a multiple of 16 (MD_EINVAL otherwise).  A tile whose staged
+ * must be a multiple of 16, and ld at most 2^23 (MD_EINVAL otherwise).  A tile whose staged
  * sequence exceeds md_tile_capacity() (at most MD_TILE_SLOTS) raises
  * MD_F_TILE_OVERFLOW (the list is then unusable: rebuild with smaller
  * tiles).  Tile-local lists take one atom type (md_lj_forces returns

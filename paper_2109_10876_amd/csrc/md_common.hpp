@@ -164,6 +164,41 @@ __device__ __forceinline__ double wave_max(double v)
 
 // Block-level sum over kUnit threads in a fixed order; result valid in
 // thread 0.  `lds` must hold kWavesPerUnit doubles.
+// Block-wide fixed-order reductions over NT threads (NT a multiple of the
+// wave size); the result is valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum_n(double v, double *lds)
+{
+    v = wave_sum(v);
+    if (NT == kWave) return v;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / kWave; ++k) s += lds[k];
+    __syncthreads();
+    return s;
+}
+template <int NT>
+__device__ __forceinline__ double block_max_n(double v, double *lds)
+{
+    v = wave_max(v);
+    if (NT == kWave) return v;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double m = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / kWave; ++k) m = fmax(m, lds[k]);
+    __syncthreads();
+    return m;
+}
+
+// Threads of the per-replica finalize kernels: each sums every kFin-th
+// partial in order (a fixed order for a fixed kFin), several loads in flight.
+constexpr int kFin = 1024;
+
 __device__ __forceinline__ double block_sum(double v, double *lds)
 {
     v = wave_sum(v);

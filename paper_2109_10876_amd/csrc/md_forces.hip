@@ -192,20 +192,21 @@ __global__ __launch_bounds__(kUnit) void k_zero3(int32_t N, double *fx, double *
 
 // One workgroup per replica: fixed-order sum of slot `k0` (and `k0+1`) of its
 // work units' partials.
-__global__ __launch_bounds__(kUnit) void k_finalize_sum2(const int32_t *unit_off,
-                                                         const double *partial, int k0,
-                                                         double *out0, double *out1)
+__global__ __launch_bounds__(kFin) void k_finalize_sum2(const int32_t *unit_off,
+                                                        const double *partial, int k0,
+                                                        double *out0, double *out1)
 {
-    __shared__ double red[kWavesPerUnit];
+    __shared__ double red[kFin / kWave];
     const int r = blockIdx.x;
     const int u0 = unit_off[r], u1 = unit_off[r + 1];
     double s0 = 0.0, s1 = 0.0;
-    for (int u = u0 + threadIdx.x; u < u1; u += kUnit) {
+#pragma unroll 4
+    for (int u = u0 + threadIdx.x; u < u1; u += kFin) {
         s0 += partial[size_t(u) * kPartials + k0];
         s1 += partial[size_t(u) * kPartials + k0 + 1];
     }
-    s0 = block_sum(s0, red);
-    s1 = block_sum(s1, red);
+    s0 = block_sum_n<kFin>(s0, red);
+    s1 = block_sum_n<kFin>(s1, red);
     if (threadIdx.x == 0) {
         if (out0) out0[r] = s0;
         if (out1) out1[r] = s1;
@@ -254,7 +255,7 @@ void launch_lj(const ForceArgs &a, int n_units, int prec, bool half, bool typed,
 void launch_finalize_sum2(int R, const int32_t *unit_off, const double *partial, int k0,
                           double *out0, double *out1, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize_sum2, dim3(R), dim3(kUnit), 0, s, unit_off, partial, k0,
+    hipLaunchKernelGGL(k_finalize_sum2, dim3(R), dim3(kFin), 0, s, unit_off, partial, k0,
                        out0, out1);
 }
 

@@ -41,14 +41,51 @@ struct TileArgs {
     int32_t R;
 };
 
-constexpr int kCandBatch = 8;
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Tile-list builds form column byte offsets with 24-bit multiplies (and the
+// whole list must span less than 4 GiB).
+constexpr int kTileMaxLd = 1 << 23;
+// Home cells with at most kFlatChunks x 64 stencil candidates take the
+// register path (a multiple of 3: chunks are tested three at a time).
+constexpr int kFlatChunks = 12;
+
+// Lanes 0 .. nb-1 of a wavefront hold the entry counts of home atoms
+// hb .. hb+nb-1: store them, flag overflow, or pad each column to a multiple
+// of 16 entries (max_nbr is one) with the pad slot, so force loops need no
+// tail mask.
+__device__ __forceinline__ void tile_finish_counts(const TileArgs &a, int hb, int nb, int lane,
+                                                   int vcnt, int cap)
+{
+    if (lane >= nb) return;
+    const int i = hb + lane;
+    a.count[i] = vcnt;
+    if (vcnt > a.max_nbr) {
+        if (a.status) atomicOr(a.status, MD_F_NBR_OVERFLOW);
+        if (a.need) atomicMax(a.need, vcnt);
+        return;
+    }
+    const int padded = (vcnt + 15) & ~15;
+    for (int k = vcnt; k < padded; ++k) a.idx[size_t(k) * a.ld + i] = uint16_t(cap * 8);
+}
+
+// List build, one wavefront per home cell.  The lanes hold up to 64 staged
+// candidates of one stencil row (nine contiguous slot ranges, one per row of
+// the cell's 27-cell stencil) and the wave visits the cell's home atoms in
+// turn, so every lane runs the same loop.  A home atom's hits are placed by
+// a ballot and the count of hitting lanes below each lane: entries come out
+// in stencil-row order, then ascending slot.  Per-atom counts live one per
+// lane of a batch of up to 64 home atoms.
 template <class SH, bool P4>
-__global__ __launch_bounds__(SH::TB) void k_tile_build(TileArgs a)
+__global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) void k_tile_build(
+    TileArgs a)
 {
     constexpr int TB = SH::TB, CAP = SH::CAP;
+    constexpr int kWaves = TB / kWave;
     __shared__ TileStage<CAP, SH::MAXC> st;
     if (sole_replica_gated_off(a.gate, a.R)) return;
+    const int lane = __lane_id();
+    const int wid = uniform(threadIdx.x / kWave);
     for (int lt = blockIdx.x; lt < a.n_tiles; lt += gridDim.x) {
         const int t = xcd_swizzle(lt, a.n_tiles);
         const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
@@ -62,73 +99,127 @@ __global__ __launch_bounds__(SH::TB) void k_tile_build(TileArgs a)
             __syncthreads();
             continue;
         }
-        const int nh = st.home_start[s.hy * s.hz];
-        const double hx = s.L[0] / s.nx, hy = s.L[1] / s.ny, hz = s.L[2] / s.nz;
-        // a neighbour cell is skipped when the distance from the atom to the
-        // cell's box is at least r_l (with a relative margin far above
-        // rounding, so no pair inside r_l is ever dropped)
-        const double cull2 = a.rl2 * (1.0 + 1e-10);
-        const uint32_t lastoff = uint32_t(a.max_nbr - 1) * uint32_t(a.ld);
-        for (int hk = threadIdx.x; hk < nh; hk += TB) {
-            int dy, dz;
-            const int i = home_atom(s, st, hk, dy, dz);
-            const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
-            const int cx = min(max(cell_coord(xi, cells_per_length(s.nx, s.L[0]), s.nx), s.a), s.b);
-            const int kc = cx - s.a;   // stage index of unwrapped cell cx - 1
+        const int ncx = s.b - s.a + 1;
+        const int nhc = ncx * s.hy * s.hz;
+        for (int hc = wid; hc < nhc; hc += kWaves) {
+            const int kc = hc % ncx, hrow = hc / ncx;   // kc: stage index of cell cx - 1
+            const int dy = hrow % s.hy, dz = hrow / s.hy;
             const int qc = staged_row(s, dy, dz);
-            const int own = st.row_slot[qc] + st.cslot[qc][kc + 1] +
-                            (i - a.cell_start[st.row_rb[qc] + cx]);
-            // squared gaps to the lower / upper faces of the atom's cell
-            const double gxl = fmax(xi - cx * hx, 0.0), gxr = fmax((cx + 1) * hx - xi, 0.0);
-            const int cy = s.y0 + dy, cz = s.z0 + dz;
-            const double gyl = fmax(yi - cy * hy, 0.0), gyr = fmax((cy + 1) * hy - yi, 0.0);
-            const double gzl = fmax(zi - cz * hz, 0.0), gzr = fmax((cz + 1) * hz - zi, 0.0);
-            uint16_t *col = a.idx + i;
-            uint32_t off = 0;   // element offset of the next entry, clamped to the last column
-            int cnt = 0;
+            const int cell = uniform(st.row_rb[qc]) + s.a + kc;
+            const int g0 = uniform(a.cell_start[cell]), g1 = uniform(a.cell_start[cell + 1]);
+            const int own0 = uniform(st.row_slot[qc] + st.cslot[qc][kc + 1]);
+            const size_t ld2 = size_t(a.ld) * sizeof(uint16_t);
+            // The nine stencil rows of this home cell: first slot, length.
+            int rs0[9], rlen[9];
+#pragma unroll
             for (int r9 = 0; r9 < 9; ++r9) {
-                const int oy = r9 % 3 - 1, oz = r9 / 3 - 1;
-                const double gy = oy < 0 ? gyl : (oy > 0 ? gyr : 0.0);
-                const double gz = oz < 0 ? gzl : (oz > 0 ? gzr : 0.0);
-                const double g2 = gy * gy + gz * gz;
-                if (g2 >= cull2) continue;
-                const int r = staged_row(s, dy + oy, dz + oz);
-                const int k0 = kc + (g2 + gxl * gxl < cull2 ? 0 : 1);
-                const int k1 = kc + (g2 + gxr * gxr < cull2 ? 3 : 2);
-                const int s0 = st.row_slot[r] + st.cslot[r][k0];
-                const int s1 = st.row_slot[r] + st.cslot[r][k1];
-                for (int sb = s0; sb < s1; sb += kCandBatch) {
-                    double px[kCandBatch], py[kCandBatch], pz[kCandBatch];
+                const int r = staged_row(s, dy + r9 % 3 - 1, dz + r9 / 3 - 1);
+                rs0[r9] = uniform(st.row_slot[r] + st.cslot[r][kc]);
+                rlen[r9] = uniform(st.row_slot[r] + st.cslot[r][kc + 3]) - rs0[r9];
+            }
+            // The nine rows concatenated in stencil order form the cell's
+            // candidate sequence; flat index f of row q maps to slot
+            // rs0[q] + f - pref[q].
+            int pref[9];
+            int T = 0;
 #pragma unroll
-                    for (int q = 0; q < kCandBatch; ++q) {
-                        const int sl = min(sb + q, s1 - 1);
-                        px[q] = st.x[sl];
-                        py[q] = st.y[sl];
-                        pz[q] = st.z[sl];
+            for (int r9 = 0; r9 < 9; ++r9) {
+                pref[r9] = T;
+                T += rlen[r9];
+            }
+            if (T <= kFlatChunks * kWave) {
+                // Fast path: chunk c of the sequence (flat 64 c + lane) sits
+                // in registers; each home atom tests the chunks in groups of
+                // three with no branch inside a group, so the scheduler can
+                // interleave them; the home atom's count is a scalar.
+                double px[kFlatChunks], py[kFlatChunks], pz[kFlatChunks];
+                int ent[kFlatChunks];
+#pragma unroll
+                for (int c = 0; c < kFlatChunks; ++c) {
+                    const int f = min(c * kWave + lane, T - 1);
+                    int slot = rs0[0] + f;
+#pragma unroll
+                    for (int q = 1; q < 9; ++q)
+                        slot += f >= pref[q] ? rs0[q] - rs0[q - 1] - rlen[q - 1] : 0;
+                    px[c] = st.x[slot];
+                    py[c] = st.y[slot];
+                    pz[c] = st.z[slot];
+                    ent[c] = slot * 8;
+                }
+                const int nch = (T + kWave - 1) / kWave;
+                const unsigned ld2u = unsigned(ld2);
+                for (int hb = g0; hb < g1; hb += kWave) {
+                    const int nb = min(kWave, g1 - hb);
+                    int vcnt = 0;   // lane j: entries of home atom hb + j
+                    for (int j = 0; j < nb; ++j) {
+                        const int hs = own0 + (hb - g0) + j;
+                        const double hx = st.x[hs], hy = st.y[hs], hz = st.z[hs];
+                        const int fown = pref[4] + (hs - rs0[4]);   // own slot in the sequence
+                        char *col = reinterpret_cast<char *>(a.idx + (hb + j));
+                        int cnt = 0;
+#pragma unroll
+                        for (int g = 0; g < kFlatChunks; g += 3) {
+                            if (g >= nch) break;
+#pragma unroll
+                            for (int c = g; c < g + 3; ++c) {
+                                const int left = T - c * kWave;   // valid lanes of chunk c
+                                const uint64_t vm = left >= kWave ? ~uint64_t(0)
+                                                    : (left <= 0 ? 0 : (uint64_t(1) << left) - 1);
+                                const int lown = fown - c * kWave;   // own lane if in [0, 64)
+                                const uint64_t om = (lown >= 0 && lown < kWave)
+                                                        ? ~(uint64_t(1) << lown) : ~uint64_t(0);
+                                const double dx = hx - px[c], dyy = hy - py[c], dzz = hz - pz[c];
+                                const bool near = dx * dx + dyy * dyy + dzz * dzz < a.rl2;
+                                const uint64_t m = __builtin_amdgcn_ballot_w64(near) & vm & om;
+                                const int k = cnt + int(__builtin_amdgcn_mbcnt_hi(
+                                                        uint32_t(m >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
+                                // past max_nbr entries are not stored (the
+                                // count still grows and flags the overflow)
+                                if (near && lane < left && lane != lown && k < a.max_nbr)
+                                    *reinterpret_cast<uint16_t *>(
+                                        col + size_t(unsigned(__umul24(unsigned(k), ld2u)))) =
+                                        uint16_t(ent[c]);
+                                cnt += int(__popcll(m));
+                            }
+                        }
+                        vcnt = lane == j ? cnt : vcnt;
                     }
-#pragma unroll
-                    for (int q = 0; q < kCandBatch; ++q) {
-                        const int sl = sb + q;
-                        const double dx = xi - px[q], dy2 = yi - py[q], dz2 = zi - pz[q];
-                        const bool take = (sl < s1) & (sl != own) &
-                                          (dx * dx + dy2 * dy2 + dz2 * dz2 < a.rl2);
-                        // past max_nbr entries land in the last column (the
-                        // count still grows and flags the overflow)
-                        if (take) col[off] = uint16_t(sl * 8);
-                        cnt += take ? 1 : 0;
-                        off = take ? min(off + uint32_t(a.ld), lastoff) : off;
+                    tile_finish_counts(a, hb, nb, lane, vcnt, CAP);
+                }
+                continue;
+            }
+            for (int hb = g0; hb < g1; hb += kWave) {
+                const int nb = min(kWave, g1 - hb);
+                int vcnt = 0;   // lane j: entries of home atom hb + j so far
+                for (int r9 = 0; r9 < 9; ++r9) {
+                    const int s0 = rs0[r9], s1 = rs0[r9] + rlen[r9];
+                    for (int cb = s0; cb < s1; cb += kWave) {
+                        const int sl = cb + lane;
+                        const bool valid = sl < s1;
+                        const int sc = valid ? sl : s1 - 1;
+                        const double px = st.x[sc], py = st.y[sc], pz = st.z[sc];
+                        const uint16_t ent = uint16_t(sl * 8);
+                        for (int j = 0; j < nb; ++j) {
+                            const int hs = own0 + (hb - g0) + j;   // the home atom's own slot
+                            const double dx = st.x[hs] - px, dyy = st.y[hs] - py,
+                                         dzz = st.z[hs] - pz;
+                            const bool take = valid & (sl != hs) &
+                                              (dx * dx + dyy * dyy + dzz * dzz < a.rl2);
+                            const uint64_t m = __builtin_amdgcn_ballot_w64(take);
+                            const int cnt = __builtin_amdgcn_readlane(vcnt, j);
+                            const int k = cnt + int(__builtin_amdgcn_mbcnt_hi(
+                                                    uint32_t(m >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
+                            if (take && k < a.max_nbr) {
+                                char *col = reinterpret_cast<char *>(a.idx + (hb + j));
+                                *reinterpret_cast<uint16_t *>(col + size_t(unsigned(k)) * ld2) = ent;
+                            }
+                            vcnt = lane == j ? cnt + int(__popcll(m)) : vcnt;
+                        }
                     }
                 }
-            }
-            a.count[i] = cnt;
-            if (cnt > a.max_nbr) {
-                if (a.status) atomicOr(a.status, MD_F_NBR_OVERFLOW);
-                if (a.need) atomicMax(a.need, cnt);
-            } else {
-                // pad to a multiple of 16 entries (max_nbr is one) with the
-                // pad slot, so force loops need no tail mask
-                const int padded = (cnt + 15) & ~15;
-                for (int k = cnt; k < padded; ++k) col[size_t(k) * a.ld] = uint16_t(CAP * 8);
+                tile_finish_counts(a, hb, nb, lane, vcnt, CAP);
             }
         }
         __syncthreads();
@@ -210,8 +301,8 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
             if (a.status && !isfinite(c.fx + c.fy + c.fz + ed)) atomicOr(a.status, MD_F_NONFINITE);
         }
     }
-    const double es = block_sum_t<TB>(e_acc, red);
-    const double ws = block_sum_t<TB>(w_acc, red);
+    const double es = block_sum_n<TB>(e_acc, red);
+    const double ws = block_sum_n<TB>(w_acc, red);
     if (threadIdx.x == 0) {
         a.tpart[size_t(t) * 2 + 0] = es;
         a.tpart[size_t(t) * 2 + 1] = ws;
@@ -219,19 +310,20 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
 }
 
 // Per replica: fixed-order sums of its tiles' partials.
-__global__ __launch_bounds__(kUnit) void k_tile_finalize(const int32_t *tile_off,
-                                                         const double *tpart, double *energy,
-                                                         double *virial)
+__global__ __launch_bounds__(kFin) void k_tile_finalize(const int32_t *tile_off,
+                                                        const double *tpart, double *energy,
+                                                        double *virial)
 {
-    __shared__ double red[kWavesPerUnit];
+    __shared__ double red[kFin / kWave];
     const int r = blockIdx.x;
     double s0 = 0.0, s1 = 0.0;
-    for (int t = tile_off[r] + threadIdx.x; t < tile_off[r + 1]; t += kUnit) {
+#pragma unroll 4
+    for (int t = tile_off[r] + threadIdx.x; t < tile_off[r + 1]; t += kFin) {
         s0 += tpart[size_t(t) * 2];
         s1 += tpart[size_t(t) * 2 + 1];
     }
-    s0 = block_sum(s0, red);
-    s1 = block_sum(s1, red);
+    s0 = block_sum_n<kFin>(s0, red);
+    s1 = block_sum_n<kFin>(s1, red);
     if (threadIdx.x == 0) {
         if (energy) energy[r] = s0;
         if (virial) virial[r] = s1;
@@ -268,7 +360,8 @@ bool tile_stage_packed() { return md_tune_get(MD_TUNE_TILE_STAGE_PACKED) != 0; }
 bool tile_list_ok(const md_batch *b, const md_nlist *nl)
 {
     return nl->n_tiles >= 1 && nl->n_tiles <= b->C && nl->tile_rep && nl->tile_off &&
-           nl->max_nbr % 16 == 0 &&
+           nl->max_nbr % 16 == 0 && nl->ld <= kTileMaxLd &&
+           size_t(nl->max_nbr) * size_t(nl->ld) * 2 < (size_t(1) << 32) &&
            nl->tile_cells >= 1 && nl->tile_cells <= tile_max_cells() && nl->tile_py >= 1 &&
            nl->tile_py <= MD_TILE_MAX_ROWS && nl->tile_pz >= 1 && nl->tile_pz <= MD_TILE_MAX_ROWS;
 }
@@ -367,7 +460,7 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
 #undef MD_TILE_LAUNCH
     });
     if (energy || virial)
-        hipLaunchKernelGGL(k_tile_finalize, dim3(b->R), dim3(kUnit), 0, s, nl->tile_off, tpart,
+        hipLaunchKernelGGL(k_tile_finalize, dim3(b->R), dim3(kFin), 0, s, nl->tile_off, tpart,
                            energy, virial);
     return launch_status();
 }

@@ -36,22 +36,6 @@ using TileShape256S2048 = TileShape<256, 2048, 16>;
 using TileShape256S1536 = TileShape<256, 1536, 8>;
 static_assert(TileShape256::CAP == MD_TILE_SLOTS, "largest shape holds MD_TILE_SLOTS");
 
-// Block-wide fixed-order sum over TB threads; result valid in thread 0.
-template <int TB>
-__device__ __forceinline__ double block_sum_t(double v, double *lds)
-{
-    v = wave_sum(v);
-    if (TB == kWave) return v;
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-    if (lane == 0) lds[wid] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int k = 0; k < TB / kWave; ++k) s += lds[k];
-    __syncthreads();
-    return s;
-}
-
 struct TileSpec {
     int rep, nx, ny, nz, coff;
     int a, b;        // home cells along x

@@ -76,20 +76,21 @@ __global__ __launch_bounds__(kUnit) void k_vv(VVArgs a)
 }
 
 // Per replica: kinetic energy (fixed-order sum) and the rebuild gate.
-__global__ __launch_bounds__(kUnit) void k_vv_finalize(const int32_t *unit_off,
-                                                       const double *partial, double lim2,
-                                                       double *ke, uint32_t *gate)
+__global__ __launch_bounds__(kFin) void k_vv_finalize(const int32_t *unit_off,
+                                                      const double *partial, double lim2,
+                                                      double *ke, uint32_t *gate)
 {
-    __shared__ double red[kWavesPerUnit];
+    __shared__ double red[kFin / kWave];
     const int r = blockIdx.x;
     const int u0 = unit_off[r], u1 = unit_off[r + 1];
     double s = 0.0, m = 0.0;
-    for (int u = u0 + threadIdx.x; u < u1; u += kUnit) {
+#pragma unroll 4
+    for (int u = u0 + threadIdx.x; u < u1; u += kFin) {
         if (ke) s += partial[size_t(u) * kPartials + 2];
         if (gate) m = fmax(m, partial[size_t(u) * kPartials + 3]);
     }
-    s = block_sum(s, red);
-    m = block_max(m, red);
+    s = block_sum_n<kFin>(s, red);
+    m = block_max_n<kFin>(m, red);
     if (threadIdx.x == 0) {
         if (ke) ke[r] = s;
         if (gate) gate[r] = m > lim2 ? 1u : 0u;
@@ -128,7 +129,7 @@ extern "C" int md_vv_step(const md_batch *b, md_atoms *atoms, int32_t phase, dou
     double *ke_out = phase >= 2 ? ke : nullptr;
     uint32_t *gate_out = phase != 2 ? gate : nullptr;
     if (ke_out || gate_out)
-        hipLaunchKernelGGL(k_vv_finalize, dim3(b->R), block, 0, s, b->unit_off, partial,
+        hipLaunchKernelGGL(k_vv_finalize, dim3(b->R), dim3(kFin), 0, s, b->unit_off, partial,
                            0.25 * skin * skin, ke_out, gate_out);
     return launch_status();
 }
