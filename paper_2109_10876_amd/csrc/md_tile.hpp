@@ -99,6 +99,8 @@ struct TileStage {
     int cslot[kMaxStagedRows][kRowStage];  // start (within the row) of unwrapped cell a-1+k
     int home_start[kMaxHomeRows + 1];  // prefix of home atoms over the home rows
     int home_g0[kMaxHomeRows];         // first atom of each home row's run a..b
+    static constexpr int kChunks = CAP / 64 + 1;
+    int rowc[kChunks];                 // staged row holding slot 64 c (first row if several)
 };
 
 // Coordinate of the pad slot: every distance to it is far beyond any cutoff
@@ -122,89 +124,101 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
 {
     const int tid = threadIdx.x;
     const int nhome = s.hy * s.hz;
+    const int nk = s.b - s.a + 4;       // cell starts a-1 .. b+2 per staged row
+    const int nq = s.nrows * nk;
+    const int lo = max(s.a - 1, 0), hi = min(s.b + 1, s.nx - 1);
     __syncthreads();   // readers of the previous tile are done with st
     if (tid == TB - 1) {
         st.x[Stage::kCap] = kPadCoord;
         st.y[Stage::kCap] = kPadCoord;
         st.z[Stage::kCap] = kPadCoord;
     }
-    if (tid < s.nrows) {
-        const int zr = tid / (s.hy + 2), yr = tid % (s.hy + 2);
+    // Phase 1, global loads only: every (row, cell) start, and per row the
+    // bounds of its three pieces (left wrap, main run, right wrap).
+    for (int t = tid; t < nq; t += TB) {
+        const int q = t / nk, k = t % nk;
+        const int zr = q / (s.hy + 2), yr = q % (s.hy + 2);
         int az = s.z0 - 1 + zr, ay = s.y0 - 1 + yr;
         double dz = 0.0, dy = 0.0;
         // a row reached across a face holds atoms one box length away
         if (az < 0) { az += s.nz; dz = -s.L[2]; } else if (az >= s.nz) { az -= s.nz; dz = s.L[2]; }
         if (ay < 0) { ay += s.ny; dy = -s.L[1]; } else if (ay >= s.ny) { ay -= s.ny; dy = s.L[1]; }
         const int rb = s.coff + (az * s.ny + ay) * s.nx;
-        const int lo = max(s.a - 1, 0), hi = min(s.b + 1, s.nx - 1);
-        const int c_last = cs[rb + s.nx - 1], c_end = cs[rb + s.nx];
-        const int c_first = cs[rb], c_second = cs[rb + 1];
-        const int m0 = cs[rb + lo], m1 = cs[rb + hi + 1];
-        st.row_rb[tid] = rb;
-        st.row_lo[tid] = lo;
-        st.row_lw[tid] = s.a - 1 < 0 ? c_end - c_last : 0;
-        st.row_main[tid] = m1 - m0;
-        st.row_rw[tid] = s.b + 1 >= s.nx ? c_second - c_first : 0;
-        st.row_g0[tid][0] = c_last;
-        st.row_g0[tid][1] = m0;
-        st.row_g0[tid][2] = c_first;
-        st.row_dy[tid] = dy;
-        st.row_dz[tid] = dz;
-    } else if (tid >= kMaxStagedRows && tid < kMaxStagedRows + nhome) {
-        const int h = tid - kMaxStagedRows;
+        const int xu = s.a - 1 + k;
+        st.cslot[q][k] = (xu >= 0 && xu < s.nx) ? cs[rb + xu] : 0;
+        if (k == 0) {
+            const int c_last = cs[rb + s.nx - 1], c_end = cs[rb + s.nx];
+            const int c_first = cs[rb], c_second = cs[rb + 1];
+            const int m0 = cs[rb + lo], m1 = cs[rb + hi + 1];
+            st.row_rb[q] = rb;
+            st.row_lo[q] = lo;
+            st.row_lw[q] = s.a - 1 < 0 ? c_end - c_last : 0;
+            st.row_main[q] = m1 - m0;
+            st.row_rw[q] = s.b + 1 >= s.nx ? c_second - c_first : 0;
+            st.row_g0[q][0] = c_last;
+            st.row_g0[q][1] = m0;
+            st.row_g0[q][2] = c_first;
+            st.row_dy[q] = dy;
+            st.row_dz[q] = dz;
+        }
+    }
+    if (tid >= TB - kMaxHomeRows && tid - (TB - kMaxHomeRows) < nhome) {
+        const int h = tid - (TB - kMaxHomeRows);
         const int rb = s.coff + ((s.z0 + h / s.hy) * s.ny + (s.y0 + h % s.hy)) * s.nx;
         const int g0 = cs[rb + s.a];
         st.home_g0[h] = g0;
         st.home_start[h + 1] = cs[rb + s.b + 1] - g0;   // count, summed below
     }
     __syncthreads();
-    if (tid == 0) {
-        int acc = 0;
-        for (int q = 0; q < s.nrows; ++q) {
-            st.row_slot[q] = acc;
-            acc += st.row_lw[q] + st.row_main[q] + st.row_rw[q];
-        }
-        st.row_slot[s.nrows] = acc;
-        int hacc = 0;
-        st.home_start[0] = 0;
-        for (int h = 0; h < nhome; ++h) {
-            hacc += st.home_start[h + 1];
-            st.home_start[h + 1] = hacc;
-        }
-    }
-    const int nk = s.b - s.a + 4;
-    for (int q = tid; q < s.nrows * nk; q += TB) {
-        const int r = q / nk, k = q % nk, xu = s.a - 1 + k;
-        const int lw = st.row_lw[r], mn = st.row_main[r];
+    // Phase 2, LDS only: cell starts within the row; wave 0 scans the row
+    // lengths into row starts (and the chunk -> row table) and the home
+    // counts into home starts.
+    for (int t = tid; t < nq; t += TB) {
+        const int q = t / nk, k = t % nk, xu = s.a - 1 + k;
+        const int lw = st.row_lw[q], mn = st.row_main[q];
         int off;
         if (xu < 0) off = 0;
-        else if (xu < s.nx) off = lw + (cs[st.row_rb[r] + xu] - cs[st.row_rb[r] + st.row_lo[r]]);
+        else if (xu < s.nx) off = lw + (st.cslot[q][k] - st.row_g0[q][1]);
         else if (xu == s.nx) off = lw + mn;
-        else off = lw + mn + st.row_rw[r];
-        st.cslot[r][k] = off;
+        else off = lw + mn + st.row_rw[q];
+        st.cslot[q][k] = off;
+    }
+    if (tid < kWave) {
+        const int len = tid < s.nrows ? st.row_lw[tid] + st.row_main[tid] + st.row_rw[tid] : 0;
+        const int hc = (tid >= 1 && tid <= nhome) ? st.home_start[tid] : 0;
+        int pl = len, ph = hc;   // inclusive prefix sums over the lanes
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int ul = __shfl_up(pl, o, kWave), uh = __shfl_up(ph, o, kWave);
+            if (tid >= o) {
+                pl += ul;
+                ph += uh;
+            }
+        }
+        if (tid < s.nrows) {
+            const int start = pl - len;
+            st.row_slot[tid] = start;
+            if (tid == s.nrows - 1) st.row_slot[s.nrows] = pl;
+            for (int c = (start + 63) >> 6; c * 64 < pl && c < Stage::kChunks; ++c) st.rowc[c] = tid;
+        }
+        if (tid <= nhome) st.home_start[tid] = ph;   // lane 0: 0
     }
     __syncthreads();
     const int total = st.row_slot[s.nrows];
     if (total > cap) return total;
     if (total > 0) {
-        // Row starts are the same for the whole workgroup: keep them in
-        // scalar registers and find a slot's row by counting starts <= slot.
-        int rs[kMaxStagedRows];
-#pragma unroll
-        for (int q = 1; q < kMaxStagedRows; ++q)
-            rs[q] = q < s.nrows ? __builtin_amdgcn_readfirstlane(st.row_slot[q]) : INT_MAX;
         // Slots tid, tid + TB, ...: first resolve every slot's source atom and
-        // image shift, then issue all loads together (lanes past the end
-        // re-read the last slot's atom), then write LDS.
+        // image shift (the row from the chunk table, then forward over rows
+        // that end inside the chunk), then issue all loads together (lanes
+        // past the end re-read the last slot's atom), then write LDS.
         constexpr int kPer = (Stage::kCap + TB - 1) / TB;
         int src[kPer], rowof[kPer];
         double sxk[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int sl = min(tid + k * TB, total - 1);
-            int r = 0;
-#pragma unroll
-            for (int q = 1; q < kMaxStagedRows; ++q) r += sl >= rs[q] ? 1 : 0;
+            int r = st.rowc[sl >> 6];
+            while (sl >= st.row_slot[r + 1]) ++r;
             const int off = sl - st.row_slot[r];
             const int lw = st.row_lw[r], mn = st.row_main[r];
             const int piece = off < lw ? 0 : (off < lw + mn ? 1 : 2);
