@@ -27,7 +27,7 @@ struct WsLayout {
     size_t cell_count;   // C x int32
     size_t cell_of;      // N x int32
     size_t slot;         // N x int32
-    size_t key;          // N (+16 padding) x int32
+    size_t key;          // N (+16 padding: 64-byte reads) x int32
     size_t vjp_partial;  // n_units x 2 x MD_MAX_TYPES^2 doubles
     size_t tile_partial; // C x 2 doubles (tiles never outnumber cells)
     size_t total;
@@ -45,7 +45,7 @@ inline WsLayout ws_layout(const md_batch *b)
     l.cell_count = o;  o = align256(o + size_t(b->C) * sizeof(int32_t));
     l.cell_of = o;     o = align256(o + size_t(b->N) * sizeof(int32_t));
     l.slot = o;        o = align256(o + size_t(b->N) * sizeof(int32_t));
-    l.key = o;         o = align256(o + (size_t(b->N) + 16) * sizeof(int32_t));   // 16 B reads may pass the end
+    l.key = o;         o = align256(o + (size_t(b->N) + 16) * sizeof(int32_t));   // 64 B reads may pass the end
     l.vjp_partial = o; o = align256(o + size_t(b->n_units) * 2 * MD_MAX_TYPES * MD_MAX_TYPES * sizeof(double));
     l.tile_partial = o; o = align256(o + size_t(b->C) * 2 * sizeof(double));
     l.total = o;

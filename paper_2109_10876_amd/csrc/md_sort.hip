@@ -197,34 +197,45 @@ __global__ __launch_bounds__(kUnit) void k_gather(BatchArgs a, md_atoms in, md_a
     MD_FOR_UNITS(a, w) {
         const int i = w.begin + threadIdx.x;
         if (i >= w.end) continue;
+        // every input of the atom is loaded first, so these loads overlap
+        // the dependent cell-start and key reads of the rank search
+        const double x0 = in.x[i], y0 = in.y[i], z0 = in.z[i];
+        const double vx = in.vx[i], vy = in.vy[i], vz = in.vz[i];
+        const int32_t ty = in.type[i], me = in.id[i];
+        const int32_t ix = in.img[i], iy = in.img[N + i], iz = in.img[2 * N + i];
         const int c = cell_of[i];
         const int s = cell_start[c], e = cell_start[c + 1];
-        const int32_t me = in.id[i];
         // rank among the cell's ids, read 16 bytes at a time from the
         // 16-byte-aligned start at or below s (the key buffer is padded)
         int rank = 0;
-        for (int m = s & ~3; m < e; m += 8) {
-            const int4 k0 = *reinterpret_cast<const int4 *>(key + m);
-            const int4 k1 = *reinterpret_cast<const int4 *>(key + m + 4);
-            const int kk[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+        for (int m = s & ~3; m < e; m += 16) {
+            int4 kv[4];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                rank += (m + q >= s && m + q < e && kk[q] < me) ? 1 : 0;
+            for (int v = 0; v < 4; ++v) kv[v] = *reinterpret_cast<const int4 *>(key + m + 4 * v);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int kk[4] = {kv[v].x, kv[v].y, kv[v].z, kv[v].w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int mq = m + 4 * v + q;
+                    rank += (mq >= s && mq < e && kk[q] < me) ? 1 : 0;
+                }
+            }
         }
         const int dst = s + rank;
         const double *L = a.box + 3 * w.rep;
         int sx, sy, sz;
-        out.x[dst] = wrap_coord(in.x[i], L[0], &sx);
-        out.y[dst] = wrap_coord(in.y[i], L[1], &sy);
-        out.z[dst] = wrap_coord(in.z[i], L[2], &sz);
-        out.vx[dst] = in.vx[i];
-        out.vy[dst] = in.vy[i];
-        out.vz[dst] = in.vz[i];
-        out.type[dst] = in.type[i];
+        out.x[dst] = wrap_coord(x0, L[0], &sx);
+        out.y[dst] = wrap_coord(y0, L[1], &sy);
+        out.z[dst] = wrap_coord(z0, L[2], &sz);
+        out.vx[dst] = vx;
+        out.vy[dst] = vy;
+        out.vz[dst] = vz;
+        out.type[dst] = ty;
         out.id[dst] = me;
-        out.img[dst] = in.img[i] + sx;
-        out.img[N + dst] = in.img[N + i] + sy;
-        out.img[2 * N + dst] = in.img[2 * N + i] + sz;
+        out.img[dst] = ix + sx;
+        out.img[N + dst] = iy + sy;
+        out.img[2 * N + dst] = iz + sz;
         if (in.where) in.where[me] = dst;
     }
 }
