@@ -65,11 +65,12 @@ def test_broken_bond_raises_the_flag():
     assert int(s.status.item()) & abi.MD_F_BOND_BROKEN
 
 
-def test_melt_trajectory_with_thermostat_matches_oracle():
-    print("case: melt trajectory", flush=True)
+@pytest.mark.parametrize("mode", ["full", "tile"])
+def test_melt_trajectory_with_thermostat_matches_oracle(mode):
+    print(f"case: melt trajectory {mode}", flush=True)
     cfg = md_inputs.lattice_chains((8, 8, 10), 40, seed=6, temperature=1.0)
     steps = 60
-    s = _system(cfg, langevin=(0.5, 1.0, 2024, 0))
+    s = _system(cfg, langevin=(0.5, 1.0, 2024, 0), mode=mode)
     s.setup()
     flags, ep = [], []
     for t in range(steps):

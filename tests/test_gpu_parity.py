@@ -4,7 +4,11 @@ Tolerances (derivations):
   FP64 path -- same arithmetic, different summation order and a reciprocal
     refined by Newton steps: per-atom force error ~ (terms) x (largest term)
     x 2^-53 ~ 50 x 200 x 1.1e-16 ~ 1e-12; bound 1e-10 absolute, 1e-12
-    normwise; energy/virial relative 1e-12.
+    normwise; energy/virial relative 1e-12 for the 4000-atom cases.  For a
+    replica of N_r atoms the energy sums P ~ 27 N_r pair terms of mixed
+    sign in a different order on each side: the recursive-summation bound
+    P x 2^-53 x sum|U| with sum|U| ~ 2|E| gives ~3e-11 relative at
+    N_r = 6000, so larger replicas are held to 1e-10.
   FP32-mixed path -- single-precision reciprocal (1 ulp) and LJ polynomial:
     relative pair-force error ~ 10 x 2^-24 ~ 6e-7, partly cancelling in the
     sum; the required bound is the target's 1e-5 normwise relative force
@@ -485,3 +489,52 @@ def test_tile_list_padding_and_neighbour_overflow(c1_snapshot):
     ref, e, _ = oracle.lj_forces(cfg.pos, cfg.box[0], RC, shift=1)
     assert np.abs(s.forces_np() - ref).max() < 1e-10
     assert float(s.energy[0]) == pytest.approx(e, rel=1e-12)
+
+
+def _one_type(cfg):
+    # the replica batch with every atom of type 0 and a 1 x 1 (eps, sigma)
+    return md_inputs.Config(cfg.name + "_1t", cfg.pos, cfg.vel, cfg.box, cfg.natoms,
+                            np.zeros_like(cfg.types), 1, np.ones((1, 1)), np.ones((1, 1)),
+                            np.ones(1), cfg.rc, cfg.skin, cfg.dt, cfg.temperature, cfg.steps)
+
+
+@pytest.mark.parametrize("rows", [(1, 1), (2, 2)])
+def test_tile_lists_on_a_batch_of_uneven_replicas(rows):
+    # five replicas of 500 .. 6000 atoms (boxes of 2 to 4 cells per side),
+    # each replica's forces and energy against the oracle on that replica
+    cfg = _one_type(md_inputs.replica_batch(nrep=5, nmin=500, nmax=6000, seed=21))
+    say(f"case: tile batch of replicas rows={rows}")
+    s = _system(cfg, mode="tile", prec="fp64", tile_rows=rows)
+    s.setup()
+    assert s.ensure_list() == 0
+    f = s.forces_np()
+    off = cfg.atom_off()
+    for r in range(5):
+        a, b = off[r], off[r + 1]
+        ref, e, w = oracle.lj_forces(cfg.pos[a:b], cfg.box[r], RC, shift=1)
+        assert np.abs(f[a:b] - ref).max() < 1e-10
+        assert float(s.energy[r]) == pytest.approx(e, rel=1e-10)
+        assert float(s.virial[r]) == pytest.approx(w, rel=1e-10)
+
+
+def test_tile_batch_equals_each_replica_alone():
+    cfg = _one_type(md_inputs.replica_batch(nrep=4, nmin=800, nmax=5000, seed=22))
+    say("case: tile batch vs single")
+    s = _system(cfg, mode="tile", tile_cells=2, tile_rows=(2, 2))
+    s.setup()
+    s.run(12)
+    s.ensure_list()
+    pos_b, f_b = s.positions(), s.forces_np()
+    off = cfg.atom_off()
+    for r in (0, 2, 3):
+        a, b = off[r], off[r + 1]
+        one = md_inputs.Config("one", cfg.pos[a:b], cfg.vel[a:b], cfg.box[r:r + 1],
+                               cfg.natoms[r:r + 1], cfg.types[a:b], 1, cfg.eps, cfg.sig,
+                               cfg.mass, RC, SKIN, cfg.dt, 1.0, 12)
+        t = _system(one, mode="tile", tile_cells=2, tile_rows=(2, 2))
+        t.setup()
+        t.run(12)
+        t.ensure_list()
+        assert np.array_equal(t.positions(), pos_b[a:b])
+        assert np.array_equal(t.forces_np(), f_b[a:b])
+        assert float(t.ke[0]) == float(s.ke[r])
