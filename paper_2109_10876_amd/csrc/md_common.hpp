@@ -70,6 +70,21 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nblocks)
     return x * per + (x < rem ? x : rem) + k;
 }
 
+// Chunked variant for work laid out in space with holes (tiles over a cell
+// grid that may be mostly vacuum): XCD x receives chunks x, x + 8, x + 16, ...
+// of C consecutive items, so neighbouring items still share an L2 while any
+// occupied band is spread over all XCDs.  Items past the last full round of
+// 8 chunks are split contiguously as in xcd_swizzle.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_chunked(int b, int n, int C)
+{
+    const int x = b % kXcds, k = b / kXcds;
+    const int full = n / (kXcds * C);
+    if (k < full * C) return ((k / C) * kXcds + x) * C + k % C;
+    const int base = full * kXcds * C, m = n - base;
+    const int per = m / kXcds, rem = m % kXcds;
+    return base + x * per + (x < rem ? x : rem) + (k - full * C);
+}
+
 struct Unit {
     int rep;    // replica
     int begin;  // first atom of the unit

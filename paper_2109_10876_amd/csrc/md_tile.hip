@@ -43,6 +43,9 @@ struct TileArgs {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Tiles go to the XCDs in chunks of this many consecutive tiles.
+constexpr int kTileXcdChunk = 16;
+
 // Tile-list builds form column byte offsets with 24-bit multiplies (and the
 // whole list must span less than 4 GiB).
 constexpr int kTileMaxLd = 1 << 23;
@@ -87,9 +90,10 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
     const int lane = __lane_id();
     const int wid = uniform(threadIdx.x / kWave);
     for (int lt = blockIdx.x; lt < a.n_tiles; lt += gridDim.x) {
-        const int t = xcd_swizzle(lt, a.n_tiles);
+        const int t = xcd_chunked(lt, a.n_tiles, kTileXcdChunk);
         const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
         if (a.gate != nullptr && a.gate[s.rep] == 0u) continue;
+        if (tile_home_atoms(s, a.cell_start) == 0) continue;
         const int total = stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP);
         if (total > CAP) {
             if (threadIdx.x == 0) {
@@ -232,8 +236,15 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
     constexpr int TB = SH::TB, CAP = SH::CAP;
     __shared__ TileStage<CAP, SH::MAXC> st;
     __shared__ double red[TB / kWave];
-    const int t = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int t = xcd_chunked(blockIdx.x, gridDim.x, kTileXcdChunk);
     const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
+    if (tile_home_atoms(s, a.cell_start) == 0) {
+        if (threadIdx.x == 0) {
+            a.tpart[size_t(t) * 2 + 0] = 0.0;
+            a.tpart[size_t(t) * 2 + 1] = 0.0;
+        }
+        return;
+    }
     const PolyConst pc = poly_const(a.eps[0], a.sig[0], a.rc, a.shift);
     const double rc2 = a.rc * a.rc;
     const int total = stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP);

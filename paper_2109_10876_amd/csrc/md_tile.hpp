@@ -254,6 +254,19 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
     return total;
 }
 
+// Number of home atoms of the tile, from the cell starts of its home rows
+// (uniform across the workgroup: scalar loads).  Empty tiles (vacuum in an
+// inhomogeneous system) skip staging altogether.
+__device__ __forceinline__ int tile_home_atoms(const TileSpec &s, const int32_t *__restrict__ cs)
+{
+    int n = 0;
+    for (int h = 0; h < s.hy * s.hz; ++h) {
+        const int rb = s.coff + ((s.z0 + h / s.hy) * s.ny + (s.y0 + h % s.hy)) * s.nx;
+        n += cs[rb + s.b + 1] - cs[rb + s.a];
+    }
+    return n;
+}
+
 // Home atom number k of the tile (0 .. home_start[hy hz]): its index and home
 // row offsets (dy, dz) relative to (y0, z0).
 template <class Stage>

@@ -26,6 +26,20 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _occupied_cell_density(pos, natoms, box, ncell):
+    """Host-side launch planning: mean atoms per non-empty cell of the cell
+    grid, for the replica where it is largest."""
+    nu, off = 1.0, 0
+    for r, n in enumerate(np.asarray(natoms).ravel()):
+        n = int(n)
+        L, nc = box[r], ncell[r].astype(np.int64)
+        c = np.minimum((np.mod(pos[off:off + n], L) * nc / L).astype(np.int64), nc - 1)
+        cnt = np.bincount((c[:, 2] * nc[1] + c[:, 1]) * nc[0] + c[:, 0])
+        nu = max(nu, float(cnt[cnt > 0].mean()))
+        off += n
+    return nu
+
+
 class MDSystem:
     """R independent periodic LJ systems, concatenated, resident on one GPU.
 
@@ -126,9 +140,9 @@ class MDSystem:
             if tile_cells is None:
                 # cells per tile: staged neighbourhood 9 (m + 2) nu within 92% of
                 # the staging capacity and about one home atom per thread,
-                # nu = mean atoms per cell of the densest replica; then balanced
-                # along each row
-                nu = float(np.max(natoms / np.prod(self.h_ncell, axis=1)))
+                # nu = mean atoms per occupied cell of the densest replica (so
+                # vacuum does not dilute it); then balanced along each row
+                nu = _occupied_cell_density(pos, natoms, box, self.h_ncell)
                 cap = self.lib.md_tile_capacity()
                 tb = self.lib.md_tune_get(abi.MD_TUNE_TILE_THREADS)
                 py, pz = self.tile_py, self.tile_pz
