@@ -72,6 +72,7 @@ extern "C" {
 #define MD_TILE_SLOTS 3072          /* staged atoms per tile (MD_TILE_FULL)       */
 #define MD_TILE_MAX_CELLS 64        /* cells per tile along x                     */
 #define MD_TILE_MAX_ROWS  2         /* cell rows per tile along y and along z     */
+#define MD_TILE_MAX_TYPES 4         /* atom types of a typed tile-local list      */
 
 /* Verlet-list entry encoding.  Entry e of atom i names atom j = e & MD_IDX_MASK
  * and the periodic image under which j is i's neighbour: for dimension d
@@ -91,15 +92,16 @@ extern "C" {
  * x = a-1 .. b+1 of that row (x = -1 is cell nx-1 one box length to the
  * left, x = nx is cell 0 one box length to the right), each cell's atoms in
  * index order, concatenated.  Entry k of atom i is the uint16
- * ((uint16_t *)idx)[k * ld + i] = 8 p, where p is the position of the
+ * ((uint16_t *)idx)[k * ld + i] = 8 p + t, where p is the position of the
  * neighbour in its tile's staged sequence (its image is the one its staged
- * row and cell imply).  Entries count[i] .. (count[i] rounded up to 16) - 1
+ * row and cell imply) and t is its atom type when tile_types > 1 (else 0).  Entries count[i] .. (count[i] rounded up to 16) - 1
  * hold 8 md_tile_capacity(), a pad slot far from every atom, so max_nbr
  * must be a multiple of 16, and ld at most 2^23 (MD_EINVAL otherwise).  A tile whose staged
  * sequence exceeds md_tile_capacity() (at most MD_TILE_SLOTS) raises
  * MD_F_TILE_OVERFLOW (the list is then unusable: rebuild with smaller
- * tiles).  Tile-local lists take one atom type (md_lj_forces returns
- * MD_EUNSUPPORTED otherwise) and have no adjoint. */
+ * tiles).  md_lj_forces takes a tile-local list whose tile_types equals
+ * the LJ table's ntypes (0 or 1 for one type), at most MD_TILE_MAX_TYPES
+ * (MD_EINVAL / MD_EUNSUPPORTED otherwise); tile-local lists have no adjoint. */
 
 /* ------------------------------------------------------------------ structs */
 
@@ -148,7 +150,9 @@ typedef struct md_nlist {
     int32_t  n_tiles;         /* MD_TILE_FULL: tiles (md_tile_plan)               */
     int32_t  tile_py;         /* MD_TILE_FULL: cell rows per tile along y, 1..2   */
     int32_t  tile_pz;         /* MD_TILE_FULL: cell rows per tile along z, 1..2   */
-    int32_t  _pad;
+    int32_t  tile_types;      /* MD_TILE_FULL: 0 or 1 = entries carry no type;
+                                 2..MD_TILE_MAX_TYPES = entries carry the
+                                 neighbour's type (set to the LJ table's ntypes) */
     const int32_t *tile_rep;  /* MD_TILE_FULL: [n_tiles] replica of each tile     */
     const int32_t *tile_off;  /* MD_TILE_FULL: [R+1] first tile of each replica   */
     int32_t  *tile_need;      /* optional: largest staged count seen (overflow)   */

@@ -31,6 +31,7 @@ MD_TILE_FULL = 2
 MD_TILE_SLOTS = 3072
 MD_TILE_MAX_CELLS = 64
 MD_TILE_MAX_ROWS = 2
+MD_TILE_MAX_TYPES = 4
 MD_FP64 = 0
 MD_FP32_MIXED = 1
 MD_UNIT_ATOMS = 256
@@ -70,7 +71,7 @@ class MdAtoms(ctypes.Structure):
 class MdNlist(ctypes.Structure):
     _fields_ = [("mode", _i32), ("max_nbr", _i32), ("ld", _i32), ("tile_cells", _i32),
                 ("count", _vp), ("idx", _vp), ("n_tiles", _i32), ("tile_py", _i32),
-                ("tile_pz", _i32), ("_pad", _i32),
+                ("tile_pz", _i32), ("tile_types", _i32),
                 ("tile_rep", _vp), ("tile_off", _vp), ("tile_need", _vp), ("cell_start", _vp)]
 
 

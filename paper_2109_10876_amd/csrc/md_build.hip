@@ -216,6 +216,7 @@ extern "C" int md_verlet_build(const md_batch *b, const md_atoms *atoms,
     if (!(rc > 0.0) || !(skin >= 0.0)) return MD_EINVAL;
     if (nl->mode == MD_TILE_FULL) {
         if (!tile_list_ok(b, nl) || nl->cell_start != cell_start) return MD_EINVAL;
+        if (nl->tile_types > 1 && !atoms->type) return MD_EINVAL;
         return tile_build(b, atoms, cell_start, (rc + skin) * (rc + skin), nl, need, gate, status,
                           as_stream(stream));
     }

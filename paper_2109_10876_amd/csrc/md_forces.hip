@@ -281,7 +281,10 @@ extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_n
     if (ws_bytes < l.total) return MD_ENOWS;
     if (nl->mode == MD_TILE_FULL) {
         if (!tile_list_ok(b, nl) || !nl->cell_start) return MD_EINVAL;
-        if (p->ntypes > 1) return MD_EUNSUPPORTED;
+        if (p->ntypes > MD_TILE_MAX_TYPES) return MD_EUNSUPPORTED;
+        // a typed list is needed for several types, and only then
+        if (p->ntypes > 1 ? (nl->tile_types != p->ntypes || !atoms->type) : nl->tile_types > 1)
+            return MD_EINVAL;
         return tile_forces(b, atoms, nl, p, prec, accumulate, nl->cell_start, energy, virial,
                            ws_at<double>(ws, l.tile_partial), md_tune_get(MD_TUNE_PAIR_BATCH),
                            status, as_stream(stream));

@@ -22,6 +22,8 @@ struct TileArgs {
     const double *box;
     const uint32_t *gate;
     const double *x, *y, *z, *pos4;
+    const int32_t *type;
+    int32_t tile_types;   // > 1: list entries carry the neighbour's type
     const int32_t *cell_start;
     TileGrid g;
     int32_t n_tiles, max_nbr, ld;
@@ -149,6 +151,11 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
                     py[c] = st.y[slot];
                     pz[c] = st.z[slot];
                     ent[c] = slot * 8;
+                    if (a.tile_types > 1) {
+                        int row;
+                        double sx;
+                        ent[c] |= a.type[slot_source(s, st, slot, row, sx)];
+                    }
                 }
                 const int nch = (T + kWave - 1) / kWave;
                 const unsigned ld2u = unsigned(ld2);
@@ -203,7 +210,13 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
                         const bool valid = sl < s1;
                         const int sc = valid ? sl : s1 - 1;
                         const double px = st.x[sc], py = st.y[sc], pz = st.z[sc];
-                        const uint16_t ent = uint16_t(sl * 8);
+                        int ty = 0;
+                        if (a.tile_types > 1) {
+                            int row;
+                            double sx;
+                            ty = a.type[slot_source(s, st, sc, row, sx)];
+                        }
+                        const uint16_t ent = uint16_t(sl * 8 + ty);
                         for (int j = 0; j < nb; ++j) {
                             const int hs = own0 + (hb - g0) + j;   // the home atom's own slot
                             const double dx = st.x[hs] - px, dyy = st.y[hs] - py,
@@ -230,12 +243,16 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
 }
 
-template <class SH, int PREC, int U, bool P4>
+// Typed lists: LJ constants of type pair (ti, tj) at ti * kTileMaxTypes + tj.
+constexpr int kTileMaxTypes = MD_TILE_MAX_TYPES;
+
+template <class SH, int PREC, int U, bool P4, bool TYPED>
 __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
 {
     constexpr int TB = SH::TB, CAP = SH::CAP;
     __shared__ TileStage<CAP, SH::MAXC> st;
     __shared__ double red[TB / kWave];
+    __shared__ PolyConst ptab[TYPED ? kTileMaxTypes * kTileMaxTypes : 1];
     const int t = xcd_chunked(blockIdx.x, gridDim.x, kTileXcdChunk);
     const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
     if (tile_home_atoms(s, a.cell_start) == 0) {
@@ -247,6 +264,15 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
     }
     const PolyConst pc = poly_const(a.eps[0], a.sig[0], a.rc, a.shift);
     const double rc2 = a.rc * a.rc;
+    if (TYPED) {
+        // filled before staging, whose barriers publish it
+        const int nt = a.tile_types;
+        if (threadIdx.x < nt * nt) {
+            const int ti = threadIdx.x / nt, tj = threadIdx.x % nt;
+            ptab[ti * kTileMaxTypes + tj] = poly_const(a.eps[threadIdx.x], a.sig[threadIdx.x], a.rc,
+                                                       a.shift);
+        }
+    }
     const int total = stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP);
     double e_acc = 0.0, w_acc = 0.0;
     if (total > CAP) {
@@ -260,6 +286,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
             const int i = home_atom(s, st, hk, dy, dz);
             const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
             const int n = min(a.count[i], a.max_nbr);
+            const int ti4 = TYPED ? a.type[i] * kTileMaxTypes : 0;
             Acc c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
             // Entries are LDS byte offsets, consumed U at a time while the
             // next U are in flight; a list is padded with the pad slot to a
@@ -282,14 +309,17 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
                 double px[U], py[U], pz[U];
 #pragma unroll
                 for (int q = 0; q < U; ++q) {
-                    const char *pq = stb + min(unsigned(cur[q]), unsigned(CAP * 8));
+                    // typed entries carry the type in the low 3 bits
+                    const unsigned e = TYPED ? unsigned(cur[q]) & ~7u : unsigned(cur[q]);
+                    const char *pq = stb + min(e, unsigned(CAP * 8));
                     px[q] = *reinterpret_cast<const double *>(pq);
                     py[q] = *reinterpret_cast<const double *>(pq + kY);
                     pz[q] = *reinterpret_cast<const double *>(pq + 2 * kY);
                 }
 #pragma unroll
                 for (int q = 0; q < U; ++q)
-                    lj_pair_masked<PREC>(pc, xi - px[q], yi - py[q], zi - pz[q], rc2, c);
+                    lj_pair_masked<PREC>(TYPED ? ptab[ti4 + (cur[q] & 7)] : pc, xi - px[q],
+                                         yi - py[q], zi - pz[q], rc2, c);
 #pragma unroll
                 for (int q = 0; q < U; ++q) cur[q] = nxt[q];
             }
@@ -361,6 +391,8 @@ TileArgs tile_args(const md_batch *b, const md_atoms *atoms, const md_nlist *nl)
     a.idx = reinterpret_cast<uint16_t *>(nl->idx);
     a.tile_need = nl->tile_need;
     a.R = b->R;
+    a.type = atoms->type;
+    a.tile_types = nl->tile_types;
     return a;
 }
 
@@ -371,7 +403,8 @@ bool tile_stage_packed() { return md_tune_get(MD_TUNE_TILE_STAGE_PACKED) != 0; }
 bool tile_list_ok(const md_batch *b, const md_nlist *nl)
 {
     return nl->n_tiles >= 1 && nl->n_tiles <= b->C && nl->tile_rep && nl->tile_off &&
-           nl->max_nbr % 16 == 0 && nl->ld <= kTileMaxLd &&
+           nl->max_nbr % 16 == 0 && nl->ld <= kTileMaxLd && nl->tile_types >= 0 &&
+           nl->tile_types <= MD_TILE_MAX_TYPES &&
            size_t(nl->max_nbr) * size_t(nl->ld) * 2 < (size_t(1) << 32) &&
            nl->tile_cells >= 1 && nl->tile_cells <= tile_max_cells() && nl->tile_py >= 1 &&
            nl->tile_py <= MD_TILE_MAX_ROWS && nl->tile_pz >= 1 && nl->tile_pz <= MD_TILE_MAX_ROWS;
@@ -453,20 +486,24 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
     const dim3 grid(nl->n_tiles);
     const bool p4 = tile_stage_packed() && atoms->pos4;
     const bool big = batch >= 8;
+    const bool typed = p->ntypes > 1;
     with_tile_shape([&](auto sh) {
         using SH = decltype(sh);
         const dim3 blk(SH::TB);
-#define MD_TILE_LAUNCH(P, U)                                                          \
-    do {                                                                              \
-        if (p4) hipLaunchKernelGGL((k_tile_lj<SH, P, U, true>), grid, blk, 0, s, a);  \
-        else hipLaunchKernelGGL((k_tile_lj<SH, P, U, false>), grid, blk, 0, s, a);    \
+#define MD_TILE_LAUNCH(P, U, T)                                                          \
+    do {                                                                                 \
+        if (p4) hipLaunchKernelGGL((k_tile_lj<SH, P, U, true, T>), grid, blk, 0, s, a);  \
+        else hipLaunchKernelGGL((k_tile_lj<SH, P, U, false, T>), grid, blk, 0, s, a);    \
     } while (0)
-        if (prec == MD_FP64) {
-            if (big) MD_TILE_LAUNCH(MD_FP64, 16);
-            else MD_TILE_LAUNCH(MD_FP64, 8);
+        if (typed) {
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, true);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, true);
+        } else if (prec == MD_FP64) {
+            if (big) MD_TILE_LAUNCH(MD_FP64, 16, false);
+            else MD_TILE_LAUNCH(MD_FP64, 8, false);
         } else {
-            if (big) MD_TILE_LAUNCH(MD_FP32_MIXED, 16);
-            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8);
+            if (big) MD_TILE_LAUNCH(MD_FP32_MIXED, 16, false);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, false);
         }
 #undef MD_TILE_LAUNCH
     });

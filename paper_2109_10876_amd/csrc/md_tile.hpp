@@ -116,6 +116,23 @@ __device__ __forceinline__ int staged_row(const TileSpec &s, int dy, int dz)
 // Fills the staging tables and stages positions (x, y, z planes or the
 // packed copy).  All TB threads of the workgroup must call it.  Returns the
 // total staged count (may exceed cap: then nothing is staged).
+// Source atom of staged slot sl: its staged row (from the chunk table, then
+// forward over rows that end inside the chunk), and the x image shift of the
+// row piece it sits in.  Needs the row tables of stage_tile's second phase.
+template <class Stage>
+__device__ __forceinline__ int slot_source(const TileSpec &s, const Stage &st, int sl, int &row,
+                                           double &sx)
+{
+    int r = st.rowc[sl >> 6];
+    while (sl >= st.row_slot[r + 1]) ++r;
+    const int off = sl - st.row_slot[r];
+    const int lw = st.row_lw[r], mn = st.row_main[r];
+    const int piece = off < lw ? 0 : (off < lw + mn ? 1 : 2);
+    row = r;
+    sx = piece == 0 ? -s.L[0] : (piece == 1 ? 0.0 : s.L[0]);
+    return st.row_g0[r][piece] + off - (piece == 0 ? 0 : (piece == 1 ? lw : lw + mn));
+}
+
 template <int TB, bool P4, class Stage>
 __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
                           const double *__restrict__ x, const double *__restrict__ y,
@@ -217,14 +234,7 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int sl = min(tid + k * TB, total - 1);
-            int r = st.rowc[sl >> 6];
-            while (sl >= st.row_slot[r + 1]) ++r;
-            const int off = sl - st.row_slot[r];
-            const int lw = st.row_lw[r], mn = st.row_main[r];
-            const int piece = off < lw ? 0 : (off < lw + mn ? 1 : 2);
-            src[k] = st.row_g0[r][piece] + off - (piece == 0 ? 0 : (piece == 1 ? lw : lw + mn));
-            sxk[k] = piece == 0 ? -s.L[0] : (piece == 1 ? 0.0 : s.L[0]);
-            rowof[k] = r;
+            src[k] = slot_source(s, st, sl, rowof[k], sxk[k]);
         }
         double px[kPer], py[kPer], pz[kPer];
 #pragma unroll

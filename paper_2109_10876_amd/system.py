@@ -233,7 +233,8 @@ class MDSystem:
         self.nlist = abi.MdNlist(
             self.mode, self.max_nbr, self.ld, self.tile_cells if tiled else 0,
             self.count.data_ptr(), self.idx.data_ptr(), self.n_tiles if tiled else 0,
-            self.tile_py, self.tile_pz, 0, self.tile_rep.data_ptr() if tiled else None,
+            self.tile_py, self.tile_pz, self.ntypes if tiled and self.ntypes > 1 else 0,
+            self.tile_rep.data_ptr() if tiled else None,
             self.tile_off.data_ptr() if tiled else None,
             self.tile_need.data_ptr(), self.cell_start.data_ptr() if tiled else None)
 
@@ -445,7 +446,7 @@ class MDSystem:
             for home, slots in self.tile_slot_table():
                 for i in home:
                     n = min(cnt[i], self.max_nbr)
-                    js = slots[idx[:n, i].astype(np.int64) // 8]
+                    js = slots[idx[:n, i].astype(np.int64) >> 3]
                     out.append(np.stack([np.full(n, ids[i]), ids[js]], 1))
             return np.concatenate(out), None
         cnt = self.count.cpu().numpy()

@@ -34,7 +34,10 @@ def test_header_constants_match_binding():
     src = open(os.path.join(ROOT, "include", "md.h")).read()
     for name in ("MD_OK", "MD_EINVAL", "MD_EBOX", "MD_ENOWS", "MD_EUNSUPPORTED", "MD_EHIP",
                  "MD_ERANGE", "MD_HALF", "MD_FULL", "MD_FP64", "MD_FP32_MIXED",
-                 "MD_UNIT_ATOMS", "MD_IDX_BITS", "MD_MAX_TYPES"):
+                 "MD_UNIT_ATOMS", "MD_IDX_BITS", "MD_MAX_TYPES", "MD_TILE_FULL",
+                 "MD_TILE_SLOTS", "MD_TILE_MAX_CELLS", "MD_TILE_MAX_ROWS", "MD_TILE_MAX_TYPES",
+                 "MD_TUNE_PAIR_BATCH", "MD_TUNE_TILE_THREADS", "MD_TUNE_TILE_STAGE_PACKED",
+                 "MD_TUNE_TILE_SLOTS"):
         m = re.search(rf"#define\s+{name}\s+(-?\w+)", src)
         assert m, name
         assert int(m.group(1), 0) == getattr(abi, name), name

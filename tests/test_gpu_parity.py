@@ -12,7 +12,10 @@ Tolerances (derivations):
   FP32-mixed path -- single-precision reciprocal (1 ulp) and LJ polynomial:
     relative pair-force error ~ 10 x 2^-24 ~ 6e-7, partly cancelling in the
     sum; the required bound is the target's 1e-5 normwise relative force
-    error; energy and virial relative 1e-6.
+    error; energy and virial relative 1e-6 where the total is large.  Each
+    atom sums its ~40 pair energies (each below ~10 in size) in single
+    precision: at most ~40 x 10 x 2^-24 ~ 2.4e-5 per atom, so for replicas
+    whose total energy nearly cancels the bound is |dE| <= 1e-5 N_r.
   Integer work (pair sets, counts, rebuild schedule): exact.
 """
 import numpy as np
@@ -538,3 +541,50 @@ def test_tile_batch_equals_each_replica_alone():
         assert np.array_equal(t.positions(), pos_b[a:b])
         assert np.array_equal(t.forces_np(), f_b[a:b])
         assert float(t.ke[0]) == float(s.ke[r])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_typed_tile_lists_on_the_two_type_replica_batch(prec):
+    # two atom types with one symmetric (eps, sigma) table: tile-list entries
+    # carry the neighbour's type; forces and energy per replica against the
+    # oracle, and the pair set against the global full list
+    cfg = md_inputs.replica_batch(nrep=5, nmin=500, nmax=6000, seed=23)
+    say(f"case: typed tile batch {prec}")
+    s = _system(cfg, mode="tile", prec=prec, tile_rows=(2, 2))
+    assert s.nlist.tile_types == 2
+    s.setup()
+    assert s.ensure_list() == 0
+    f = s.forces_np()
+    off = cfg.atom_off()
+    for r in range(5):
+        a, b = off[r], off[r + 1]
+        ref, e, w = oracle.lj_forces(cfg.pos[a:b], cfg.box[r], RC, cfg.eps, cfg.sig,
+                                     cfg.types[a:b], shift=1)
+        if prec == "fp64":
+            assert np.abs(f[a:b] - ref).max() < 1e-10
+            assert float(s.energy[r]) == pytest.approx(e, rel=1e-10)
+            assert float(s.virial[r]) == pytest.approx(w, rel=1e-10)
+        else:
+            assert _err(f[a:b], ref) < 1e-5
+            assert abs(float(s.energy[r]) - e) <= 1e-5 * (b - a)
+    g = _system(cfg, mode="full")
+    g.setup()
+    assert _unordered(s.list_pairs()[0]) == _unordered(g.list_pairs()[0])
+
+
+def test_typed_tile_list_is_required_for_several_types(c1_snapshot):
+    # an untyped tile list with a two-type LJ table (and the reverse) is
+    # refused on the host
+    from paper_2109_10876_amd import _abi as abi
+    cfg = md_inputs.replica_batch(nrep=2, nmin=500, nmax=900, seed=24)
+    say("case: typed tile list checks")
+    s = _system(cfg, mode="tile")
+    s.setup()
+    s.nlist.tile_types = 0
+    with pytest.raises(abi.MDError):
+        s.forces()
+    one = _system(c1_snapshot, mode="tile")
+    one.setup()
+    one.nlist.tile_types = 2
+    with pytest.raises(abi.MDError):
+        one.forces()
