@@ -158,8 +158,9 @@ def time_workload(name, steps, warmup=10):
                         cfg.mass, rc=cfg.rc, skin=cfg.skin, dt=cfg.dt, shift=cfg.shift,
                         bonds=cfg.bonds, langevin=lang, prec="mixed", mode=mode,
                         tile_cells=tile_cells, tile_rows=tile_rows)
-    if ntypes == 1:
-        # tile-local lists take one atom type: let the autotuner pick (untimed)
+    from paper_2109_10876_amd import _abi
+    if ntypes <= _abi.MD_TILE_MAX_TYPES:
+        # list form and launch shape from the autotuner (untimed)
         key = autotune.signature(cfg.natoms, cfg.box, cfg.rc, cfg.skin, ntypes)
         tuned, _ = autotune.tune(make, key, steps=30, warmup=5, cache=None)
     else:
@@ -182,6 +183,14 @@ def time_workload(name, steps, warmup=10):
            "atom_steps_per_s": s.N * steps / (ms * 1e-3), "status": st,
            "mean_list_entries": float(s.count.double().mean().item())}
     if name == "replicas":
+        if tuned["mode"] != "full":
+            # the adjoint runs on a global full list
+            del s
+            torch.cuda.empty_cache()
+            autotune.apply({"mode": "full", "batch": 4})
+            s = make("full")
+            s.setup()
+            s.ensure_list()
         gf = [torch.randn(s.N, dtype=torch.float64, device=s.dev) for _ in range(3)]
         gE = torch.randn(s.R, dtype=torch.float64, device=s.dev)
         gx = torch.empty(3 * s.N, dtype=torch.float64, device=s.dev)

@@ -97,7 +97,16 @@ def tune(make, key, steps=40, warmup=10, cache=DEFAULT_CACHE, retune=False, log=
 
     def run(c):
         t0 = time.perf_counter()
-        ms, status, tc = _time(make, c, steps, warmup)
+        try:
+            ms, status, tc = _time(make, c, steps, warmup)
+        except (RuntimeError, abi.MDError) as exc:
+            # a candidate the workload cannot use (e.g. a single-cell tile
+            # that overflows the staging capacity): skipped
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            if log:
+                log(f"autotune {json.dumps(c)} -> not usable ({exc})")
+            return math.inf
         c = dict(c, tile_cells=tc) if c["mode"] == "tile" else c
         trials.append((c, ms))
         if log:
@@ -113,6 +122,8 @@ def tune(make, key, steps=40, warmup=10, cache=DEFAULT_CACHE, retune=False, log=
         base = {"mode": "tile", "batch": 4, "tile_threads": tb, "tile_slots": slots,
                 "tile_rows": rows}
         best_ms = run(dict(base, tile_cells=None))
+        if math.isinf(best_ms):
+            continue
         m = trials[-1][0]["tile_cells"]
         while m and m > 2:
             m = max(2, m - max(1, m // 4))
