@@ -282,6 +282,22 @@ int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
                  double *energy, double *virial, void *ws, size_t ws_bytes,
                  uint32_t *status, void *stream);
 
+/* md_lj_forces followed, in the same kernel, by md_vv_step phase 3 for each
+ * atom as soon as its force is known (the forces of a step feed its
+ * Integrate2 and the next step's Integrate1 directly): on return fx, fy, fz
+ * hold the forces at the positions on entry, velocities and positions are
+ * advanced, gate[r] and ke[r] (optional) are set as by md_vv_step phase 3,
+ * energy/virial as by md_lj_forces.  Pure pair forces only: MD_TILE_FULL
+ * lists of one atom type (MD_EUNSUPPORTED otherwise); a step that adds bond
+ * or thermostat forces uses md_lj_forces and md_vv_step.  The same
+ * arithmetic as those two calls in sequence, so trajectories are bitwise
+ * equal; the kinetic energy is summed in another order.  New positions are
+ * staged in the workspace and copied back (with the packed copy, if set). */
+int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlist *nl, const md_lj *p,
+                    int32_t prec, double dt, const double *inv_mass, int32_t ntypes,
+                    double skin, uint32_t *gate, double *ke, double *energy, double *virial,
+                    void *ws, size_t ws_bytes, uint32_t *status, void *stream);
+
 /* Velocity-Verlet update (Sec. 2.1, Fig. 1: Integrate1 / Integrate2).
  *  phase 1: v += dt/2 F/m; x += dt v; gate[r] = 1 if some atom of replica r
  *           moved more than skin/2 from x_build (the list may miss a pair

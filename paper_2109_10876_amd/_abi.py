@@ -49,7 +49,7 @@ EXPORTS = (
     "md_abi_version", "md_strerror", "md_tune_set", "md_tune_get", "md_tile_capacity", "md_tile_max_cells", "md_plan_sizes", "md_plan_fill",
     "md_tile_plan",
     "md_workspace_bytes", "md_cell_sort", "md_verlet_build", "md_lj_forces",
-    "md_vv_step", "md_lj_forces_vjp", "md_fene_forces", "md_langevin",
+    "md_vv_step", "md_lj_forces_vv", "md_lj_forces_vjp", "md_fene_forces", "md_langevin",
 )
 
 _vp = ctypes.c_void_p
@@ -137,6 +137,10 @@ def load():
     lib.md_vv_step.restype = ctypes.c_int
     lib.md_vv_step.argtypes = [P(MdBatch), P(MdAtoms), _i32, _dbl, _vp, _i32, _dbl, _vp, _vp,
                                _vp, ctypes.c_size_t, _vp, _vp]
+    lib.md_lj_forces_vv.restype = ctypes.c_int
+    lib.md_lj_forces_vv.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32, _dbl,
+                                    _vp, _i32, _dbl, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                    _vp, _vp]
     lib.md_lj_forces_vjp.restype = ctypes.c_int
     lib.md_lj_forces_vjp.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32,
                                      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,

@@ -29,10 +29,12 @@ struct WsLayout {
     size_t slot;         // N x int32
     size_t key;          // N (+16 padding: 64-byte reads) x int32
     size_t vjp_partial;  // n_units x 2 x MD_MAX_TYPES^2 doubles
-    size_t tile_partial; // C x 2 doubles (tiles never outnumber cells)
+    size_t tile_partial; // C x kTilePartials doubles (tiles never outnumber cells)
+    size_t xnext;        // 3 N doubles: next positions of the fused force + step call
     size_t total;
 };
 constexpr int kPartials = 4;   // E, W, KE, max displacement^2
+constexpr int kTilePartials = 4;   // per tile: E, W, KE, max displacement^2
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -47,7 +49,8 @@ inline WsLayout ws_layout(const md_batch *b)
     l.slot = o;        o = align256(o + size_t(b->N) * sizeof(int32_t));
     l.key = o;         o = align256(o + (size_t(b->N) + 16) * sizeof(int32_t));   // 64 B reads may pass the end
     l.vjp_partial = o; o = align256(o + size_t(b->n_units) * 2 * MD_MAX_TYPES * MD_MAX_TYPES * sizeof(double));
-    l.tile_partial = o; o = align256(o + size_t(b->C) * 2 * sizeof(double));
+    l.tile_partial = o; o = align256(o + size_t(b->C) * kTilePartials * sizeof(double));
+    l.xnext = o;       o = align256(o + size_t(b->N) * 3 * sizeof(double));
     l.total = o;
     return l;
 }
@@ -249,9 +252,25 @@ bool tile_list_ok(const md_batch *b, const md_nlist *nl);
 int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_start, double rl2,
                const md_nlist *nl, int32_t *need, const uint32_t *gate, uint32_t *status,
                hipStream_t s);
+// Velocity-Verlet phase 3 (Integrate2 of this step, then Integrate1 of the
+// next, as in md_vv_step) applied by the tile force kernel to each home
+// atom right after its force: next positions go to xn/yn/zn, copied back
+// once every workgroup has read the current ones.
+struct VVFuse {
+    double *vx, *vy, *vz;
+    const double *xb, *yb, *zb;
+    const double *inv_mass;
+    int32_t ntypes;
+    double hdt, dt, lim2;
+    double *xn, *yn, *zn;
+    double *ke;
+    uint32_t *gate;
+};
+
 int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const md_lj *p,
                 int32_t prec, int32_t accumulate, const int32_t *cell_start, double *energy,
-                double *virial, double *tpart, int batch, uint32_t *status, hipStream_t s);
+                double *virial, double *tpart, int batch, const VVFuse *vvf, uint32_t *status,
+                hipStream_t s);
 
 // Per-replica fixed-order sums of partial slots k0 and k0+1 (md_forces.hip).
 void launch_finalize_sum2(int R, const int32_t *unit_off, const double *partial, int k0,

@@ -287,7 +287,7 @@ extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_n
             return MD_EINVAL;
         return tile_forces(b, atoms, nl, p, prec, accumulate, nl->cell_start, energy, virial,
                            ws_at<double>(ws, l.tile_partial), md_tune_get(MD_TUNE_PAIR_BATCH),
-                           status, as_stream(stream));
+                           nullptr, status, as_stream(stream));
     }
     ForceArgs a{b->atom_off, b->unit_rep, b->unit_off, b->box, atoms->x, atoms->y, atoms->z,
                 atoms->pos4, atoms->type, nl->count, nl->idx, nl->ld, nl->max_nbr, p->eps,
@@ -304,4 +304,36 @@ extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_n
         launch_finalize_sum2(b->R, b->unit_off, ws_at<const double>(ws, l.partial), 0, energy,
                              virial, s);
     return launch_status();
+}
+
+extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlist *nl,
+                               const md_lj *p, int32_t prec, double dt, const double *inv_mass,
+                               int32_t ntypes, double skin, uint32_t *gate, double *ke,
+                               double *energy, double *virial, void *ws, size_t ws_bytes,
+                               uint32_t *status, void *stream)
+{
+    using namespace md;
+    int e = check_batch(b);
+    if (e != MD_OK) return e;
+    if (!atoms || !atoms->x || !atoms->y || !atoms->z || !atoms->fx || !atoms->fy ||
+        !atoms->fz || !atoms->vx || !atoms->vy || !atoms->vz || !atoms->xb || !atoms->yb ||
+        !atoms->zb || !nl || !nl->count || !nl->idx || !p || !p->eps || !p->sig || !ws ||
+        !inv_mass || !gate)
+        return MD_EINVAL;
+    if (nl->mode != MD_TILE_FULL) return MD_EUNSUPPORTED;
+    if (nl->max_nbr < 1 || nl->ld < b->N || nl->ld % 64 != 0) return MD_EINVAL;
+    if (p->ntypes != 1 || !(p->rc > 0.0)) return p->ntypes > 1 ? MD_EUNSUPPORTED : MD_EINVAL;
+    if (ntypes < 1 || ntypes > MD_MAX_TYPES || (ntypes > 1 && !atoms->type)) return MD_EINVAL;
+    if (prec != MD_FP64 && prec != MD_FP32_MIXED) return MD_EINVAL;
+    if (!(skin >= 0.0) || !(dt > 0.0)) return MD_EINVAL;
+    const WsLayout l = ws_layout(b);
+    if (ws_bytes < l.total) return MD_ENOWS;
+    if (!tile_list_ok(b, nl) || !nl->cell_start || nl->tile_types > 1) return MD_EINVAL;
+    double *xn = ws_at<double>(ws, l.xnext);
+    const VVFuse f{atoms->vx, atoms->vy, atoms->vz, atoms->xb, atoms->yb, atoms->zb, inv_mass,
+                   ntypes, 0.5 * dt, dt, 0.25 * skin * skin, xn, xn + b->N, xn + 2 * size_t(b->N),
+                   ke, gate};
+    return tile_forces(b, atoms, nl, p, prec, 0, nl->cell_start, energy, virial,
+                       ws_at<double>(ws, l.tile_partial), md_tune_get(MD_TUNE_PAIR_BATCH), &f,
+                       status, as_stream(stream));
 }

@@ -38,7 +38,8 @@ struct TileArgs {
     double rc;
     double *fx, *fy, *fz;
     int32_t accumulate;
-    double *tpart;    // [n_tiles * 2]
+    double *tpart;    // [n_tiles * kTilePartials]
+    VVFuse vv;        // FUSE variant only
     uint32_t *status;
     int32_t R;
 };
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
 // Typed lists: LJ constants of type pair (ti, tj) at ti * kTileMaxTypes + tj.
 constexpr int kTileMaxTypes = MD_TILE_MAX_TYPES;
 
-template <class SH, int PREC, int U, bool P4, bool TYPED>
+template <class SH, int PREC, int U, bool P4, bool TYPED, bool FUSE>
 __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
 {
     constexpr int TB = SH::TB, CAP = SH::CAP;
@@ -256,10 +257,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
     const int t = xcd_chunked(blockIdx.x, gridDim.x, kTileXcdChunk);
     const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
     if (tile_home_atoms(s, a.cell_start) == 0) {
-        if (threadIdx.x == 0) {
-            a.tpart[size_t(t) * 2 + 0] = 0.0;
-            a.tpart[size_t(t) * 2 + 1] = 0.0;
-        }
+        if (threadIdx.x < kTilePartials) a.tpart[size_t(t) * kTilePartials + threadIdx.x] = 0.0;
         return;
     }
     const PolyConst pc = poly_const(a.eps[0], a.sig[0], a.rc, a.shift);
@@ -274,7 +272,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
         }
     }
     const int total = stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP);
-    double e_acc = 0.0, w_acc = 0.0;
+    double e_acc = 0.0, w_acc = 0.0, ke_acc = 0.0, d2_max = 0.0;
     if (total > CAP) {
         if (threadIdx.x == 0 && a.status) atomicOr(a.status, MD_F_TILE_OVERFLOW);
     } else {
@@ -340,34 +338,92 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
                 a.fz[i] = c.fz;
             }
             if (a.status && !isfinite(c.fx + c.fy + c.fz + ed)) atomicOr(a.status, MD_F_NONFINITE);
+            if (FUSE) {
+                // md_vv_step phase 3 on this atom with the force just computed
+                const VVFuse &f = a.vv;
+                const double im = f.inv_mass[f.ntypes > 1 ? a.type[i] : 0];
+                const double k = f.hdt * im;
+                double vx = f.vx[i], vy = f.vy[i], vz = f.vz[i];
+                vx = fma(k, c.fx, vx);
+                vy = fma(k, c.fy, vy);
+                vz = fma(k, c.fz, vz);
+                ke_acc += 0.5 * (vx * vx + vy * vy + vz * vz) / im;
+                vx = fma(k, c.fx, vx);
+                vy = fma(k, c.fy, vy);
+                vz = fma(k, c.fz, vz);
+                const double x = fma(f.dt, vx, xi);
+                const double y = fma(f.dt, vy, yi);
+                const double z = fma(f.dt, vz, zi);
+                f.xn[i] = x;
+                f.yn[i] = y;
+                f.zn[i] = z;
+                const double ex = x - f.xb[i], ey = y - f.yb[i], ez = z - f.zb[i];
+                d2_max = fmax(d2_max, ex * ex + ey * ey + ez * ez);
+                f.vx[i] = vx;
+                f.vy[i] = vy;
+                f.vz[i] = vz;
+            }
         }
     }
     const double es = block_sum_n<TB>(e_acc, red);
     const double ws = block_sum_n<TB>(w_acc, red);
+    double ks = 0.0, dm = 0.0;
+    if (FUSE) {
+        ks = block_sum_n<TB>(ke_acc, red);
+        dm = block_max_n<TB>(d2_max, red);
+    }
     if (threadIdx.x == 0) {
-        a.tpart[size_t(t) * 2 + 0] = es;
-        a.tpart[size_t(t) * 2 + 1] = ws;
+        double *tp = a.tpart + size_t(t) * kTilePartials;
+        tp[0] = es;
+        tp[1] = ws;
+        tp[2] = ks;
+        tp[3] = dm;
     }
 }
 
-// Per replica: fixed-order sums of its tiles' partials.
+// Next positions of the fused call back into the position planes (and the
+// packed copy when present).
+__global__ __launch_bounds__(kUnit) void k_copy_next(int32_t n, const double *__restrict__ xn,
+                                                     const double *__restrict__ yn,
+                                                     const double *__restrict__ zn, double *x,
+                                                     double *y, double *z, double *pos4)
+{
+    const int i = blockIdx.x * kUnit + threadIdx.x;
+    if (i >= n) return;
+    const double xv = xn[i], yv = yn[i], zv = zn[i];
+    x[i] = xv;
+    y[i] = yv;
+    z[i] = zv;
+    if (pos4) reinterpret_cast<double4 *>(pos4)[i] = make_double4(xv, yv, zv, 0.0);
+}
+
+// Per replica: fixed-order sums of its tiles' partials (energy, virial,
+// kinetic energy) and the largest displacement (the rebuild gate).
 __global__ __launch_bounds__(kFin) void k_tile_finalize(const int32_t *tile_off,
                                                         const double *tpart, double *energy,
-                                                        double *virial)
+                                                        double *virial, double *ke,
+                                                        uint32_t *gate, double lim2)
 {
     __shared__ double red[kFin / kWave];
     const int r = blockIdx.x;
-    double s0 = 0.0, s1 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, m = 0.0;
 #pragma unroll 4
     for (int t = tile_off[r] + threadIdx.x; t < tile_off[r + 1]; t += kFin) {
-        s0 += tpart[size_t(t) * 2];
-        s1 += tpart[size_t(t) * 2 + 1];
+        const double *tp = tpart + size_t(t) * kTilePartials;
+        s0 += tp[0];
+        s1 += tp[1];
+        if (ke) s2 += tp[2];
+        if (gate) m = fmax(m, tp[3]);
     }
     s0 = block_sum_n<kFin>(s0, red);
     s1 = block_sum_n<kFin>(s1, red);
+    if (ke) s2 = block_sum_n<kFin>(s2, red);
+    if (gate) m = block_max_n<kFin>(m, red);
     if (threadIdx.x == 0) {
         if (energy) energy[r] = s0;
         if (virial) virial[r] = s1;
+        if (ke) ke[r] = s2;
+        if (gate) gate[r] = m > lim2 ? 1u : 0u;
     }
 }
 
@@ -469,7 +525,8 @@ int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_sta
 
 int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const md_lj *p,
                 int32_t prec, int32_t accumulate, const int32_t *cell_start, double *energy,
-                double *virial, double *tpart, int batch, uint32_t *status, hipStream_t s)
+                double *virial, double *tpart, int batch, const VVFuse *vvf, uint32_t *status,
+                hipStream_t s)
 {
     TileArgs a = tile_args(b, atoms, nl);
     a.cell_start = cell_start;
@@ -482,34 +539,44 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
     a.fz = atoms->fz;
     a.accumulate = accumulate;
     a.tpart = tpart;
+    if (vvf) a.vv = *vvf;
     a.status = status;
     const dim3 grid(nl->n_tiles);
     const bool p4 = tile_stage_packed() && atoms->pos4;
     const bool big = batch >= 8;
     const bool typed = p->ntypes > 1;
+    const bool fuse = vvf != nullptr;
     with_tile_shape([&](auto sh) {
         using SH = decltype(sh);
         const dim3 blk(SH::TB);
-#define MD_TILE_LAUNCH(P, U, T)                                                          \
-    do {                                                                                 \
-        if (p4) hipLaunchKernelGGL((k_tile_lj<SH, P, U, true, T>), grid, blk, 0, s, a);  \
-        else hipLaunchKernelGGL((k_tile_lj<SH, P, U, false, T>), grid, blk, 0, s, a);    \
+#define MD_TILE_LAUNCH(P, U, T, F)                                                          \
+    do {                                                                                    \
+        if (p4) hipLaunchKernelGGL((k_tile_lj<SH, P, U, true, T, F>), grid, blk, 0, s, a);  \
+        else hipLaunchKernelGGL((k_tile_lj<SH, P, U, false, T, F>), grid, blk, 0, s, a);    \
     } while (0)
-        if (typed) {
-            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, true);
-            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, true);
+        if (fuse) {
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, false, true);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, false, true);
+        } else if (typed) {
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, true, false);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, true, false);
         } else if (prec == MD_FP64) {
-            if (big) MD_TILE_LAUNCH(MD_FP64, 16, false);
-            else MD_TILE_LAUNCH(MD_FP64, 8, false);
+            if (big) MD_TILE_LAUNCH(MD_FP64, 16, false, false);
+            else MD_TILE_LAUNCH(MD_FP64, 8, false, false);
         } else {
-            if (big) MD_TILE_LAUNCH(MD_FP32_MIXED, 16, false);
-            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, false);
+            if (big) MD_TILE_LAUNCH(MD_FP32_MIXED, 16, false, false);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, false, false);
         }
 #undef MD_TILE_LAUNCH
     });
-    if (energy || virial)
+    double *ke = fuse ? vvf->ke : nullptr;
+    uint32_t *gate = fuse ? vvf->gate : nullptr;
+    if (energy || virial || ke || gate)
         hipLaunchKernelGGL(k_tile_finalize, dim3(b->R), dim3(kFin), 0, s, nl->tile_off, tpart,
-                           energy, virial);
+                           energy, virial, ke, gate, fuse ? vvf->lim2 : 0.0);
+    if (fuse)
+        hipLaunchKernelGGL(k_copy_next, dim3((b->N + kUnit - 1) / kUnit), dim3(kUnit), 0, s, b->N,
+                           vvf->xn, vvf->yn, vvf->zn, atoms->x, atoms->y, atoms->z, atoms->pos4);
     return launch_status();
 }
 

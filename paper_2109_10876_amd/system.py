@@ -53,7 +53,7 @@ class MDSystem:
     def __init__(self, natoms, box, pos, vel, types=None, eps=1.0, sig=1.0, mass=None,
                  rc=2.5, skin=0.3, dt=0.005, shift=1, mode="full", prec="fp64",
                  max_nbr=None, pos4=None, bonds=None, fene=(30.0, 1.5), langevin=None,
-                 tile_cells=None, tile_rows=(1, 1), device="cuda"):
+                 tile_cells=None, tile_rows=(1, 1), fuse=True, device="cuda"):
         self.lib = abi.load()
         self.dev = torch.device(device)
         natoms = np.asarray(natoms, dtype=np.int32).ravel()
@@ -198,6 +198,10 @@ class MDSystem:
             self.langevin_cfg = (float(gamma), float(temp), int(seed))
             self.mass_t = f64(mass)
             self.noise_step = torch.tensor([int(step0)], dtype=torch.int64, device=d)
+        # pure pair forces on tile lists: the force call also advances the
+        # step (md_lj_forces_vv); bonds or a thermostat need the split calls
+        self.fuse = bool(fuse) and self.mode == abi.MD_TILE_FULL and self.bonds is None \
+            and self.langevin_cfg is None and self.ntypes == 1
 
     @staticmethod
     def _atoms_struct(s):
@@ -260,6 +264,15 @@ class MDSystem:
             ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.nlist),
             ctypes.byref(self.lj), self.prec, int(accumulate), _ptr(self.energy),
             _ptr(self.virial), _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
+
+    def forces_vv(self):
+        """Forces at the current positions, then velocity-Verlet phase 3, in
+        one call (pure pair forces on tile lists)."""
+        check("md_lj_forces_vv", self.lib.md_lj_forces_vv(
+            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.nlist),
+            ctypes.byref(self.lj), self.prec, self.dt, _ptr(self.inv_mass), self.ntypes,
+            self.skin, _ptr(self.gate), _ptr(self.ke), _ptr(self.energy), _ptr(self.virial),
+            _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
 
     def vv(self, phase):
         check("md_vv_step", self.lib.md_vv_step(
@@ -338,22 +351,53 @@ class MDSystem:
         self.build()
         self.all_forces()
 
-    def run(self, steps, check_every=50):
-        """`steps` full steps (Integrate2 of step s fused with Integrate1 of s+1)."""
-        for s in range(steps):
-            self.step_body(first=(s == 0))
-            if check_every and (s + 1) % check_every == 0:
-                self.ensure_list()
+    def fused_body(self):
+        """The same work in the fused order: the forces of one step with its
+        Integrate2 and the next step's Integrate1 (one call), then the gated
+        re-sort and list build of the next step."""
+        self.forces_vv()
+        self.sort()
+        self.build()
+
+    def _body(self):
+        if self.fuse:
+            self.fused_body()
+        else:
+            self.step_body(first=False)
+
+    def _head(self):
+        # first step up to its forces (fused: up to its list build)
+        if self.fuse:
+            self.vv(1)
+            self.sort()
+            self.build()
+        else:
+            self.step_body(first=True)
+
+    def _tail(self):
+        # last step's forces (fused) and the final half kick
+        if self.fuse:
+            self.all_forces()
         self.vv(2)
 
+    def run(self, steps, check_every=50):
+        """`steps` full steps (Integrate2 of step s fused with Integrate1 of s+1)."""
+        self._head()
+        for s in range(1, steps):
+            self._body()
+            if check_every and s % check_every == 0:
+                self.ensure_list()
+        self._tail()
+
     def capture(self, k):
-        """Capture k fused steps (Integrate2+Integrate1, gated re-sort and list
-        build, forces) as one HIP graph; replays launch on the current stream."""
+        """Capture k repeated steps (Integrate2+Integrate1, gated re-sort and
+        list build, forces) as one HIP graph; replays launch on the current
+        stream."""
         torch.cuda.synchronize(self.dev)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             for _ in range(k):
-                self.step_body(first=False)
+                self._body()
         torch.cuda.synchronize(self.dev)
         self._graph = (k, g)
         return g
@@ -364,13 +408,13 @@ class MDSystem:
         if self._graph is None or self._graph[0] != k:
             self.capture(k)
         kk, g = self._graph
-        self.step_body(first=True)
+        self._head()
         rest = steps - 1
         for _ in range(rest // kk):
             g.replay()
         for _ in range(rest % kk):
-            self.step_body(first=False)
-        self.vv(2)
+            self._body()
+        self._tail()
 
     # ------------------------------------------------------------ readback
     def order(self):

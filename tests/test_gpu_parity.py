@@ -588,3 +588,62 @@ def test_typed_tile_list_is_required_for_several_types(c1_snapshot):
     one.nlist.tile_types = 2
     with pytest.raises(abi.MDError):
         one.forces()
+
+
+@pytest.mark.parametrize("rows", [(1, 1), (2, 2)])
+def test_fused_force_step_trajectory_matches_oracle(rows):
+    # md_lj_forces_vv: the forces of step t with its Integrate2 and the
+    # Integrate1 of step t + 1 in one call; same schedule, energies and
+    # kinetic energies as the oracle's 100 NVE steps
+    cfg = md_inputs.lj_fluid(10, temperature=0.72, seed=1)
+    say(f"case: fused force+step trajectory {rows}")
+    s = _system(cfg, mode="tile", prec="fp64", tile_rows=rows)
+    assert s.fuse
+    s.setup()
+    flags, ek, ep = [], [], []
+    s.vv(1)
+    flags.append(int(s.gate[0].item()))
+    s.sort()
+    s.build()
+    for t in range(1, cfg.steps):
+        s.forces_vv()
+        ep.append(float(s.energy[0]))
+        ek.append(float(s.ke[0]))
+        flags.append(int(s.gate[0].item()))
+        s.sort()
+        s.build()
+    s.forces()
+    ep.append(float(s.energy[0]))
+    s.vv(2)
+    ek.append(float(s.ke[0]))
+    assert s.ensure_list() == 0
+    ref = oracle.md_run(cfg.pos, cfg.vel, cfg.box[0], RC, SKIN, cfg.dt, cfg.steps)
+    assert flags == list(ref["rebuild"].astype(int))
+    assert np.abs(s.positions() - ref["pos"]).max() < 1e-9
+    assert np.abs(s.velocities() - ref["vel"]).max() < 1e-9
+    np.testing.assert_allclose(ep, ref["epot"][1:], rtol=1e-10)
+    np.testing.assert_allclose(ek, ref["ekin"][1:], rtol=1e-10)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fused_and_split_steps_are_bitwise_equal(prec):
+    # same FMA sequence in one kernel or in md_lj_forces + md_vv_step:
+    # positions and velocities equal bit for bit, also through graphs
+    cfg = md_inputs.lj_fluid(8, temperature=1.5, seed=25)
+    say(f"case: fused vs split {prec}")
+    a = _system(cfg, mode="tile", prec=prec, fuse=False)
+    b = _system(cfg, mode="tile", prec=prec)
+    c = _system(cfg, mode="tile", prec=prec)
+    assert not a.fuse and b.fuse
+    for x in (a, b, c):
+        x.setup()
+    a.run(40, check_every=0)
+    b.run(40, check_every=0)
+    c.run_graphed(40, k=6)
+    for x in (a, b, c):
+        assert x.ensure_list() == 0
+    assert np.array_equal(a.positions(), b.positions())
+    assert np.array_equal(a.velocities(), b.velocities())
+    assert np.array_equal(b.positions(), c.positions())
+    assert np.array_equal(a.forces_np(), b.forces_np())
+    assert float(b.ke[0]) == pytest.approx(float(a.ke[0]), rel=1e-12)
