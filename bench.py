@@ -37,6 +37,10 @@ VALU_PEAK_TFLOPS = 78.6
 # accumulation (6), energy (5) and virial (2).
 FLOPS_PER_ENTRY = 9
 FLOPS_PER_PAIR_IN_RC = 20
+# Velocity-Verlet work per atom when fused into the force kernel: two half
+# kicks (2 x 6), kinetic energy (8), drift (6), displacement from the build
+# positions and its running maximum (9), and the step factor (1).
+FLOPS_PER_ATOM_VV = 36
 
 # Memory bytes per md_lj_forces launch on this workload from rocprofv3
 # FETCH_SIZE and WRITE_SIZE (FETCH x 2.0, WRITE x 1.0: the factors a plain
@@ -122,22 +126,27 @@ def time_path(cfg, prec, steps, warmup, tuned, graph_k=50):
         s.ensure_list()
     else:
         raise RuntimeError("list overflow persisted")
-    # dominant kernel: md_lj_forces, timed launch by launch with HIP events
-    # on the stream it is launched on
+    # dominant kernel: the pair-force kernel of the step (fused with the
+    # integrator on pure-LJ tile runs), timed by libmd itself with HIP events
+    # around each of its launches on their stream, over nrep eager steps of
+    # the same configuration right after the timed region
+    import ctypes
+    from paper_2109_10876_amd import _abi
+    lib = _abi.load()
     nrep = 50
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(nrep)]
     torch.cuda.synchronize()
-    for a, b in ev:
-        a.record(stream)
-        s.forces()
-        b.record(stream)
-    torch.cuda.synchronize()
-    f_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    assert lib.md_kernel_timing_start(nrep) == 0
+    s.run(nrep + 1, check_every=0)
+    f_ms, n_timed = ctypes.c_double(), ctypes.c_int32()
+    assert lib.md_kernel_timing_read(ctypes.byref(f_ms), ctypes.byref(n_timed)) == 0
+    assert n_timed.value == nrep, n_timed.value
+    f_ms = f_ms.value
+    s.ensure_list()
+    s.forces()   # forces at the final positions for the snapshot
     mean_k = float(s.count.double().mean().item())
     npairs = pairs_within_rc(s)
     snap = (s.positions(), s.forces_np())
-    return s, ms, f_ms, mean_k, npairs, snap
+    return s, ms, f_ms, mean_k, npairs, snap, bool(s.fuse)
 
 
 def time_workload(name, steps, warmup=10):
@@ -285,25 +294,32 @@ def main():
     out, snaps = {}, {}
     for prec in ("mixed", "fp64"):
         log(f"[{prec}] timing {args.steps} steps after {args.warmup} warm-up steps")
-        s, ms, f_ms, mean_k, npairs, snap = time_path(cfg, prec, args.steps, args.warmup, tuned)
+        s, ms, f_ms, mean_k, npairs, snap, fused = time_path(cfg, prec, args.steps, args.warmup, tuned)
         snaps[prec] = snap
-        # algorithmic bytes of one md_lj_forces launch: per atom the list
-        # column (4 B per entry, 2 B for tile-local lists), count (4 B), own
-        # position (24 B) and force write (24 B); neighbour positions are
-        # cache- or LDS-resident
+        # algorithmic bytes of one pair-kernel launch: per atom the list
+        # entries (4 B each, 2 B in tile-local lists), count (4 B), own
+        # position (24 B) and force write (24 B), neighbour positions being
+        # cache- or LDS-resident; fused with the integrator also velocity
+        # read and write, build-time position read and next position write
+        # (4 x 24 B)
         ebytes = 2.0 if tuned["mode"] == "tile" else 4.0
-        bytes_launch = s.N * (ebytes * mean_k + 4 + 24 + 24)
+        bytes_launch = s.N * (ebytes * mean_k + 4 + 24 + 24 + (96 if fused else 0))
         gbs = bytes_launch / (f_ms * 1e-3) / 1e9
         # algorithmic flops of one launch: full list, so every unordered pair
-        # inside rc is visited from both ends
-        flops_launch = s.N * mean_k * FLOPS_PER_ENTRY + 2 * npairs * FLOPS_PER_PAIR_IN_RC
+        # inside rc is visited from both ends; fused, the integrator's flops
+        # per atom on top
+        flops_launch = (s.N * mean_k * FLOPS_PER_ENTRY + 2 * npairs * FLOPS_PER_PAIR_IN_RC
+                        + (s.N * FLOPS_PER_ATOM_VV if fused else 0))
         tfs = flops_launch / (f_ms * 1e-3) / 1e12
         traffic = traffic_bytes = None
         counted = COUNTED_TRAFFIC.get(tuned["mode"])
         if counted and force_kernel_src_hash(tuned["mode"]) == counted["src_sha256_16"]:
             traffic_bytes = counted["bytes_per_launch"][prec]
             traffic = traffic_bytes / (f_ms * 1e-3) / 1e9
-        kernel = "md_lj_forces (%s)" % ("k_tile_lj" if tuned["mode"] == "tile" else "k_lj")
+        if fused:
+            kernel = "md_lj_forces_vv (k_tile_lj fused with velocity-Verlet)"
+        else:
+            kernel = "md_lj_forces (%s)" % ("k_tile_lj" if tuned["mode"] == "tile" else "k_lj")
         hbm_view = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
                     "bytes_per_launch": bytes_launch, "kernel": kernel}

@@ -91,12 +91,16 @@ extern "C" {
  * periodically with the image the wrap implies), the cells of unwrapped
  * x = a-1 .. b+1 of that row (x = -1 is cell nx-1 one box length to the
  * left, x = nx is cell 0 one box length to the right), each cell's atoms in
- * index order, concatenated.  Entry k of atom i is the uint16
- * ((uint16_t *)idx)[k * ld + i] = 8 p + t, where p is the position of the
- * neighbour in its tile's staged sequence (its image is the one its staged
- * row and cell imply) and t is its atom type when tile_types > 1 (else 0).  Entries count[i] .. (count[i] rounded up to 16) - 1
- * hold 8 md_tile_capacity(), a pad slot far from every atom, so max_nbr
- * must be a multiple of 16, and ld at most 2^23 (MD_EINVAL otherwise).  A tile whose staged
+ * index order, concatenated.  Entries come in blocks of 8 per atom: entry k
+ * of atom i is the uint16 ((uint16_t *)idx)[(k / 8) * 8 ld + 8 i + k % 8]
+ * = 8 p + t, where p is the position of the neighbour in its tile's staged
+ * sequence (its image is the one its staged row and cell imply) and t is its
+ * atom type when tile_types > 1 (else 0).  Entries count[i] .. (count[i]
+ * rounded up to 16) - 1 hold 8 md_tile_capacity(), a pad slot far from every
+ * atom, so max_nbr must be a multiple of 16, ld at most 2^23 and idx
+ * 16-byte aligned (MD_EINVAL otherwise).  Pairs are those within rc + skin up to rounding: the tile
+ * build may keep a pair whose distance exceeds rc + skin by rounding only.
+ * A tile whose staged
  * sequence exceeds md_tile_capacity() (at most MD_TILE_SLOTS) raises
  * MD_F_TILE_OVERFLOW (the list is then unusable: rebuild with smaller
  * tiles).  md_lj_forces takes a tile-local list whose tile_types equals
@@ -138,7 +142,8 @@ typedef struct md_atoms {
 } md_atoms;
 
 /* Verlet list in ELL layout, column-major so that entry k of consecutive
- * atoms is contiguous: entry k of atom i is idx[k * ld + i]. */
+ * atoms is contiguous: entry k of atom i is idx[k * ld + i] (MD_TILE_FULL:
+ * uint16 entries in blocks of 8, see "Tile-local lists"). */
 typedef struct md_nlist {
     int32_t  mode;            /* MD_HALF, MD_FULL or MD_TILE_FULL                 */
     int32_t  max_nbr;         /* capacity per atom (columns)                      */
@@ -207,6 +212,15 @@ const char *md_strerror(int code);
 #define MD_TUNE_NKNOBS     4
 int md_tune_set(int32_t knob, int32_t value);
 int md_tune_get(int32_t knob);
+/* Measurement aid.  md_kernel_timing_start(n) (0 <= n <= 1024) has the next
+ * n pair-force kernel launches of md_lj_forces and md_lj_forces_vv that are
+ * not under stream capture record a HIP event pair around the kernel alone,
+ * on the launch's stream; md_kernel_timing_read waits for the recorded pairs
+ * and gives their mean duration in ms and their count.  Process-wide state,
+ * not thread-safe; MD_EINVAL for n out of range or null outputs, MD_EHIP if
+ * an event cannot be read. */
+int md_kernel_timing_start(int32_t n);
+int md_kernel_timing_read(double *mean_ms, int32_t *count);
 /* Staged-atom capacity per tile of MD_TILE_FULL lists for the current
  * MD_TUNE_TILE_THREADS and MD_TUNE_TILE_SLOTS (a tile whose staged sequence
  * is larger raises MD_F_TILE_OVERFLOW). */

@@ -46,7 +46,9 @@ MD_TUNE_TILE_STAGE_PACKED = 2
 MD_TUNE_TILE_SLOTS = 3
 
 EXPORTS = (
-    "md_abi_version", "md_strerror", "md_tune_set", "md_tune_get", "md_tile_capacity", "md_tile_max_cells", "md_plan_sizes", "md_plan_fill",
+    "md_abi_version", "md_strerror", "md_tune_set", "md_tune_get", "md_tile_capacity",
+    "md_tile_max_cells", "md_kernel_timing_start", "md_kernel_timing_read", "md_plan_sizes",
+    "md_plan_fill",
     "md_tile_plan",
     "md_workspace_bytes", "md_cell_sort", "md_verlet_build", "md_lj_forces",
     "md_vv_step", "md_lj_forces_vv", "md_lj_forces_vjp", "md_fene_forces", "md_langevin",
@@ -121,6 +123,10 @@ def load():
     lib.md_tile_capacity.argtypes = []
     lib.md_tile_max_cells.restype = ctypes.c_int
     lib.md_tile_max_cells.argtypes = []
+    lib.md_kernel_timing_start.restype = ctypes.c_int
+    lib.md_kernel_timing_start.argtypes = [_i32]
+    lib.md_kernel_timing_read.restype = ctypes.c_int
+    lib.md_kernel_timing_read.argtypes = [P(_dbl), P(_i32)]
     lib.md_tile_plan.restype = ctypes.c_int
     lib.md_tile_plan.argtypes = [_i32, _vp, _i32, _i32, _i32, _vp, _vp]
     lib.md_workspace_bytes.restype = ctypes.c_size_t

@@ -272,6 +272,11 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
                 double *virial, double *tpart, int batch, const VVFuse *vvf, uint32_t *status,
                 hipStream_t s);
 
+// Events around a pair-force kernel launch while md_kernel_timing_start
+// asks for them (md_timing.hip): begin returns a slot or -1, end takes it.
+int timing_begin(hipStream_t s);
+void timing_end(int slot, hipStream_t s);
+
 // Per-replica fixed-order sums of partial slots k0 and k0+1 (md_forces.hip).
 void launch_finalize_sum2(int R, const int32_t *unit_off, const double *partial, int k0,
                           double *out0, double *out1, hipStream_t s);

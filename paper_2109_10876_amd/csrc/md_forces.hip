@@ -298,8 +298,10 @@ extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_n
     if (half && !accumulate)
         hipLaunchKernelGGL(k_zero3, dim3((b->N + kUnit - 1) / kUnit), dim3(kUnit), 0, s, b->N,
                            atoms->fx, atoms->fy, atoms->fz);
+    const int timed = timing_begin(s);
     launch_lj(a, b->n_units, prec, half, p->ntypes > 1, md_tune_get(MD_TUNE_PAIR_BATCH),
               atoms->pos4 != nullptr, s);
+    timing_end(timed, s);
     if (energy || virial)
         launch_finalize_sum2(b->R, b->unit_off, ws_at<const double>(ws, l.partial), 0, energy,
                              virial, s);

@@ -291,4 +291,98 @@ __device__ __forceinline__ int home_atom(const TileSpec &s, const Stage &st, int
     return st.home_g0[h] + (k - st.home_start[h]);
 }
 
+// Arguments of the tile kernels (list build and forces).
+struct TileArgs {
+    const int32_t *tile_rep, *tile_off, *ncell, *cell_off;
+    const double *box;
+    const uint32_t *gate;
+    const double *x, *y, *z, *pos4;
+    const int32_t *type;
+    int32_t tile_types;   // > 1: list entries carry the neighbour's type
+    const int32_t *cell_start;
+    TileGrid g;
+    int32_t n_tiles, max_nbr, ld;
+    int32_t *count;
+    uint16_t *idx;
+    // build
+    double rl2;
+    int32_t *need, *tile_need;
+    // forces
+    const double *eps, *sig;
+    int32_t shift;
+    double rc;
+    double *fx, *fy, *fz;
+    int32_t accumulate;
+    double *tpart;    // [n_tiles * kTilePartials]
+    VVFuse vv;        // FUSE variant only
+    uint32_t *status;
+    int32_t R;
+};
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Tiles go to the XCDs in chunks of this many consecutive tiles.
+constexpr int kTileXcdChunk = 16;
+
+// Tile-list builds form column byte offsets with 24-bit multiplies (and the
+// whole list must span less than 4 GiB).
+constexpr int kTileMaxLd = 1 << 23;
+
+// Tile-local list layout: an atom's entries sit in blocks of 8 consecutive
+// uint16 values and the blocks of consecutive atoms are adjacent, so entry k
+// of atom i is the uint16 at (k / 8) 8 ld + 8 i + k % 8: one 16-byte load
+// fetches 8 entries of an atom, and a wave of consecutive atoms reads one
+// contiguous run.  Byte offset of that entry (below 4 GiB: the list is).
+constexpr int kEntryBlock = 8;
+
+__device__ __forceinline__ unsigned tile_entry_byte(int k, int i, int ld)
+{
+    return (unsigned(__umul24(unsigned(k) >> 3, unsigned(ld))) << 4) + (unsigned(i) << 4) +
+           ((unsigned(k) & 7u) << 1);
+}
+
+inline TileArgs tile_args(const md_batch *b, const md_atoms *atoms, const md_nlist *nl)
+{
+    TileArgs a{};
+    a.tile_rep = nl->tile_rep;
+    a.tile_off = nl->tile_off;
+    a.ncell = b->ncell;
+    a.cell_off = b->cell_off;
+    a.box = b->box;
+    a.x = atoms->x;
+    a.y = atoms->y;
+    a.z = atoms->z;
+    a.pos4 = atoms->pos4;
+    a.g = TileGrid{nl->tile_cells, nl->tile_py, nl->tile_pz};
+    a.n_tiles = nl->n_tiles;
+    a.max_nbr = nl->max_nbr;
+    a.ld = nl->ld;
+    a.count = nl->count;
+    a.idx = reinterpret_cast<uint16_t *>(nl->idx);
+    a.tile_need = nl->tile_need;
+    a.R = b->R;
+    a.type = atoms->type;
+    a.tile_types = nl->tile_types;
+    return a;
+}
+
+int tile_threads();
+
+// Calls f with the shape selected by MD_TUNE_TILE_THREADS and
+// MD_TUNE_TILE_SLOTS: the largest capacity of that workgroup size not above
+// the requested slot count (0: the largest there is).
+template <class F>
+inline void with_tile_shape(F &&f)
+{
+    const int slots = md_tune_get(MD_TUNE_TILE_SLOTS);
+    switch (tile_threads()) {
+    case 64: f(TileShape64{}); break;
+    case 128: f(TileShape128{}); break;
+    default:
+        if (slots == 0 || slots >= TileShape256::CAP) f(TileShape256{});
+        else if (slots >= TileShape256S2048::CAP) f(TileShape256S2048{});
+        else f(TileShape256S1536{});
+    }
+}
+
 }  // namespace md

@@ -478,19 +478,25 @@ class MDSystem:
             tables.append((np.array(home, dtype=np.int64), np.array(slots, dtype=np.int64)))
         return tables
 
+    def tile_entries(self):
+        """Tile-local list entries as [N, max_nbr] uint16 (entry k of atom i
+        sits at (k // 8) * 8 ld + 8 i + k % 8 of the list)."""
+        idx = self.idx.cpu().numpy().view(np.uint16)[:self.max_nbr * self.ld]
+        idx = idx.reshape(self.max_nbr // 8, self.ld, 8)[:, :self.N, :]
+        return np.ascontiguousarray(idx.transpose(1, 0, 2).reshape(self.N, self.max_nbr))
+
     def list_pairs(self):
         """Verlet list as (id_i, id_j) pairs [P,2] plus decoded image codes
         (image codes are not decoded for tile-local lists: None)."""
         if self.mode == abi.MD_TILE_FULL:
             cnt = self.count.cpu().numpy()
-            idx = self.idx.cpu().numpy().view(np.uint16)[:self.max_nbr * self.ld]
-            idx = idx.reshape(self.max_nbr, self.ld)
+            ent = self.tile_entries()
             ids = self.id.cpu().numpy()
             out = []
             for home, slots in self.tile_slot_table():
                 for i in home:
                     n = min(cnt[i], self.max_nbr)
-                    js = slots[idx[:n, i].astype(np.int64) >> 3]
+                    js = slots[ent[i, :n].astype(np.int64) >> 3]
                     out.append(np.stack([np.full(n, ids[i]), ids[js]], 1))
             return np.concatenate(out), None
         cnt = self.count.cpu().numpy()

@@ -160,3 +160,16 @@ def test_calls_reject_bad_arguments_without_a_gpu():
     assert lib.md_lj_forces_vjp(P(ok), P(full), P(nl), P(lj1), 0, 8, 8, 8, None, 8, None, None,
                                 8, 1 << 30, None, None) == abi.MD_EUNSUPPORTED
     assert lib.md_vv_step(P(ok), P(full), 4, 0.005, 8, 1, 0.3, 8, None, 8, 1 << 30, None, None) == abi.MD_EINVAL
+
+
+def test_kernel_timing_arguments_and_empty_read():
+    # no launch is timed on the host: start and an empty read touch no GPU
+    import ctypes
+    lib = abi.load()
+    assert lib.md_kernel_timing_start(-1) == abi.MD_EINVAL
+    assert lib.md_kernel_timing_start(1025) == abi.MD_EINVAL
+    assert lib.md_kernel_timing_start(0) == abi.MD_OK
+    ms, n = ctypes.c_double(-1.0), ctypes.c_int32(-1)
+    assert lib.md_kernel_timing_read(ctypes.byref(ms), ctypes.byref(n)) == abi.MD_OK
+    assert n.value == 0 and ms.value == 0.0
+    assert lib.md_kernel_timing_read(None, ctypes.byref(n)) == abi.MD_EINVAL

@@ -481,13 +481,13 @@ def test_tile_list_padding_and_neighbour_overflow(c1_snapshot):
     s.ensure_list()
     assert s.max_nbr % 16 == 0 and s.max_nbr >= int(s.count.max().item())
     cnt = s.count.cpu().numpy()
-    idx = s.idx.cpu().numpy().view(np.uint16)[:s.max_nbr * s.ld].reshape(s.max_nbr, s.ld)
+    ent = s.tile_entries()
     pad = 8 * lib.md_tile_capacity()
     for i in range(0, s.N, 97):
         n = int(cnt[i])
         top = (n + 15) // 16 * 16
-        assert np.all(idx[n:top, i] == pad)
-        assert np.all(idx[:n, i] < pad) and np.all(idx[:n, i] % 8 == 0)
+        assert np.all(ent[i, n:top] == pad)
+        assert np.all(ent[i, :n] < pad) and np.all(ent[i, :n] % 8 == 0)
     s.forces()
     ref, e, _ = oracle.lj_forces(cfg.pos, cfg.box[0], RC, shift=1)
     assert np.abs(s.forces_np() - ref).max() < 1e-10
@@ -647,3 +647,19 @@ def test_fused_and_split_steps_are_bitwise_equal(prec):
     assert np.array_equal(b.positions(), c.positions())
     assert np.array_equal(a.forces_np(), b.forces_np())
     assert float(b.ke[0]) == pytest.approx(float(a.ke[0]), rel=1e-12)
+
+
+def test_kernel_timing_records_eager_pair_kernels_only(c1_snapshot):
+    import ctypes
+    from paper_2109_10876_amd import _abi as abi
+    lib = abi.load()
+    say("case: kernel timing")
+    s = _system(c1_snapshot, mode="tile", prec="fp64")
+    s.setup()
+    ms, n = ctypes.c_double(), ctypes.c_int32()
+    assert lib.md_kernel_timing_start(3) == 0
+    s.capture(2)   # launches under stream capture are not timed
+    for _ in range(4):
+        s.forces()  # four eager launches, the first three timed
+    assert lib.md_kernel_timing_read(ctypes.byref(ms), ctypes.byref(n)) == 0
+    assert n.value == 3 and 0.0 < ms.value < 100.0
