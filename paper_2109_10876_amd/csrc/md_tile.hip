@@ -27,7 +27,9 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
     __shared__ PolyConst ptab[TYPED ? kTileMaxTypes * kTileMaxTypes : 1];
     const int t = xcd_chunked(blockIdx.x, gridDim.x, kTileXcdChunk);
     const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
-    if (tile_home_atoms(s, a.cell_start) == 0) {
+    const HomeRows hr = home_rows(s, a.cell_start);
+    const int nh = hr.total;
+    if (nh == 0) {
         if (threadIdx.x < kTilePartials) a.tpart[size_t(t) * kTilePartials + threadIdx.x] = 0.0;
         return;
     }
@@ -42,34 +44,37 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
                                                        a.shift);
         }
     }
+    // Entries are LDS byte offsets, 8 to a 16-byte block, consumed U at a
+    // time while the next U are in flight; a list is padded with the pad
+    // slot to a multiple of 16 entries, so no entry needs a mask.  Block
+    // reads stay inside the allocation (index clamped to the last block) and
+    // LDS reads inside the staging planes (offset clamped to the pad slot).
+    constexpr int NB = U / kEntryBlock;
+    const int bmax = a.max_nbr / kEntryBlock - 1;
+    // Inputs of this thread's first home atom (threads past the last one
+    // take it again, unused): fetched before the staging so that the two
+    // share their latency.
+    int hk = threadIdx.x;
+    int i = home_index(hr, min(hk, nh - 1));
+    double xi = a.x[i], yi = a.y[i], zi = a.z[i];
+    int n = min(a.count[i], a.max_nbr);
+    int ti4 = TYPED ? a.type[i] * kTileMaxTypes : 0;
+    u32x4 cur[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        cur[b] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a.idx) + i +
+                                            size_t(min(b, bmax)) * a.ld);
     const int total = stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP);
     double e_acc = 0.0, w_acc = 0.0, ke_acc = 0.0, d2_max = 0.0;
     if (total > CAP) {
         if (threadIdx.x == 0 && a.status) atomicOr(a.status, MD_F_TILE_OVERFLOW);
     } else {
-        const int nh = st.home_start[s.hy * s.hz];
         const char *stb = reinterpret_cast<const char *>(st.x);
         constexpr int kY = int(sizeof(double)) * decltype(st)::kStride;
-        for (int hk = threadIdx.x; hk < nh; hk += TB) {
-            int dy, dz;
-            const int i = home_atom(s, st, hk, dy, dz);
-            const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
-            const int n = min(a.count[i], a.max_nbr);
-            const int ti4 = TYPED ? a.type[i] * kTileMaxTypes : 0;
+        while (hk < nh) {
             Acc c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
-            // Entries are LDS byte offsets, 8 to a 16-byte block, consumed U
-            // at a time while the next U are in flight; a list is padded
-            // with the pad slot to a multiple of 16 entries, so no entry
-            // needs a mask.  Block reads stay inside the allocation (index
-            // clamped to the last block) and LDS reads inside the staging
-            // planes (offset clamped to the pad slot).
-            constexpr int NB = U / kEntryBlock;
-            const int bmax = a.max_nbr / kEntryBlock - 1;
             const u32x4 *lb = reinterpret_cast<const u32x4 *>(a.idx) + i;
-            u32x4 cur[NB], nxt[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-                cur[b] = __builtin_nontemporal_load(lb + size_t(min(b, bmax)) * a.ld);
+            u32x4 nxt[NB];
             for (int k = 0; k < n; k += U) {
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
@@ -140,6 +145,19 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
                 f.vx[i] = vx;
                 f.vy[i] = vy;
                 f.vz[i] = vz;
+            }
+            hk += TB;
+            if (hk < nh) {
+                i = home_index(hr, hk);
+                xi = a.x[i];
+                yi = a.y[i];
+                zi = a.z[i];
+                n = min(a.count[i], a.max_nbr);
+                ti4 = TYPED ? a.type[i] * kTileMaxTypes : 0;
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    cur[b] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a.idx) + i +
+                                                        size_t(min(b, bmax)) * a.ld);
             }
         }
     }

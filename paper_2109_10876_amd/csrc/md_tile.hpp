@@ -97,8 +97,6 @@ struct TileStage {
     int row_g0[kMaxStagedRows][3];     // first atom index of the three pieces
     double row_dy[kMaxStagedRows], row_dz[kMaxStagedRows];  // shift of the row's image
     int cslot[kMaxStagedRows][kRowStage];  // start (within the row) of unwrapped cell a-1+k
-    int home_start[kMaxHomeRows + 1];  // prefix of home atoms over the home rows
-    int home_g0[kMaxHomeRows];         // first atom of each home row's run a..b
     static constexpr int kChunks = CAP / 64 + 1;
     int rowc[kChunks];                 // staged row holding slot 64 c (first row if several)
 };
@@ -140,7 +138,6 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
                           Stage &st, int cap)
 {
     const int tid = threadIdx.x;
-    const int nhome = s.hy * s.hz;
     const int nk = s.b - s.a + 4;       // cell starts a-1 .. b+2 per staged row
     const int nq = s.nrows * nk;
     const int lo = max(s.a - 1, 0), hi = min(s.b + 1, s.nx - 1);
@@ -179,13 +176,6 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
             st.row_dz[q] = dz;
         }
     }
-    if (tid >= TB - kMaxHomeRows && tid - (TB - kMaxHomeRows) < nhome) {
-        const int h = tid - (TB - kMaxHomeRows);
-        const int rb = s.coff + ((s.z0 + h / s.hy) * s.ny + (s.y0 + h % s.hy)) * s.nx;
-        const int g0 = cs[rb + s.a];
-        st.home_g0[h] = g0;
-        st.home_start[h + 1] = cs[rb + s.b + 1] - g0;   // count, summed below
-    }
     __syncthreads();
     // Phase 2, LDS only: cell starts within the row; wave 0 scans the row
     // lengths into row starts (and the chunk -> row table) and the home
@@ -202,15 +192,11 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
     }
     if (tid < kWave) {
         const int len = tid < s.nrows ? st.row_lw[tid] + st.row_main[tid] + st.row_rw[tid] : 0;
-        const int hc = (tid >= 1 && tid <= nhome) ? st.home_start[tid] : 0;
-        int pl = len, ph = hc;   // inclusive prefix sums over the lanes
+        int pl = len;   // inclusive prefix sum over the lanes
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
-            const int ul = __shfl_up(pl, o, kWave), uh = __shfl_up(ph, o, kWave);
-            if (tid >= o) {
-                pl += ul;
-                ph += uh;
-            }
+            const int ul = __shfl_up(pl, o, kWave);
+            if (tid >= o) pl += ul;
         }
         if (tid < s.nrows) {
             const int start = pl - len;
@@ -218,7 +204,6 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
             if (tid == s.nrows - 1) st.row_slot[s.nrows] = pl;
             for (int c = (start + 63) >> 6; c * 64 < pl && c < Stage::kChunks; ++c) st.rowc[c] = tid;
         }
-        if (tid <= nhome) st.home_start[tid] = ph;   // lane 0: 0
     }
     __syncthreads();
     const int total = st.row_slot[s.nrows];
@@ -277,18 +262,43 @@ __device__ __forceinline__ int tile_home_atoms(const TileSpec &s, const int32_t 
     return n;
 }
 
-// Home atom number k of the tile (0 .. home_start[hy hz]): its index and home
-// row offsets (dy, dz) relative to (y0, z0).
-template <class Stage>
-__device__ __forceinline__ int home_atom(const TileSpec &s, const Stage &st, int k, int &dy,
-                                         int &dz)
+// The home rows of a tile (runs of consecutive atoms, one per home row, in
+// row order), read from the cell starts alone so that a kernel can fetch its
+// home atoms' inputs while the tile is being staged.
+struct HomeRows {
+    int g0[kMaxHomeRows], n[kMaxHomeRows];
+    int rows, total;
+};
+
+__device__ __forceinline__ HomeRows home_rows(const TileSpec &s, const int32_t *__restrict__ cs)
 {
-    const int nhome = s.hy * s.hz;
-    int h = 0;
-    for (int q = 1; q < nhome; ++q) h += k >= st.home_start[q] ? 1 : 0;
-    dy = h % s.hy;
-    dz = h / s.hy;
-    return st.home_g0[h] + (k - st.home_start[h]);
+    HomeRows hr;
+    hr.rows = s.hy * s.hz;
+    hr.total = 0;
+#pragma unroll
+    for (int h = 0; h < kMaxHomeRows; ++h) {
+        hr.g0[h] = 0;
+        hr.n[h] = 0;
+        if (h < hr.rows) {
+            const int rb = s.coff + ((s.z0 + h / s.hy) * s.ny + (s.y0 + h % s.hy)) * s.nx;
+            hr.g0[h] = cs[rb + s.a];
+            hr.n[h] = cs[rb + s.b + 1] - hr.g0[h];
+            hr.total += hr.n[h];
+        }
+    }
+    return hr;
+}
+
+// Index of home atom number k (0 <= k < total) of the tile.
+__device__ __forceinline__ int home_index(const HomeRows &hr, int k)
+{
+    int i = hr.g0[0] + k, base = 0;
+#pragma unroll
+    for (int h = 1; h < kMaxHomeRows; ++h) {
+        base += hr.n[h - 1];
+        i = k >= base && h < hr.rows ? hr.g0[h] + (k - base) : i;
+    }
+    return i;
 }
 
 // Arguments of the tile kernels (list build and forces).
