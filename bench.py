@@ -42,15 +42,18 @@ FLOPS_PER_PAIR_IN_RC = 20
 # positions and its running maximum (9), and the step factor (1).
 FLOPS_PER_ATOM_VV = 36
 
-# Memory bytes per md_lj_forces launch on this workload from rocprofv3
+# Memory bytes per pair-kernel launch on this workload from rocprofv3
 # FETCH_SIZE and WRITE_SIZE (FETCH x 2.0, WRITE x 1.0: the factors a plain
 # 512 MiB device copy needs to read back its true size), valid only for the
 # kernel source they were taken on (profiles/k_tile_lj_lj1m_hbm_counters.md).
-# keyed by list form; each entry: source hash of the kernel's files and
-# calibrated bytes per launch for the FP32-mixed and FP64 paths
+# Keyed by list form ("_fused": the force kernel with the integrator fused
+# in); each entry: source hash of the kernel's files and calibrated bytes per
+# launch for the FP32-mixed and FP64 paths.
 COUNTED_TRAFFIC = {
-    "tile": {"src_sha256_16": "5ef30d4aebc84f3c",
-             "bytes_per_launch": {"mixed": 360239674, "fp64": 362201870}},
+    "tile_fused": {"src_sha256_16": "e7799dab388d2719",
+                   "bytes_per_launch": {"mixed": 393235558, "fp64": 392885248}},
+    "tile": {"src_sha256_16": "e7799dab388d2719",
+             "bytes_per_launch": {"mixed": 289807462, "fp64": 289978163}},
 }
 
 FORCE_KERNEL_SOURCES = {
@@ -312,7 +315,7 @@ def main():
                         + (s.N * FLOPS_PER_ATOM_VV if fused else 0))
         tfs = flops_launch / (f_ms * 1e-3) / 1e12
         traffic = traffic_bytes = None
-        counted = COUNTED_TRAFFIC.get(tuned["mode"])
+        counted = COUNTED_TRAFFIC.get(tuned["mode"] + ("_fused" if fused else ""))
         if counted and force_kernel_src_hash(tuned["mode"]) == counted["src_sha256_16"]:
             traffic_bytes = counted["bytes_per_launch"][prec]
             traffic = traffic_bytes / (f_ms * 1e-3) / 1e9
