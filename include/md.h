@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 1
+#define MD_ABI_VERSION 2
 
 /* ------------------------------------------------------------ return codes */
 #define MD_OK            0
@@ -163,6 +163,15 @@ typedef struct md_nlist {
     int32_t  *tile_need;      /* optional: largest staged count seen (overflow)   */
     const int32_t *cell_start;/* MD_TILE_FULL: the [C+1] cell ranges the list was
                                  built with (unchanged until the next rebuild)    */
+    int32_t  tile_src_cap;    /* MD_TILE_FULL: the md_tile_capacity() tile_src was
+                                 sized for; calls whose current capacity differs
+                                 return MD_EINVAL                              */
+    int32_t  _pad;
+    uint32_t *tile_src;       /* MD_TILE_FULL: [n_tiles * (tile_src_cap + 64)]
+                                 staging table of every tile (each staged slot's
+                                 source atom and image), written by
+                                 md_verlet_build and read by md_lj_forces and
+                                 md_lj_forces_vv; part of the list            */
 } md_nlist;
 
 /* Lennard-Jones parameters (Eq. lj: U = 4 eps [(sig/r)^12 - (sig/r)^6] for

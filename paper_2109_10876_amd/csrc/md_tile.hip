@@ -27,12 +27,6 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
     __shared__ PolyConst ptab[TYPED ? kTileMaxTypes * kTileMaxTypes : 1];
     const int t = xcd_chunked(blockIdx.x, gridDim.x, kTileXcdChunk);
     const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
-    const HomeRows hr = home_rows(s, a.cell_start);
-    const int nh = hr.total;
-    if (nh == 0) {
-        if (threadIdx.x < kTilePartials) a.tpart[size_t(t) * kTilePartials + threadIdx.x] = 0.0;
-        return;
-    }
     const PolyConst pc = poly_const(a.eps[0], a.sig[0], a.rc, a.shift);
     const double rc2 = a.rc * a.rc;
     if (TYPED) {
@@ -51,20 +45,36 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
     // LDS reads inside the staging planes (offset clamped to the pad slot).
     constexpr int NB = U / kEntryBlock;
     const int bmax = a.max_nbr / kEntryBlock - 1;
-    // Inputs of this thread's first home atom (threads past the last one
-    // take it again, unused): fetched before the staging so that the two
-    // share their latency.
+    // The home rows' cell starts, then the inputs of this thread's first
+    // home atom (threads past the last one take it again, unused), are
+    // fetched while the staging table loads are in flight; an empty tile
+    // (vacuum) stops there.
     int hk = threadIdx.x;
-    int i = home_index(hr, min(hk, nh - 1));
-    double xi = a.x[i], yi = a.y[i], zi = a.z[i];
-    int n = min(a.count[i], a.max_nbr);
-    int ti4 = TYPED ? a.type[i] * kTileMaxTypes : 0;
+    HomeRows hr;
+    int nh = 0, i = 0, n = 0, ti4 = 0;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
     u32x4 cur[NB];
+    const int total = stage_from_table<TB, P4>(
+        s, a.tile_src + size_t(t) * tab_stride(CAP), a.n_atoms, a.x, a.y, a.z, a.pos4, st, CAP, [&] {
+            hr = home_rows(s, a.cell_start);
+            nh = hr.total;
+            if (nh == 0) return false;
+            i = home_index(hr, min(hk, nh - 1));
+            xi = a.x[i];
+            yi = a.y[i];
+            zi = a.z[i];
+            n = min(a.count[i], a.max_nbr);
+            ti4 = TYPED ? a.type[i] * kTileMaxTypes : 0;
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-        cur[b] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a.idx) + i +
-                                            size_t(min(b, bmax)) * a.ld);
-    const int total = stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP);
+            for (int b = 0; b < NB; ++b)
+                cur[b] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a.idx) + i +
+                                                    size_t(min(b, bmax)) * a.ld);
+            return true;
+        });
+    if (total < 0) {
+        if (threadIdx.x < kTilePartials) a.tpart[size_t(t) * kTilePartials + threadIdx.x] = 0.0;
+        return;
+    }
     double e_acc = 0.0, w_acc = 0.0, ke_acc = 0.0, d2_max = 0.0;
     if (total > CAP) {
         if (threadIdx.x == 0 && a.status) atomicOr(a.status, MD_F_TILE_OVERFLOW);
@@ -230,7 +240,8 @@ bool tile_stage_packed() { return md_tune_get(MD_TUNE_TILE_STAGE_PACKED) != 0; }
 bool tile_list_ok(const md_batch *b, const md_nlist *nl)
 {
     return nl->n_tiles >= 1 && nl->n_tiles <= b->C && nl->tile_rep && nl->tile_off &&
-           (reinterpret_cast<uintptr_t>(nl->idx) & 15) == 0 &&
+           (reinterpret_cast<uintptr_t>(nl->idx) & 15) == 0 && nl->tile_src &&
+           nl->tile_src_cap == tile_capacity() &&
            nl->max_nbr % 16 == 0 && nl->ld <= kTileMaxLd && nl->tile_types >= 0 &&
            nl->tile_types <= MD_TILE_MAX_TYPES &&
            size_t(nl->max_nbr) * size_t(nl->ld) * 2 < (size_t(1) << 32) &&

@@ -111,8 +111,30 @@ __device__ __forceinline__ int staged_row(const TileSpec &s, int dy, int dz)
     return (dz + 1) * (s.hy + 2) + (dy + 1);
 }
 
+// Staging table of a tile, written by the list build for the force kernel:
+// word sl (< staged count) holds slot sl's source atom in its low 26 bits
+// and the image shift of x, y, z in two bits each (0: none, 1: +L, 2: -L);
+// word kTabTotal holds the staged count.  kTabStride words per tile.
+constexpr uint32_t kTabSrcMask = (1u << 26) - 1;
+constexpr int kTabShiftX = 26, kTabShiftY = 28, kTabShiftZ = 30;
+template <class Stage>
+constexpr int kTabTotal = Stage::kCap;
+constexpr int tab_stride(int cap) { return cap + 64; }
+
+__device__ __forceinline__ uint32_t shift_code(double d)
+{
+    return d > 0.0 ? 1u : (d < 0.0 ? 2u : 0u);
+}
+
+__device__ __forceinline__ double shift_of(uint32_t c, double L)
+{
+    c &= 3u;
+    return c == 1u ? L : (c == 2u ? -L : 0.0);
+}
+
 // Fills the staging tables and stages positions (x, y, z planes or the
-// packed copy).  All TB threads of the workgroup must call it.  Returns the
+// packed copy).  All TB threads of the workgroup must call it, after every
+// reader of a previous tile's staging has passed a barrier.  Returns the
 // total staged count (may exceed cap: then nothing is staged).
 // Source atom of staged slot sl: its staged row (from the chunk table, then
 // forward over rows that end inside the chunk), and the x image shift of the
@@ -131,49 +153,84 @@ __device__ __forceinline__ int slot_source(const TileSpec &s, const Stage &st, i
     return st.row_g0[r][piece] + off - (piece == 0 ? 0 : (piece == 1 ? lw : lw + mn));
 }
 
-template <int TB, bool P4, class Stage>
+template <int TB, bool P4, class Stage, class Mid>
 __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
                           const double *__restrict__ x, const double *__restrict__ y,
                           const double *__restrict__ z, const double *__restrict__ pos4,
-                          Stage &st, int cap)
+                          Stage &st, int cap, uint32_t *tab, Mid &&mid)
 {
     const int tid = threadIdx.x;
     const int nk = s.b - s.a + 4;       // cell starts a-1 .. b+2 per staged row
     const int nq = s.nrows * nk;
     const int lo = max(s.a - 1, 0), hi = min(s.b + 1, s.nx - 1);
-    __syncthreads();   // readers of the previous tile are done with st
     if (tid == TB - 1) {
         st.x[Stage::kCap] = kPadCoord;
         st.y[Stage::kCap] = kPadCoord;
         st.z[Stage::kCap] = kPadCoord;
     }
     // Phase 1, global loads only: every (row, cell) start, and per row the
-    // bounds of its three pieces (left wrap, main run, right wrap).
-    for (int t = tid; t < nq; t += TB) {
-        const int q = t / nk, k = t % nk;
+    // bounds of its three pieces (left wrap, main run, right wrap).  All of
+    // a thread's loads are issued before any is stored, with mid() in
+    // between, so that a caller's own loads share their latency; mid()
+    // returning false (uniformly) abandons the staging: the result is -1.
+    constexpr int kP1 = (kMaxStagedRows * Stage::kRowStage + TB - 1) / TB;
+    auto row_of = [&](int q, double &dy, double &dz) {
         const int zr = q / (s.hy + 2), yr = q % (s.hy + 2);
         int az = s.z0 - 1 + zr, ay = s.y0 - 1 + yr;
-        double dz = 0.0, dy = 0.0;
+        dz = 0.0;
+        dy = 0.0;
         // a row reached across a face holds atoms one box length away
         if (az < 0) { az += s.nz; dz = -s.L[2]; } else if (az >= s.nz) { az -= s.nz; dz = s.L[2]; }
         if (ay < 0) { ay += s.ny; dy = -s.L[1]; } else if (ay >= s.ny) { ay -= s.ny; dy = s.L[1]; }
-        const int rb = s.coff + (az * s.ny + ay) * s.nx;
-        const int xu = s.a - 1 + k;
-        st.cslot[q][k] = (xu >= 0 && xu < s.nx) ? cs[rb + xu] : 0;
-        if (k == 0) {
-            const int c_last = cs[rb + s.nx - 1], c_end = cs[rb + s.nx];
-            const int c_first = cs[rb], c_second = cs[rb + 1];
-            const int m0 = cs[rb + lo], m1 = cs[rb + hi + 1];
-            st.row_rb[q] = rb;
-            st.row_lo[q] = lo;
-            st.row_lw[q] = s.a - 1 < 0 ? c_end - c_last : 0;
-            st.row_main[q] = m1 - m0;
-            st.row_rw[q] = s.b + 1 >= s.nx ? c_second - c_first : 0;
-            st.row_g0[q][0] = c_last;
-            st.row_g0[q][1] = m0;
-            st.row_g0[q][2] = c_first;
-            st.row_dy[q] = dy;
-            st.row_dz[q] = dz;
+        return s.coff + (az * s.ny + ay) * s.nx;
+    };
+    int cv[kP1], rv[kP1][6];
+#pragma unroll
+    for (int j = 0; j < kP1; ++j) {
+        const int t = tid + j * TB;
+        cv[j] = 0;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) rv[j][r] = 0;
+        if (t < nq) {
+            const int q = t / nk, k = t % nk;
+            double dy, dz;
+            const int rb = row_of(q, dy, dz);
+            const int xu = s.a - 1 + k;
+            if (xu >= 0 && xu < s.nx) cv[j] = cs[rb + xu];
+            if (k == 0) {
+                rv[j][0] = cs[rb + s.nx - 1];
+                rv[j][1] = cs[rb + s.nx];
+                rv[j][2] = cs[rb];
+                rv[j][3] = cs[rb + 1];
+                rv[j][4] = cs[rb + lo];
+                rv[j][5] = cs[rb + hi + 1];
+            }
+        }
+    }
+    if (!mid()) return -1;
+#pragma unroll
+    for (int j = 0; j < kP1; ++j) {
+        const int t = tid + j * TB;
+        if (t < nq) {
+            const int q = t / nk, k = t % nk;
+            st.cslot[q][k] = cv[j];
+            if (k == 0) {
+                double dy, dz;
+                const int rb = row_of(q, dy, dz);
+                const int c_last = rv[j][0], c_end = rv[j][1];
+                const int c_first = rv[j][2], c_second = rv[j][3];
+                const int m0 = rv[j][4], m1 = rv[j][5];
+                st.row_rb[q] = rb;
+                st.row_lo[q] = lo;
+                st.row_lw[q] = s.a - 1 < 0 ? c_end - c_last : 0;
+                st.row_main[q] = m1 - m0;
+                st.row_rw[q] = s.b + 1 >= s.nx ? c_second - c_first : 0;
+                st.row_g0[q][0] = c_last;
+                st.row_g0[q][1] = m0;
+                st.row_g0[q][2] = c_first;
+                st.row_dy[q] = dy;
+                st.row_dz[q] = dz;
+            }
         }
     }
     __syncthreads();
@@ -207,6 +264,7 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
     }
     __syncthreads();
     const int total = st.row_slot[s.nrows];
+    if (tab && tid == 0) tab[kTabTotal<Stage>] = uint32_t(total);
     if (total > cap) return total;
     if (total > 0) {
         // Slots tid, tid + TB, ...: first resolve every slot's source atom and
@@ -239,14 +297,85 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
         for (int k = 0; k < kPer; ++k) {
             const int sl = tid + k * TB;
             if (sl < total) {
+                const double dy = st.row_dy[rowof[k]], dz = st.row_dz[rowof[k]];
                 st.x[sl] = px[k] + sxk[k];
-                st.y[sl] = py[k] + st.row_dy[rowof[k]];
-                st.z[sl] = pz[k] + st.row_dz[rowof[k]];
+                st.y[sl] = py[k] + dy;
+                st.z[sl] = pz[k] + dz;
+                if (tab)
+                    tab[sl] = uint32_t(src[k]) | shift_code(sxk[k]) << kTabShiftX |
+                              shift_code(dy) << kTabShiftY | shift_code(dz) << kTabShiftZ;
             }
         }
     }
     __syncthreads();
     return total;
+}
+
+// Stages a tile from the table its list build wrote (see kTabTotal): the
+// staged count, then every slot's source atom and image shift, gathered as
+// stage_tile does -- one round trip for the table, one for the positions,
+// no cell-start reads and no per-slot source search.  mid() runs while the
+// table loads are in flight (returning false abandons the staging: -1).
+// Source indices are clamped below n_atoms, so a table that no build has
+// written gathers garbage but stays in bounds.
+template <int TB, bool P4, class Stage, class Mid>
+__device__ int stage_from_table(const TileSpec &s, const uint32_t *__restrict__ tab, int n_atoms,
+                                const double *__restrict__ x, const double *__restrict__ y,
+                                const double *__restrict__ z, const double *__restrict__ pos4,
+                                Stage &st, int cap, Mid &&mid)
+{
+    constexpr int kPer = (Stage::kCap + TB - 1) / TB;
+    const int tid = threadIdx.x;
+    if (tid == TB - 1) {
+        st.x[Stage::kCap] = kPadCoord;
+        st.y[Stage::kCap] = kPadCoord;
+        st.z[Stage::kCap] = kPadCoord;
+    }
+    const int total = int(tab[kTabTotal<Stage>]);
+    const int nload = min(total, Stage::kCap);
+    uint32_t code[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int sl = tid + k * TB;
+        code[k] = sl < nload ? tab[sl] : 0u;
+    }
+    if (!mid()) return -1;
+    if (total > cap) return total;
+    double px[kPer], py[kPer], pz[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int src = min(int(code[k] & kTabSrcMask), n_atoms - 1);
+        if (P4) {
+            const double4 v = reinterpret_cast<const double4 *>(pos4)[src];
+            px[k] = v.x;
+            py[k] = v.y;
+            pz[k] = v.z;
+        } else {
+            px[k] = x[src];
+            py[k] = y[src];
+            pz[k] = z[src];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int sl = tid + k * TB;
+        if (sl < total) {
+            st.x[sl] = px[k] + shift_of(code[k] >> kTabShiftX, s.L[0]);
+            st.y[sl] = py[k] + shift_of(code[k] >> kTabShiftY, s.L[1]);
+            st.z[sl] = pz[k] + shift_of(code[k] >> kTabShiftZ, s.L[2]);
+        }
+    }
+    __syncthreads();
+    return total;
+}
+
+template <int TB, bool P4, class Stage>
+__device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
+                          const double *__restrict__ x, const double *__restrict__ y,
+                          const double *__restrict__ z, const double *__restrict__ pos4,
+                          Stage &st, int cap)
+{
+    return stage_tile<TB, P4>(s, cs, x, y, z, pos4, st, cap, nullptr, [] { return true; });
 }
 
 // Number of home atoms of the tile, from the cell starts of its home rows
@@ -272,19 +401,23 @@ struct HomeRows {
 
 __device__ __forceinline__ HomeRows home_rows(const TileSpec &s, const int32_t *__restrict__ cs)
 {
+    // every row's two loads are issued at once (rows past the tile's last
+    // re-read it and count zero), so they cost one round trip
     HomeRows hr;
     hr.rows = s.hy * s.hz;
     hr.total = 0;
+    int e[kMaxHomeRows];
 #pragma unroll
     for (int h = 0; h < kMaxHomeRows; ++h) {
-        hr.g0[h] = 0;
-        hr.n[h] = 0;
-        if (h < hr.rows) {
-            const int rb = s.coff + ((s.z0 + h / s.hy) * s.ny + (s.y0 + h % s.hy)) * s.nx;
-            hr.g0[h] = cs[rb + s.a];
-            hr.n[h] = cs[rb + s.b + 1] - hr.g0[h];
-            hr.total += hr.n[h];
-        }
+        const int hh = min(h, hr.rows - 1);
+        const int rb = s.coff + ((s.z0 + hh / s.hy) * s.ny + (s.y0 + hh % s.hy)) * s.nx;
+        hr.g0[h] = cs[rb + s.a];
+        e[h] = cs[rb + s.b + 1];
+    }
+#pragma unroll
+    for (int h = 0; h < kMaxHomeRows; ++h) {
+        hr.n[h] = h < hr.rows ? e[h] - hr.g0[h] : 0;
+        hr.total += hr.n[h];
     }
     return hr;
 }
@@ -320,6 +453,8 @@ struct TileArgs {
     // forces
     const double *eps, *sig;
     int32_t shift;
+    uint32_t *tile_src;   // staging tables, tab_stride(CAP) words per tile
+    int32_t n_atoms;
     double rc;
     double *fx, *fy, *fz;
     int32_t accumulate;
@@ -373,6 +508,8 @@ inline TileArgs tile_args(const md_batch *b, const md_atoms *atoms, const md_nli
     a.R = b->R;
     a.type = atoms->type;
     a.tile_types = nl->tile_types;
+    a.tile_src = nl->tile_src;
+    a.n_atoms = b->N;
     return a;
 }
 

@@ -70,7 +70,9 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
         const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
         if (a.gate != nullptr && a.gate[s.rep] == 0u) continue;
         if (tile_home_atoms(s, a.cell_start) == 0) continue;
-        const int total = stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP);
+        const int total =
+            stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP,
+                               a.tile_src + size_t(t) * tab_stride(CAP), [] { return true; });
         if (total > CAP) {
             if (threadIdx.x == 0) {
                 if (a.status) atomicOr(a.status, MD_F_TILE_OVERFLOW);

@@ -225,6 +225,10 @@ class MDSystem:
         self.tile_cells, self.n_tiles = m, n
         self.tile_rep = torch.as_tensor(rep).to(self.dev)
         self.tile_off = torch.as_tensor(off).to(self.dev)
+        # per-tile staging tables (capacity + 64 words each), written by the build
+        self.tile_src_cap = self.lib.md_tile_capacity()
+        self.tile_src = torch.zeros(n * (self.tile_src_cap + 64), dtype=torch.int32,
+                                    device=self.dev)
 
     def _alloc_list(self, max_nbr):
         self.max_nbr = (int(max_nbr) + 15) // 16 * 16   # tile lists pad to 16 entries
@@ -240,7 +244,8 @@ class MDSystem:
             self.tile_py, self.tile_pz, self.ntypes if tiled and self.ntypes > 1 else 0,
             self.tile_rep.data_ptr() if tiled else None,
             self.tile_off.data_ptr() if tiled else None,
-            self.tile_need.data_ptr(), self.cell_start.data_ptr() if tiled else None)
+            self.tile_need.data_ptr(), self.cell_start.data_ptr() if tiled else None,
+            self.tile_src_cap if tiled else 0, 0, self.tile_src.data_ptr() if tiled else None)
 
     @property
     def stream(self):

@@ -27,12 +27,12 @@ def test_library_exports_every_declared_symbol():
     lib = abi.load()
     for name in _declared():
         assert hasattr(lib, name), name
-    assert lib.md_abi_version() == 1
+    assert lib.md_abi_version() == abi.MD_ABI_VERSION
 
 
 def test_header_constants_match_binding():
     src = open(os.path.join(ROOT, "include", "md.h")).read()
-    for name in ("MD_OK", "MD_EINVAL", "MD_EBOX", "MD_ENOWS", "MD_EUNSUPPORTED", "MD_EHIP",
+    for name in ("MD_ABI_VERSION", "MD_OK", "MD_EINVAL", "MD_EBOX", "MD_ENOWS", "MD_EUNSUPPORTED", "MD_EHIP",
                  "MD_ERANGE", "MD_HALF", "MD_FULL", "MD_FP64", "MD_FP32_MIXED",
                  "MD_UNIT_ATOMS", "MD_IDX_BITS", "MD_MAX_TYPES", "MD_TILE_FULL",
                  "MD_TILE_SLOTS", "MD_TILE_MAX_CELLS", "MD_TILE_MAX_ROWS", "MD_TILE_MAX_TYPES",
@@ -173,3 +173,20 @@ def test_kernel_timing_arguments_and_empty_read():
     assert lib.md_kernel_timing_read(ctypes.byref(ms), ctypes.byref(n)) == abi.MD_OK
     assert n.value == 0 and ms.value == 0.0
     assert lib.md_kernel_timing_read(None, ctypes.byref(n)) == abi.MD_EINVAL
+
+
+def test_tile_list_needs_a_staging_table_of_the_current_capacity():
+    # rejected on the host before anything is launched (fake device pointers)
+    lib = abi.load()
+    P = ctypes.pointer
+    ok = abi.MdBatch(1, 1000, 27, 4, 8, 8, 8, 8, 8, 8)
+    full = abi.MdAtoms(*([8] * 17))
+    cap = lib.md_tile_capacity()
+
+    def nl(src, src_cap):
+        return abi.MdNlist(abi.MD_TILE_FULL, 64, 1024, 1, 16, 16, 1, 1, 1, 0, 16, 16, None, 16,
+                           src_cap, 0, src)
+
+    for bad in (nl(None, cap), nl(16, cap + 1), nl(16, 0)):
+        assert lib.md_verlet_build(P(ok), P(full), 16, 2.5, 0.3, P(bad), None, None, None,
+                                   None) == abi.MD_EINVAL
