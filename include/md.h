@@ -314,12 +314,18 @@ int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
  * lists of one atom type (MD_EUNSUPPORTED otherwise); a step that adds bond
  * or thermostat forces uses md_lj_forces and md_vv_step.  The same
  * arithmetic as those two calls in sequence, so trajectories are bitwise
- * equal; the kinetic energy is summed in another order.  New positions are
- * staged in the workspace and copied back (with the packed copy, if set). */
+ * equal; the kinetic energy is summed in another order.  New positions:
+ * with x_next, y_next, z_next NULL they are staged in the workspace and
+ * copied back into atoms->x, y, z (and the packed copy, if set); with all
+ * three given ([N] device each, not overlapping atoms->x, y, z; atoms->pos4
+ * must be NULL) they are written there and atoms->x, y, z stay as they were,
+ * so a caller that alternates two position buffers skips the copy.  Other
+ * combinations return MD_EINVAL. */
 int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlist *nl, const md_lj *p,
                     int32_t prec, double dt, const double *inv_mass, int32_t ntypes,
                     double skin, uint32_t *gate, double *ke, double *energy, double *virial,
-                    void *ws, size_t ws_bytes, uint32_t *status, void *stream);
+                    double *x_next, double *y_next, double *z_next, void *ws,
+                    size_t ws_bytes, uint32_t *status, void *stream);
 
 /* Velocity-Verlet update (Sec. 2.1, Fig. 1: Integrate1 / Integrate2).
  *  phase 1: v += dt/2 F/m; x += dt v; gate[r] = 1 if some atom of replica r

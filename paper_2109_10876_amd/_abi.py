@@ -147,8 +147,8 @@ def load():
                                _vp, ctypes.c_size_t, _vp, _vp]
     lib.md_lj_forces_vv.restype = ctypes.c_int
     lib.md_lj_forces_vv.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32, _dbl,
-                                    _vp, _i32, _dbl, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
-                                    _vp, _vp]
+                                    _vp, _i32, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    ctypes.c_size_t, _vp, _vp]
     lib.md_lj_forces_vjp.restype = ctypes.c_int
     lib.md_lj_forces_vjp.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32,
                                      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,

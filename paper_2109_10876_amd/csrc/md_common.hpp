@@ -254,8 +254,9 @@ int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_sta
                hipStream_t s);
 // Velocity-Verlet phase 3 (Integrate2 of this step, then Integrate1 of the
 // next, as in md_vv_step) applied by the tile force kernel to each home
-// atom right after its force: next positions go to xn/yn/zn, copied back
-// once every workgroup has read the current ones.
+// atom right after its force: next positions go to xn/yn/zn (the caller's
+// second buffer, or workspace copied back once every workgroup has read the
+// current ones).
 struct VVFuse {
     double *vx, *vy, *vz;
     const double *xb, *yb, *zb;
@@ -265,6 +266,7 @@ struct VVFuse {
     double *xn, *yn, *zn;
     double *ke;
     uint32_t *gate;
+    bool copy_back;   // xn/yn/zn are workspace: copy them into atoms->x/y/z
 };
 
 int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const md_lj *p,

@@ -311,8 +311,9 @@ extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_n
 extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlist *nl,
                                const md_lj *p, int32_t prec, double dt, const double *inv_mass,
                                int32_t ntypes, double skin, uint32_t *gate, double *ke,
-                               double *energy, double *virial, void *ws, size_t ws_bytes,
-                               uint32_t *status, void *stream)
+                               double *energy, double *virial, double *x_next, double *y_next,
+                               double *z_next, void *ws, size_t ws_bytes, uint32_t *status,
+                               void *stream)
 {
     using namespace md;
     int e = check_batch(b);
@@ -331,10 +332,22 @@ extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlis
     const WsLayout l = ws_layout(b);
     if (ws_bytes < l.total) return MD_ENOWS;
     if (!tile_list_ok(b, nl) || !nl->cell_start || nl->tile_types > 1) return MD_EINVAL;
-    double *xn = ws_at<double>(ws, l.xnext);
+    // next positions: the caller's buffers (all three, not overlapping the
+    // current ones, and no packed copy to keep), or workspace copied back
+    const bool given = x_next || y_next || z_next;
+    if (given) {
+        if (!x_next || !y_next || !z_next || atoms->pos4) return MD_EINVAL;
+        const double *cur[3] = {atoms->x, atoms->y, atoms->z};
+        const double *nxt[3] = {x_next, y_next, z_next};
+        for (const double *c : cur)
+            for (const double *n : nxt)
+                if (n < c + b->N && c < n + b->N) return MD_EINVAL;
+    }
+    double *xw = ws_at<double>(ws, l.xnext);
     const VVFuse f{atoms->vx, atoms->vy, atoms->vz, atoms->xb, atoms->yb, atoms->zb, inv_mass,
-                   ntypes, 0.5 * dt, dt, 0.25 * skin * skin, xn, xn + b->N, xn + 2 * size_t(b->N),
-                   ke, gate};
+                   ntypes, 0.5 * dt, dt, 0.25 * skin * skin,
+                   given ? x_next : xw, given ? y_next : xw + b->N,
+                   given ? z_next : xw + 2 * size_t(b->N), ke, gate, !given};
     return tile_forces(b, atoms, nl, p, prec, 0, nl->cell_start, energy, virial,
                        ws_at<double>(ws, l.tile_partial), md_tune_get(MD_TUNE_PAIR_BATCH), &f,
                        status, as_stream(stream));

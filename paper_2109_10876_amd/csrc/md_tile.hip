@@ -318,7 +318,7 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
     if (energy || virial || ke || gate)
         hipLaunchKernelGGL(k_tile_finalize, dim3(b->R), dim3(kFin), 0, s, nl->tile_off, tpart,
                            energy, virial, ke, gate, fuse ? vvf->lim2 : 0.0);
-    if (fuse)
+    if (fuse && vvf->copy_back)
         hipLaunchKernelGGL(k_copy_next, dim3((b->N + kUnit - 1) / kUnit), dim3(kUnit), 0, s, b->N,
                            vvf->xn, vvf->yn, vvf->zn, atoms->x, atoms->y, atoms->z, atoms->pos4);
     return launch_status();

@@ -99,7 +99,11 @@ class MDSystem:
         vel = np.asarray(vel, np.float64).reshape(self.N, 3)
         types = np.zeros(self.N, np.int32) if types is None else np.asarray(types, np.int32)
         z64 = lambda: torch.zeros(self.N, dtype=torch.float64, device=d)
-        self.x, self.y, self.z = (f64(pos[:, k]) for k in range(3))
+        # positions: one (x, y, z) buffer, or two that the fused force +
+        # integrator call alternates between (it writes the next positions
+        # into the other one); self._par names the current one
+        self._pos = [tuple(f64(pos[:, k]) for k in range(3))]
+        self._par = 0
         self.vx, self.vy, self.vz = (f64(vel[:, k]) for k in range(3))
         self.fx, self.fy, self.fz = z64(), z64(), z64()
         self.xb, self.yb, self.zb = self.x.clone(), self.y.clone(), self.z.clone()
@@ -114,7 +118,7 @@ class MDSystem:
             pos4 = (mode != "tile" or
                     self.lib.md_tune_get(abi.MD_TUNE_TILE_STAGE_PACKED) == 1)
         self.pos4 = torch.zeros(4 * self.N, dtype=torch.float64, device=d) if pos4 else None
-        self.atoms = self._atoms_struct(self)
+        self._atoms = [self._atoms_struct(xyz) for xyz in self._pos]
         # re-sort scratch planes
         self.s_x, self.s_y, self.s_z, self.s_vx, self.s_vy, self.s_vz = (z64() for _ in range(6))
         self.s_type = torch.zeros(self.N, dtype=torch.int32, device=d)
@@ -202,10 +206,29 @@ class MDSystem:
         # step (md_lj_forces_vv); bonds or a thermostat need the split calls
         self.fuse = bool(fuse) and self.mode == abi.MD_TILE_FULL and self.bonds is None \
             and self.langevin_cfg is None and self.ntypes == 1
+        if self.fuse and self.pos4 is None:
+            self._pos.append((z64(), z64(), z64()))
+            self._atoms.append(self._atoms_struct(self._pos[1]))
 
-    @staticmethod
-    def _atoms_struct(s):
-        return abi.MdAtoms(s.x.data_ptr(), s.y.data_ptr(), s.z.data_ptr(), s.vx.data_ptr(),
+    @property
+    def x(self):
+        return self._pos[self._par][0]
+
+    @property
+    def y(self):
+        return self._pos[self._par][1]
+
+    @property
+    def z(self):
+        return self._pos[self._par][2]
+
+    @property
+    def atoms(self):
+        return self._atoms[self._par]
+
+    def _atoms_struct(s, xyz):
+        x, y, z = xyz
+        return abi.MdAtoms(x.data_ptr(), y.data_ptr(), z.data_ptr(), s.vx.data_ptr(),
                            s.vy.data_ptr(), s.vz.data_ptr(), s.fx.data_ptr(), s.fy.data_ptr(),
                            s.fz.data_ptr(), s.xb.data_ptr(), s.yb.data_ptr(), s.zb.data_ptr(),
                            s.type.data_ptr(), s.id.data_ptr(), s.img.data_ptr(),
@@ -273,11 +296,16 @@ class MDSystem:
     def forces_vv(self):
         """Forces at the current positions, then velocity-Verlet phase 3, in
         one call (pure pair forces on tile lists)."""
+        two = len(self._pos) == 2
+        nxt = self._pos[self._par ^ 1] if two else (None, None, None)
         check("md_lj_forces_vv", self.lib.md_lj_forces_vv(
             ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.nlist),
             ctypes.byref(self.lj), self.prec, self.dt, _ptr(self.inv_mass), self.ntypes,
             self.skin, _ptr(self.gate), _ptr(self.ke), _ptr(self.energy), _ptr(self.virial),
+            _ptr(nxt[0]), _ptr(nxt[1]), _ptr(nxt[2]),
             _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
+        if two:
+            self._par ^= 1   # the next positions are now the current ones
 
     def vv(self, phase):
         check("md_vv_step", self.lib.md_vv_step(
@@ -397,14 +425,19 @@ class MDSystem:
     def capture(self, k):
         """Capture k repeated steps (Integrate2+Integrate1, gated re-sort and
         list build, forces) as one HIP graph; replays launch on the current
-        stream."""
+        stream.  With alternating position buffers a graph holds an even
+        number of steps (k + 1 for odd k), so a replay ends on the buffer it
+        started from."""
+        kk = k + 1 if len(self._pos) == 2 and k % 2 else k
+        par0 = self._par
         torch.cuda.synchronize(self.dev)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            for _ in range(k):
+            for _ in range(kk):
                 self._body()
         torch.cuda.synchronize(self.dev)
-        self._graph = (k, g)
+        assert self._par == par0
+        self._graph = (k, g, kk, par0)
         return g
 
     def run_graphed(self, steps, k=50):
@@ -412,9 +445,12 @@ class MDSystem:
         captured graph of k steps.  Status flags are not inspected here."""
         if self._graph is None or self._graph[0] != k:
             self.capture(k)
-        kk, g = self._graph
+        _, g, kk, par0 = self._graph
         self._head()
         rest = steps - 1
+        if rest > 0 and self._par != par0:
+            self._body()   # onto the buffer the graph starts from
+            rest -= 1
         for _ in range(rest // kk):
             g.replay()
         for _ in range(rest % kk):

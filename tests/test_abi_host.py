@@ -190,3 +190,28 @@ def test_tile_list_needs_a_staging_table_of_the_current_capacity():
     for bad in (nl(None, cap), nl(16, cap + 1), nl(16, 0)):
         assert lib.md_verlet_build(P(ok), P(full), 16, 2.5, 0.3, P(bad), None, None, None,
                                    None) == abi.MD_EINVAL
+
+
+def test_fused_step_next_position_buffers_are_checked():
+    # all three or none, no overlap with the current planes, no packed copy;
+    # rejected on the host before anything is launched (fake device pointers)
+    lib = abi.load()
+    P = ctypes.pointer
+    ok = abi.MdBatch(1, 1000, 27, 4, 8, 8, 8, 8, 8, 8)
+    cap = lib.md_tile_capacity()
+    nl = abi.MdNlist(abi.MD_TILE_FULL, 64, 1024, 1, 16, 16, 1, 1, 1, 0, 16, 16, None, 16,
+                     cap, 0, 16)
+    lj1 = abi.MdLj(1, 1, 2.5, 8, 8)
+    X, Y, Z = 1 << 20, 2 << 20, 3 << 20
+    atoms = abi.MdAtoms(X, Y, Z, *([8] * 13), None)
+    packed = abi.MdAtoms(X, Y, Z, *([8] * 13), 8)
+    far = 16 << 20
+
+    def call(a, xn, yn, zn):
+        return lib.md_lj_forces_vv(P(ok), P(a), P(nl), P(lj1), 0, 0.005, 8, 1, 0.3, 8, None,
+                                   None, None, xn, yn, zn, 8, 1 << 30, None, None)
+
+    assert call(atoms, far, None, None) == abi.MD_EINVAL             # not all three
+    assert call(atoms, X + 8 * 500, far, far + (1 << 20)) == abi.MD_EINVAL   # overlaps x
+    assert call(atoms, far, far + (1 << 20), Z) == abi.MD_EINVAL     # overlaps z
+    assert call(packed, far, far + (1 << 20), far + (2 << 20)) == abi.MD_EINVAL  # pos4 set

@@ -634,17 +634,23 @@ def test_fused_and_split_steps_are_bitwise_equal(prec):
     a = _system(cfg, mode="tile", prec=prec, fuse=False)
     b = _system(cfg, mode="tile", prec=prec)
     c = _system(cfg, mode="tile", prec=prec)
-    assert not a.fuse and b.fuse
-    for x in (a, b, c):
+    # with the packed copy kept, the fused call copies the next positions
+    # back instead of alternating two buffers
+    d = _system(cfg, mode="tile", prec=prec, pos4=True)
+    assert not a.fuse and b.fuse and d.fuse
+    assert len(b._pos) == 2 and len(d._pos) == 1
+    for x in (a, b, c, d):
         x.setup()
     a.run(40, check_every=0)
     b.run(40, check_every=0)
-    c.run_graphed(40, k=6)
-    for x in (a, b, c):
+    c.run_graphed(40, k=5)
+    d.run(40, check_every=0)
+    for x in (a, b, c, d):
         assert x.ensure_list() == 0
     assert np.array_equal(a.positions(), b.positions())
     assert np.array_equal(a.velocities(), b.velocities())
     assert np.array_equal(b.positions(), c.positions())
+    assert np.array_equal(b.positions(), d.positions())
     assert np.array_equal(a.forces_np(), b.forces_np())
     assert float(b.ke[0]) == pytest.approx(float(a.ke[0]), rel=1e-12)
 
