@@ -23,7 +23,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
 {
     constexpr int TB = SH::TB, CAP = SH::CAP;
     __shared__ TileStage<CAP, SH::MAXC> st;
-    __shared__ double red[TB / kWave];
+    __shared__ double red[4][TB / kWave];
     __shared__ PolyConst ptab[TYPED ? kTileMaxTypes * kTileMaxTypes : 1];
     const int t = xcd_chunked(blockIdx.x, gridDim.x, kTileXcdChunk);
     const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
@@ -171,19 +171,35 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
             }
         }
     }
-    const double es = block_sum_n<TB>(e_acc, red);
-    const double ws = block_sum_n<TB>(w_acc, red);
-    double ks = 0.0, dm = 0.0;
+    // the tile's partials: wave totals, one barrier, then the waves' totals
+    // in wave order (as block_sum_n sums them)
+    e_acc = wave_sum(e_acc);
+    w_acc = wave_sum(w_acc);
     if (FUSE) {
-        ks = block_sum_n<TB>(ke_acc, red);
-        dm = block_max_n<TB>(d2_max, red);
+        ke_acc = wave_sum(ke_acc);
+        d2_max = wave_max(d2_max);
     }
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) {
+        red[0][wid] = e_acc;
+        red[1][wid] = w_acc;
+        red[2][wid] = ke_acc;
+        red[3][wid] = d2_max;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        double es = 0.0, ws = 0.0, ks = 0.0, dm = 0.0;
+        for (int q = 0; q < TB / kWave; ++q) {
+            es += red[0][q];
+            ws += red[1][q];
+            ks += red[2][q];
+            dm = fmax(dm, red[3][q]);
+        }
         double *tp = a.tpart + size_t(t) * kTilePartials;
         tp[0] = es;
         tp[1] = ws;
-        tp[2] = ks;
-        tp[3] = dm;
+        tp[2] = FUSE ? ks : 0.0;
+        tp[3] = FUSE ? dm : 0.0;
     }
 }
 
@@ -210,7 +226,8 @@ __global__ __launch_bounds__(kFin) void k_tile_finalize(const int32_t *tile_off,
                                                         double *virial, double *ke,
                                                         uint32_t *gate, double lim2)
 {
-    __shared__ double red[kFin / kWave];
+    constexpr int kW = kFin / kWave;
+    __shared__ double red[4][kW];
     const int r = blockIdx.x;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, m = 0.0;
 #pragma unroll 4
@@ -221,15 +238,32 @@ __global__ __launch_bounds__(kFin) void k_tile_finalize(const int32_t *tile_off,
         if (ke) s2 += tp[2];
         if (gate) m = fmax(m, tp[3]);
     }
-    s0 = block_sum_n<kFin>(s0, red);
-    s1 = block_sum_n<kFin>(s1, red);
-    if (ke) s2 = block_sum_n<kFin>(s2, red);
-    if (gate) m = block_max_n<kFin>(m, red);
+    // the four reductions share one barrier; wave totals are then summed in
+    // wave order, as by block_sum_n
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (ke) s2 = wave_sum(s2);
+    if (gate) m = wave_max(m);
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) {
+        red[0][wid] = s0;
+        red[1][wid] = s1;
+        red[2][wid] = s2;
+        red[3][wid] = m;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        if (energy) energy[r] = s0;
-        if (virial) virial[r] = s1;
-        if (ke) ke[r] = s2;
-        if (gate) gate[r] = m > lim2 ? 1u : 0u;
+        double e = 0.0, w = 0.0, k = 0.0, d = 0.0;
+        for (int q = 0; q < kW; ++q) {
+            e += red[0][q];
+            w += red[1][q];
+            k += red[2][q];
+            d = fmax(d, red[3][q]);
+        }
+        if (energy) energy[r] = e;
+        if (virial) virial[r] = w;
+        if (ke) ke[r] = k;
+        if (gate) gate[r] = d > lim2 ? 1u : 0u;
     }
 }
 
