@@ -50,10 +50,10 @@ FLOPS_PER_ATOM_VV = 36
 # in); each entry: source hash of the kernel's files and calibrated bytes per
 # launch for the FP32-mixed and FP64 paths.
 COUNTED_TRAFFIC = {
-    "tile_fused": {"src_sha256_16": "e7799dab388d2719",
-                   "bytes_per_launch": {"mixed": 393235558, "fp64": 392885248}},
-    "tile": {"src_sha256_16": "e7799dab388d2719",
-             "bytes_per_launch": {"mixed": 289807462, "fp64": 289978163}},
+    "tile_fused": {"src_sha256_16": "c1fd1a64c5ff9f3d",
+                   "bytes_per_launch": {"mixed": 422676787, "fp64": 423592346}},
+    "tile": {"src_sha256_16": "c1fd1a64c5ff9f3d",
+             "bytes_per_launch": {"mixed": 319221965, "fp64": 320458240}},
 }
 
 FORCE_KERNEL_SOURCES = {
