@@ -155,14 +155,16 @@ def time_path(cfg, prec, steps, warmup, tuned, graph_k=50):
 def time_workload(name, steps, warmup=10):
     """Throughput of one of the other workloads (FP32-mixed, graphed steps):
     the polymer melt (purely repulsive LJ + FENE + Langevin), the LJ slab
-    (Langevin) and the batch of uneven replicas (NVE), plus, for the batch,
+    and the LJ sphere in vacuum (Langevin) and the batch of uneven replicas
+    (NVE), plus, for the batch,
     one force + adjoint evaluation of a force-matching loss."""
     import torch
     import md_inputs
     from paper_2109_10876_amd import MDSystem
     from paper_2109_10876_amd import autotune
     cfg = md_inputs.CONFIGS[name]()
-    lang = {"kg_melt": (0.5, 1.0, 3), "lj_slab": (1.0, 0.85, 4)}.get(name)
+    lang = {"kg_melt": (0.5, 1.0, 3), "lj_slab": (1.0, 0.85, 4),
+            "lj_sphere": (1.0, 0.1, 6)}.get(name)
     ntypes = int(np.atleast_2d(np.asarray(cfg.eps)).shape[0])
 
     def make(mode="full", tile_cells=None, tile_rows=(1, 1)):
@@ -370,7 +372,8 @@ def main():
     }
     if not args.no_other:
         other = {}
-        for name, steps in (("kg_melt", 300), ("lj_slab", 300), ("replicas", 200)):
+        for name, steps in (("kg_melt", 300), ("lj_slab", 300), ("lj_sphere", 100),
+                            ("replicas", 200)):
             log(f"[{name}] timing {steps} steps")
             try:
                 other[name] = time_workload(name, steps)

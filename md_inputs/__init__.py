@@ -24,7 +24,7 @@ import numpy as np
 
 __all__ = [
     "Config", "fcc_lattice", "maxwell_velocities", "jitter", "lj_fluid",
-    "random_walk_chains", "lattice_chains", "lj_slab", "replica_batch", "CONFIGS",
+    "random_walk_chains", "lattice_chains", "lj_slab", "lj_sphere", "replica_batch", "CONFIGS",
 ]
 
 # Basis of the FCC conventional cubic cell, in units of the lattice constant.
@@ -201,6 +201,28 @@ def lj_slab(m=50, rho=0.8, temperature=0.85, seed=4, dt=0.005, steps=1000):
                   temperature, steps)
 
 
+def lj_sphere(n_target=2_580_000, box=271.0, rho=0.8442, temperature=0.1, seed=6, dt=0.005,
+              steps=100):
+    """LJ liquid filling a sphere at the centre of a cubic box, vacuum around
+    it (the paper's spatially inhomogeneous case, Sec. 4.2): FCC sites at
+    density rho within radius R = (3 n_target / (4 pi rho))^(1/3) of the box
+    centre, so N is n_target up to the lattice's discreteness."""
+    R = (3.0 * n_target / (4.0 * math.pi * rho)) ** (1.0 / 3.0)
+    a = (4.0 / rho) ** (1.0 / 3.0)
+    m = int(math.ceil(2.0 * R / a)) + 1
+    sites, _ = fcc_lattice(m, rho)
+    sites = sites - 0.5 * m * a          # lattice centred on the origin
+    keep = np.einsum("ij,ij->i", sites, sites) < R * R
+    pos = np.ascontiguousarray(sites[keep] + 0.5 * box)
+    n = pos.shape[0]
+    vel = maxwell_velocities(n, temperature, 1.0, seed=seed)
+    one = np.ones((1, 1))
+    return Config(f"lj_sphere{n}", pos, vel, np.array([[box, box, box]]),
+                  np.array([n], dtype=np.int64), np.zeros(n, np.int32), 1,
+                  one.copy(), one.copy(), np.ones(1), 2.5, 0.3, dt,
+                  temperature, steps)
+
+
 def replica_batch(nrep=256, nmin=500, nmax=20000, rho=0.8442, temperature=1.0,
                   seed=5, param_seed=None, dt=0.005, steps=100):
     """Independent two-type LJ replicas of uneven sizes.
@@ -250,5 +272,6 @@ CONFIGS = {
     "kg_melt": lambda: lattice_chains((80, 80, 128), 200, seed=3),
     "kg_melt_random_walk": lambda: random_walk_chains(4096, 200, seed=3),
     "lj_slab": lambda: lj_slab(50, seed=4),
+    "lj_sphere": lambda: lj_sphere(seed=6),
     "replicas": lambda: replica_batch(256, seed=5),
 }

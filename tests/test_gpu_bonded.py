@@ -121,3 +121,27 @@ def test_slab_forces_sampled(prec):
                     for i in smp])
     err = np.linalg.norm(f[smp] - ref) / np.linalg.norm(ref)
     assert err < (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec,mode", [("fp64", "tile"), ("mixed", "tile"), ("fp64", "full")])
+def test_sphere_forces_sampled(prec, mode):
+    # LJ liquid sphere in vacuum (the paper's inhomogeneous case, scaled down):
+    # ~1900 atoms at density 0.8442 in a 30 sigma box, most cells and tiles empty
+    print(f"case: sphere {prec} {mode}", flush=True)
+    cfg = md_inputs.lj_sphere(2000, 30.0, seed=9)
+    cfg.pos = md_inputs.jitter(cfg.pos, 0.08, seed=11)
+    s = _system(cfg, prec=prec, mode=mode)
+    s.setup()
+    assert s.ensure_list() == 0
+    f = s.forces_np()
+    rng = np.random.default_rng(3)
+    smp = rng.choice(cfg.n, 64, replace=False)
+    planes = tuple(np.ascontiguousarray(cfg.pos[:, k]) for k in range(3))
+    ref = np.array([oracle.lj_force_one(i, None, cfg.box[0], cfg.rc, planes=planes)[0]
+                    for i in smp])
+    err = np.linalg.norm(f[smp] - ref) / np.linalg.norm(ref)
+    assert err < (1e-12 if prec == "fp64" else 1e-5)
+    # a surface atom has fewer neighbours than one in the bulk
+    cnt = s.count.cpu().numpy()[np.argsort(s.id.cpu().numpy())]
+    r = np.linalg.norm(cfg.pos - 15.0, axis=1)
+    assert cnt[r > r.max() - 1.0].mean() < 0.8 * cnt[r < r.max() - 5.0].mean()

@@ -1,0 +1,32 @@
+"""CPU checks of the synthetic workload generators (shapes, densities and
+geometry of the inputs; no arithmetic of the method)."""
+import math
+
+import numpy as np
+
+import md_inputs
+
+
+def test_sphere_geometry_and_density():
+    # the inhomogeneous sphere (paper Sec. 4.2): FCC sites at rho within R of
+    # the box centre, vacuum elsewhere
+    cfg = md_inputs.lj_sphere(20000, 60.0, seed=3)
+    rho = 0.8442
+    R = (3.0 * 20000 / (4.0 * math.pi * rho)) ** (1.0 / 3.0)
+    r = np.linalg.norm(cfg.pos - 30.0, axis=1)
+    assert abs(cfg.n - 20000) < 0.02 * 20000
+    assert r.max() < R and np.all(cfg.pos > 0.0) and np.all(cfg.pos < 60.0)
+    inner = R - 3.0
+    dens = np.count_nonzero(r < inner) / (4.0 / 3.0 * math.pi * inner ** 3)
+    assert abs(dens - rho) < 0.03 * rho
+    v = cfg.vel
+    assert np.allclose(v.mean(axis=0), 0.0, atol=1e-12)
+    assert abs(np.sum(v * v) / (3 * cfg.n - 3) - 0.1) < 1e-12
+
+
+def test_sphere_workload_size():
+    # the benchmark workload: 2.58 million atoms, 15.4% of a 271 sigma box
+    cfg = md_inputs.CONFIGS["lj_sphere"]()
+    assert cfg.n == 2580188 and cfg.box.tolist() == [[271.0, 271.0, 271.0]]
+    frac = cfg.n / 0.8442 / 271.0 ** 3
+    assert abs(frac - 0.154) < 0.002
