@@ -145,11 +145,53 @@ def time_path(cfg, prec, steps, warmup, tuned, graph_k=50):
     assert n_timed.value == nrep, n_timed.value
     f_ms = f_ms.value
     s.ensure_list()
+    sections = time_sections(s, ms / steps, f_ms)
     s.forces()   # forces at the final positions for the snapshot
     mean_k = float(s.count.double().mean().item())
     npairs = pairs_within_rc(s)
     snap = (s.positions(), s.forces_np())
-    return s, ms, f_ms, mean_k, npairs, snap, bool(s.fuse)
+    return s, ms, f_ms, mean_k, npairs, snap, bool(s.fuse), sections
+
+
+def time_sections(s, step_ms, pair_ms, nsteps=200, nrep=10):
+    """Step time split into the paper's sections (Sec. 4: Pair, Neigh,
+    Resort, Integrate, Other), outside the timed region: the rebuild interval
+    from the gate over nsteps eager steps, the list build and the re-sort
+    timed ungated (every replica rebuilds) and amortised over that interval,
+    the pair kernel from the library's events (fused runs integrate inside
+    it), Other the remainder (finalisers, gated no-op launches, launch gaps)."""
+    import torch
+    rebuilds = 0
+    s._head()
+    for _ in range(nsteps):
+        s._body()
+        rebuilds += int(s.gate.max().item() > 0)
+    s._tail()
+    s.ensure_list()
+    interval = nsteps / max(rebuilds, 1)
+
+    def timed(fn):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(nrep):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / nrep
+
+    sort_ms = timed(lambda: s.sort(gated=False))
+    build_ms = timed(lambda: s.build(gated=False))
+    s.ensure_list()
+    neigh, resort = build_ms / interval, sort_ms / interval
+    other = step_ms - pair_ms - neigh - resort
+    return {"rebuild_interval_steps": interval,
+            "pair_us": pair_ms * 1e3, "integrate_us": 0.0 if s.fuse else None,
+            "neigh_us": neigh * 1e3, "resort_us": resort * 1e3, "other_us": other * 1e3,
+            "per_rebuild_us": {"neigh": build_ms * 1e3, "resort": sort_ms * 1e3},
+            "note": ("integrate runs inside the pair kernel" if s.fuse
+                     else "integrate is part of other")}
 
 
 def time_workload(name, steps, warmup=10):
@@ -299,7 +341,8 @@ def main():
     out, snaps = {}, {}
     for prec in ("mixed", "fp64"):
         log(f"[{prec}] timing {args.steps} steps after {args.warmup} warm-up steps")
-        s, ms, f_ms, mean_k, npairs, snap, fused = time_path(cfg, prec, args.steps, args.warmup, tuned)
+        s, ms, f_ms, mean_k, npairs, snap, fused, sections = time_path(
+            cfg, prec, args.steps, args.warmup, tuned)
         snaps[prec] = snap
         # algorithmic bytes of one pair-kernel launch: per atom the list
         # entries (4 B each, 2 B in tile-local lists), count (4 B), own
@@ -347,6 +390,14 @@ def main():
             "forces_kernel_ms": f_ms,
             "roofline": roof,
         }
+        # Amdahl-style bound in the spirit of the paper's S_max (Sec. 4.1):
+        # the step if the pair kernel ran at the vector peak on its
+        # algorithmic flops, every other section unchanged
+        step_us = ms / args.steps * 1e3
+        pair_min_us = flops_launch / (VALU_PEAK_TFLOPS * 1e12) * 1e6
+        sections["s_max_pair_at_peak"] = step_us / (step_us - sections["pair_us"] + pair_min_us)
+        sections["pair_at_peak_us"] = pair_min_us
+        out[prec]["sections"] = sections
         log(f"[{prec}] {json.dumps(out[prec])}")
         del s
         torch.cuda.empty_cache()
@@ -366,8 +417,10 @@ def main():
         "forces_kernel_ms": m["forces_kernel_ms"],
         "force_err_rel": m["force_err_rel"],
         "roofline": m["roofline"],
+        "sections": m["sections"],
         "fp64": {k: out["fp64"][k] for k in ("atom_steps_per_s", "pair_evals_per_s",
-                                             "ms_per_step", "force_err_rel", "roofline")},
+                                             "ms_per_step", "force_err_rel", "roofline",
+                                             "sections")},
         "cpu_baseline": None,
     }
     if not args.no_other:
