@@ -287,7 +287,9 @@ int md_cell_sort(const md_batch *b, md_atoms *atoms, md_atoms *scratch,
  * If an atom has more than max_nbr entries its count still holds the true
  * number, MD_F_NBR_OVERFLOW is raised and *need (device int32, optional)
  * receives the maximum count; the list is then unusable until rebuilt with
- * max_nbr >= need.  Expects atoms sorted by md_cell_sort. */
+ * max_nbr >= need.  Expects atoms sorted by md_cell_sort.  For MD_TILE_FULL
+ * lists it also writes each tile's staging table (nl->tile_src), which the
+ * force calls read instead of re-deriving the staged sequence. */
 int md_verlet_build(const md_batch *b, const md_atoms *atoms,
                     const int32_t *cell_start, double rc, double skin,
                     md_nlist *nl, int32_t *need, const uint32_t *gate,
