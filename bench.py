@@ -239,28 +239,38 @@ def time_workload(name, steps, warmup=10):
            "atom_steps_per_s": s.N * steps / (ms * 1e-3), "status": st,
            "mean_list_entries": float(s.count.double().mean().item())}
     if name == "replicas":
+        # one force + adjoint evaluation of a force-matching loss, on the
+        # tuned list and on a global-index full list; the faster is reported
+        def force_vjp_ms(sy):
+            gf = [torch.randn(sy.N, dtype=torch.float64, device=sy.dev) for _ in range(3)]
+            gE = torch.randn(sy.R, dtype=torch.float64, device=sy.dev)
+            gx = torch.empty(3 * sy.N, dtype=torch.float64, device=sy.dev)
+            ge = torch.empty(sy.ntypes ** 2, dtype=torch.float64, device=sy.dev)
+            gs = torch.empty(sy.ntypes ** 2, dtype=torch.float64, device=sy.dev)
+            torch.cuda.synchronize()
+            ev0.record()
+            for _ in range(20):
+                sy.forces()
+                sy.vjp(*gf, gE, gx, ge, gs)
+            ev1.record()
+            torch.cuda.synchronize()
+            return ev0.elapsed_time(ev1) / 20
+        per_list = {}
+        if tuned["mode"] != "half":
+            per_list[tuned["mode"]] = force_vjp_ms(s)
         if tuned["mode"] != "full":
-            # the adjoint runs on a global full list
             del s
             torch.cuda.empty_cache()
             autotune.apply({"mode": "full", "batch": 4})
             s = make("full")
             s.setup()
             s.ensure_list()
-        gf = [torch.randn(s.N, dtype=torch.float64, device=s.dev) for _ in range(3)]
-        gE = torch.randn(s.R, dtype=torch.float64, device=s.dev)
-        gx = torch.empty(3 * s.N, dtype=torch.float64, device=s.dev)
-        ge = torch.empty(s.ntypes ** 2, dtype=torch.float64, device=s.dev)
-        gs = torch.empty(s.ntypes ** 2, dtype=torch.float64, device=s.dev)
-        torch.cuda.synchronize()
-        ev0.record()
-        for _ in range(20):
-            s.forces()
-            s.vjp(*gf, gE, gx, ge, gs)
-        ev1.record()
-        torch.cuda.synchronize()
-        t = ev0.elapsed_time(ev1) / 20
+            per_list["full"] = force_vjp_ms(s)
+        best = min(per_list, key=per_list.get)
+        t = per_list[best]
         out["force_plus_vjp_ms"] = t
+        out["force_plus_vjp_list"] = best
+        out["force_plus_vjp_ms_by_list"] = per_list
         out["force_plus_vjp_atoms_per_s"] = s.N / (t * 1e-3)
     del s
     torch.cuda.empty_cache()

@@ -103,9 +103,9 @@ extern "C" {
  * A tile whose staged
  * sequence exceeds md_tile_capacity() (at most MD_TILE_SLOTS) raises
  * MD_F_TILE_OVERFLOW (the list is then unusable: rebuild with smaller
- * tiles).  md_lj_forces takes a tile-local list whose tile_types equals
- * the LJ table's ntypes (0 or 1 for one type), at most MD_TILE_MAX_TYPES
- * (MD_EINVAL / MD_EUNSUPPORTED otherwise); tile-local lists have no adjoint. */
+ * tiles).  md_lj_forces and md_lj_forces_vjp take a tile-local list whose
+ * tile_types equals the LJ table's ntypes (0 or 1 for one type), at most
+ * MD_TILE_MAX_TYPES (MD_EINVAL / MD_EUNSUPPORTED otherwise). */
 
 /* ------------------------------------------------------------------ structs */
 
@@ -167,11 +167,12 @@ typedef struct md_nlist {
                                  sized for; calls whose current capacity differs
                                  return MD_EINVAL                              */
     int32_t  _pad;
-    uint32_t *tile_src;       /* MD_TILE_FULL: [n_tiles * (tile_src_cap + 64)]
-                                 staging table of every tile (each staged slot's
+    uint32_t *tile_src;       /* MD_TILE_FULL: [n_tiles * (tile_src_cap + 128)]
+                                 staging record of every tile (each staged slot's
                                  source atom and image), written by
-                                 md_verlet_build and read by md_lj_forces and
-                                 md_lj_forces_vv; part of the list            */
+                                 md_verlet_build and read by md_lj_forces,
+                                 md_lj_forces_vv and md_lj_forces_vjp (which also
+                                 keeps per-tile sums in it); part of the list  */
 } md_nlist;
 
 /* Lennard-Jones parameters (Eq. lj: U = 4 eps [(sig/r)^12 - (sig/r)^6] for
@@ -349,7 +350,8 @@ int md_vv_step(const md_batch *b, md_atoms *atoms, int32_t phase, double dt,
  * derivatives with respect to the shared parameter of each unordered type
  * pair; both mirrored entries hold it, summed over all replicas).  Pair terms
  * are recomputed from the list, nothing is stored by md_lj_forces.  Requires
- * an MD_FULL list. */
+ * an MD_FULL list or an MD_TILE_FULL list (at most MD_TILE_MAX_TYPES types,
+ * typed as for md_lj_forces; MD_EUNSUPPORTED for MD_HALF). */
 int md_lj_forces_vjp(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
                      const md_lj *p, int32_t prec, const double *gfx,
                      const double *gfy, const double *gfz, const double *gE,

@@ -33,12 +33,13 @@ def _set_state(system, pos, eps, sig):
 
 
 class LJForces(torch.autograd.Function):
-    """(pos [N,3], eps [nt,nt], sig [nt,nt]) -> (F [N,3], E [R]) on a full list."""
+    """(pos [N,3], eps [nt,nt], sig [nt,nt]) -> (F [N,3], E [R]) on a full list
+    (global-index or tile-local)."""
 
     @staticmethod
     def forward(ctx, pos, eps, sig, system):
-        if system.mode != abi.MD_FULL:
-            raise ValueError("LJForces needs a full Verlet list (mode='full')")
+        if system.mode not in (abi.MD_FULL, abi.MD_TILE_FULL):
+            raise ValueError("LJForces needs a full Verlet list (mode='full' or 'tile')")
         pos = pos.detach().to(torch.float64).contiguous()
         eps = eps.detach().to(torch.float64).contiguous()
         sig = sig.detach().to(torch.float64).contiguous()

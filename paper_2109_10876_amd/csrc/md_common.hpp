@@ -274,6 +274,12 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
                 double *virial, double *tpart, int batch, const VVFuse *vvf, uint32_t *status,
                 hipStream_t s);
 
+// Adjoint over tile-local lists (md_tile_vjp.hip); arguments as md_lj_forces_vjp.
+int tile_vjp(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const md_lj *p,
+             int32_t prec, const double *gfx, const double *gfy, const double *gfz,
+             const double *gE, double *gx, double *geps, double *gsig, uint32_t *status,
+             hipStream_t s);
+
 // Events around a pair-force kernel launch while md_kernel_timing_start
 // asks for them (md_timing.hip): begin returns a slot or -1, end takes it.
 int timing_begin(hipStream_t s);

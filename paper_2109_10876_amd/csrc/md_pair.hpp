@@ -129,4 +129,55 @@ __device__ __forceinline__ void lj_pair_masked(const PolyConst &pc, double dx, d
     c.fz = fma(fr, dz, c.fz);
 }
 
+// Adjoint pair terms (derivatives of Eq. lj), per unit eps or eps/sigma:
+// with s2 = sig^2/r^2, s6 = s2^3, s12 = s6^2 and inv = 1/r^2,
+//   fr1 = 24 s6 (2 s6 - 1) inv          (fr = eps fr1, F_i = fr d)
+//   dfr1 = (-672 s12 + 192 s6) inv^2    (fr'/r = eps dfr1)
+//   u1 = 4 (s12 - s6) - shift part      (U = eps u1)
+//   dfs1 = (576 s12 - 144 s6) inv       (dfr/dsig = (eps/sig) dfs1)
+//   dus1 = 48 s12 - 24 s6 - shift part  (dU/dsig = (eps/sig) dus1)
+struct VjpConst {
+    double eps, eos, s2, ush1, dus1;   // eps, eps/sig, sig^2, shift parts at rc
+};
+
+__device__ __forceinline__ VjpConst vjp_const(double eps, double sig, double rc, int shift)
+{
+    VjpConst c;
+    c.eps = eps;
+    c.eos = eps / sig;
+    c.s2 = sig * sig;
+    const double c2 = c.s2 / (rc * rc), c6 = c2 * c2 * c2, c12 = c6 * c6;
+    c.ush1 = shift ? 4.0 * (c12 - c6) : 0.0;
+    c.dus1 = shift ? (48.0 * c12 - 24.0 * c6) : 0.0;
+    return c;
+}
+
+struct VjpTerms {
+    double fr1, dfr1, u1, dfs1, dus1;
+};
+
+template <int PREC>
+__device__ __forceinline__ VjpTerms vjp_terms(const VjpConst &c, double r2)
+{
+    VjpTerms v;
+    if (PREC == MD_FP64) {
+        const double inv = rcp_f64(r2);
+        const double s2 = c.s2 * inv, s6 = s2 * s2 * s2, s12 = s6 * s6;
+        v.fr1 = 24.0 * s6 * (2.0 * s6 - 1.0) * inv;
+        v.dfr1 = (-672.0 * s12 + 192.0 * s6) * inv * inv;
+        v.u1 = 4.0 * (s12 - s6) - c.ush1;
+        v.dfs1 = (576.0 * s12 - 144.0 * s6) * inv;
+        v.dus1 = (48.0 * s12 - 24.0 * s6) - c.dus1;
+    } else {
+        const float invf = __builtin_amdgcn_rcpf(static_cast<float>(r2));
+        const float s2 = static_cast<float>(c.s2) * invf, s6 = s2 * s2 * s2, s12 = s6 * s6;
+        v.fr1 = static_cast<double>(24.0f * s6 * (2.0f * s6 - 1.0f) * invf);
+        v.dfr1 = static_cast<double>((-672.0f * s12 + 192.0f * s6) * invf * invf);
+        v.u1 = static_cast<double>(4.0f * (s12 - s6)) - c.ush1;
+        v.dfs1 = static_cast<double>((576.0f * s12 - 144.0f * s6) * invf);
+        v.dus1 = static_cast<double>(48.0f * s12 - 24.0f * s6) - c.dus1;
+    }
+    return v;
+}
+
 }  // namespace md

@@ -55,7 +55,8 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
     double xi = 0.0, yi = 0.0, zi = 0.0;
     u32x4 cur[NB];
     const int total = stage_from_table<TB, P4>(
-        s, a.tile_src + size_t(t) * tab_stride(CAP), a.n_atoms, a.x, a.y, a.z, a.pos4, st, CAP, [&] {
+        s, a.tile_src + size_t(t) * tab_stride(CAP), a.n_atoms, a.x, a.y, a.z, a.pos4, st, CAP,
+        nullptr, [&] {
             hr = home_rows(s, a.cell_start);
             nh = hr.total;
             if (nh == 0) return false;

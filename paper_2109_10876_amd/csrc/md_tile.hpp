@@ -111,15 +111,19 @@ __device__ __forceinline__ int staged_row(const TileSpec &s, int dy, int dz)
     return (dz + 1) * (s.hy + 2) + (dy + 1);
 }
 
-// Staging table of a tile, written by the list build for the force kernel:
+// Staging record of a tile, written by the list build for the force kernel:
 // word sl (< staged count) holds slot sl's source atom in its low 26 bits
 // and the image shift of x, y, z in two bits each (0: none, 1: +L, 2: -L);
-// word kTabTotal holds the staged count.  kTabStride words per tile.
+// word kTabTotal holds the staged count; words kTabAdj .. +63 hold the
+// adjoint's per-tile (eps, sigma) sums (32 doubles).  tab_stride words per
+// tile.
 constexpr uint32_t kTabSrcMask = (1u << 26) - 1;
 constexpr int kTabShiftX = 26, kTabShiftY = 28, kTabShiftZ = 30;
 template <class Stage>
 constexpr int kTabTotal = Stage::kCap;
-constexpr int tab_stride(int cap) { return cap + 64; }
+template <class Stage>
+constexpr int kTabAdj = Stage::kCap + 64;
+constexpr int tab_stride(int cap) { return cap + 128; }
 
 __device__ __forceinline__ uint32_t shift_code(double d)
 {
@@ -317,12 +321,13 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
 // no cell-start reads and no per-slot source search.  mid() runs while the
 // table loads are in flight (returning false abandons the staging: -1).
 // Source indices are clamped below n_atoms, so a table that no build has
-// written gathers garbage but stays in bounds.
+// written gathers garbage but stays in bounds.  lsrc (optional, LDS, cap
+// entries) receives every staged slot's source atom.
 template <int TB, bool P4, class Stage, class Mid>
 __device__ int stage_from_table(const TileSpec &s, const uint32_t *__restrict__ tab, int n_atoms,
                                 const double *__restrict__ x, const double *__restrict__ y,
                                 const double *__restrict__ z, const double *__restrict__ pos4,
-                                Stage &st, int cap, Mid &&mid)
+                                Stage &st, int cap, int *lsrc, Mid &&mid)
 {
     constexpr int kPer = (Stage::kCap + TB - 1) / TB;
     const int tid = threadIdx.x;
@@ -345,6 +350,10 @@ __device__ int stage_from_table(const TileSpec &s, const uint32_t *__restrict__ 
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int src = min(int(code[k] & kTabSrcMask), n_atoms - 1);
+        if (lsrc) {
+            const int sl = tid + k * TB;
+            if (sl < total) lsrc[sl] = src;
+        }
         if (P4) {
             const double4 v = reinterpret_cast<const double4 *>(pos4)[src];
             px[k] = v.x;
@@ -453,8 +462,11 @@ struct TileArgs {
     // forces
     const double *eps, *sig;
     int32_t shift;
-    uint32_t *tile_src;   // staging tables, tab_stride(CAP) words per tile
+    uint32_t *tile_src;   // staging records, tab_stride(CAP) words per tile
     int32_t n_atoms;
+    // adjoint
+    const double *gfx, *gfy, *gfz, *gE;
+    double *gx;
     double rc;
     double *fx, *fy, *fz;
     int32_t accumulate;

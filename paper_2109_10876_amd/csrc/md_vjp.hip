@@ -16,7 +16,7 @@
 // partner's visit gives -w to the partner), so each thread writes only its
 // own gradient -- no atomics, nothing stored from the forward pass: the pair
 // terms are recomputed.  Parameter terms are seen from both atoms and halved.
-#include "md_common.hpp"
+#include "md_pair.hpp"
 
 namespace md {
 namespace {
@@ -38,22 +38,6 @@ struct VjpArgs {
     double *vpart;   // [n_units][2][MD_MAX_TYPES^2]
     uint32_t *status;
 };
-
-struct VjpConst {
-    double eps, eos, s2, ush1, dus1;   // eps, eps/sig, sig^2, U(rc)/eps, shift part of dU/dsig / (eps/sig)
-};
-
-__device__ __forceinline__ VjpConst vjp_const(double eps, double sig, double rc, int shift)
-{
-    VjpConst c;
-    c.eps = eps;
-    c.eos = eps / sig;
-    c.s2 = sig * sig;
-    const double c2 = c.s2 / (rc * rc), c6 = c2 * c2 * c2, c12 = c6 * c6;
-    c.ush1 = shift ? 4.0 * (c12 - c6) : 0.0;
-    c.dus1 = shift ? (48.0 * c12 - 24.0 * c6) : 0.0;
-    return c;
-}
 
 constexpr int kSlots = MD_MAX_TYPES * MD_MAX_TYPES;
 
@@ -99,24 +83,8 @@ __global__ __launch_bounds__(kUnit) void k_vjp(VjpArgs a)
             if (!(r2 < rc2)) continue;
             const int tj = NT > 1 ? a.type[j] : 0;
             const VjpConst c = tab[ti * nt + tj];
-            double fr1, dfr1, u1, dfs1, dus1, inv;   // per unit eps (or eps/sig)
-            if (PREC == MD_FP64) {
-                inv = rcp_f64(r2);
-                const double s2 = c.s2 * inv, s6 = s2 * s2 * s2, s12 = s6 * s6;
-                fr1 = 24.0 * s6 * (2.0 * s6 - 1.0) * inv;
-                dfr1 = (-672.0 * s12 + 192.0 * s6) * inv * inv;
-                u1 = 4.0 * (s12 - s6) - c.ush1;
-                dfs1 = (576.0 * s12 - 144.0 * s6) * inv;
-                dus1 = (48.0 * s12 - 24.0 * s6) - c.dus1;
-            } else {
-                const float invf = __builtin_amdgcn_rcpf(static_cast<float>(r2));
-                const float s2 = static_cast<float>(c.s2) * invf, s6 = s2 * s2 * s2, s12 = s6 * s6;
-                fr1 = static_cast<double>(24.0f * s6 * (2.0f * s6 - 1.0f) * invf);
-                dfr1 = static_cast<double>((-672.0f * s12 + 192.0f * s6) * invf * invf);
-                u1 = static_cast<double>(4.0f * (s12 - s6)) - c.ush1;
-                dfs1 = static_cast<double>((576.0f * s12 - 144.0f * s6) * invf);
-                dus1 = static_cast<double>(48.0f * s12 - 24.0f * s6) - c.dus1;
-            }
+            const VjpTerms v = vjp_terms<PREC>(c, r2);
+            const double fr1 = v.fr1, dfr1 = v.dfr1, u1 = v.u1, dfs1 = v.dfs1, dus1 = v.dus1;
             const double fr = c.eps * fr1, dfr = c.eps * dfr1;
             const double ux = Gx - a.gfx[j], uy = Gy - a.gfy[j], uz = Gz - a.gfz[j];
             const double du = dx * ux + dy * uy + dz * uz;
@@ -187,13 +155,21 @@ extern "C" int md_lj_forces_vjp(const md_batch *b, const md_atoms *atoms, const 
     if (!atoms || !atoms->x || !atoms->y || !atoms->z || !nl || !nl->count || !nl->idx || !p ||
         !p->eps || !p->sig || !gfx || !gfy || !gfz || !gx || !ws)
         return MD_EINVAL;
-    if (nl->mode != MD_FULL) return MD_EUNSUPPORTED;
+    if (nl->mode != MD_FULL && nl->mode != MD_TILE_FULL) return MD_EUNSUPPORTED;
     if (nl->max_nbr < 1 || nl->ld < b->N || nl->ld % 64 != 0) return MD_EINVAL;
     if (p->ntypes < 1 || p->ntypes > MD_MAX_TYPES || !(p->rc > 0.0)) return MD_EINVAL;
     if (p->ntypes > 1 && !atoms->type) return MD_EINVAL;
     if (prec != MD_FP64 && prec != MD_FP32_MIXED) return MD_EINVAL;
     const WsLayout l = ws_layout(b);
     if (ws_bytes < l.total) return MD_ENOWS;
+    if (nl->mode == MD_TILE_FULL) {
+        // as for md_lj_forces: a typed list for several types, and only then
+        if (!tile_list_ok(b, nl) || !nl->cell_start) return MD_EINVAL;
+        if (p->ntypes > MD_TILE_MAX_TYPES) return MD_EUNSUPPORTED;
+        if (p->ntypes > 1 ? nl->tile_types != p->ntypes : nl->tile_types > 1) return MD_EINVAL;
+        return tile_vjp(b, atoms, nl, p, prec, gfx, gfy, gfz, gE, gx, geps, gsig, status,
+                        as_stream(stream));
+    }
     VjpArgs a{b->atom_off, b->unit_rep, b->unit_off, b->box, atoms->x, atoms->y, atoms->z,
               atoms->type, nl->count, nl->idx, nl->ld, nl->max_nbr, p->eps, p->sig, p->ntypes,
               p->shift, p->rc, gfx, gfy, gfz, gE, gx, b->N, ws_at<double>(ws, l.vjp_partial),

@@ -248,9 +248,9 @@ class MDSystem:
         self.tile_cells, self.n_tiles = m, n
         self.tile_rep = torch.as_tensor(rep).to(self.dev)
         self.tile_off = torch.as_tensor(off).to(self.dev)
-        # per-tile staging tables (capacity + 64 words each), written by the build
+        # per-tile staging records (capacity + 128 words each), written by the build
         self.tile_src_cap = self.lib.md_tile_capacity()
-        self.tile_src = torch.zeros(n * (self.tile_src_cap + 64), dtype=torch.int32,
+        self.tile_src = torch.zeros(n * (self.tile_src_cap + 128), dtype=torch.int32,
                                     device=self.dev)
 
     def _alloc_list(self, max_nbr):

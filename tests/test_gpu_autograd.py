@@ -12,10 +12,10 @@ import oracle
 pytestmark = pytest.mark.gpu
 
 
-def _system(cfg, prec="fp64"):
+def _system(cfg, prec="fp64", mode="full"):
     from paper_2109_10876_amd import MDSystem
     s = MDSystem(cfg.natoms, cfg.box, cfg.pos, cfg.vel, cfg.types, cfg.eps, cfg.sig, cfg.mass,
-                 rc=cfg.rc, skin=cfg.skin, prec=prec)
+                 rc=cfg.rc, skin=cfg.skin, prec=prec, mode=mode)
     s.setup()
     s.ensure_list()
     return s
@@ -26,11 +26,12 @@ def case():
     return md_inputs.replica_batch(nrep=2, nmin=1500, nmax=3000, seed=31)
 
 
-def test_backward_matches_finite_differences(case):
+@pytest.mark.parametrize("mode", ["full", "tile"])
+def test_backward_matches_finite_differences(case, mode):
     import torch
     from paper_2109_10876_amd.autograd import lj_forces
-    print("case: autograd fd", flush=True)
-    s = _system(case)
+    print(f"case: autograd fd {mode}", flush=True)
+    s = _system(case, mode=mode)
     dev = s.dev
     pos0 = torch.stack([s.x, s.y, s.z], 1).clone()
     eps0 = torch.tensor(case.eps, device=dev)

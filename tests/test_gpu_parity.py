@@ -294,12 +294,13 @@ def test_batch_equals_each_replica_alone():
         assert float(t.ke[0]) == float(s.ke[r])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_vjp_matches_oracle(prec):
+@pytest.mark.parametrize("prec,mode", [("fp64", "full"), ("mixed", "full"), ("fp64", "tile"),
+                                       ("mixed", "tile")])
+def test_vjp_matches_oracle(prec, mode):
     import torch
     cfg = md_inputs.replica_batch(nrep=3, nmin=900, nmax=2500, seed=13)
-    say(f"case: vjp {prec}")
-    s = _system(cfg, mode="full", prec=prec)
+    say(f"case: vjp {prec} {mode}")
+    s = _system(cfg, mode=mode, prec=prec)
     s.setup()
     rng = np.random.default_rng(0)
     G = rng.normal(size=(cfg.n, 3))
@@ -669,3 +670,37 @@ def test_kernel_timing_records_eager_pair_kernels_only(c1_snapshot):
         s.forces()  # four eager launches, the first three timed
     assert lib.md_kernel_timing_read(ctypes.byref(ms), ctypes.byref(n)) == 0
     assert n.value == 3 and 0.0 < ms.value < 100.0
+
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_tile_vjp_equals_global_vjp_one_type(prec):
+    # the same adjoint over a tile-local and a global-index list of one type
+    import torch
+    cfg = md_inputs.lj_fluid(8, temperature=1.0, seed=21, jitter_amp=0.05)
+    say(f"case: tile vs global vjp {prec}")
+    rng = np.random.default_rng(4)
+    G = rng.normal(size=(cfg.n, 3))
+    out = {}
+    for mode in ("full", "tile"):
+        s = _system(cfg, mode=mode, prec=prec)
+        s.setup()
+        assert s.ensure_list() == 0
+        ids = s.id.cpu().numpy()
+        d = s.dev
+        gfx, gfy, gfz = (torch.tensor(G[ids, k].copy(), device=d) for k in range(3))
+        gx = torch.zeros(3 * cfg.n, dtype=torch.float64, device=d)
+        ge = torch.zeros(1, dtype=torch.float64, device=d)
+        gs = torch.zeros(1, dtype=torch.float64, device=d)
+        s.vjp(gfx, gfy, gfz, torch.tensor([0.7], device=d, dtype=torch.float64), gx, ge, gs)
+        torch.cuda.synchronize()
+        gxs = gx.cpu().numpy().reshape(3, cfg.n).T
+        got = np.empty_like(gxs)
+        got[ids] = gxs
+        out[mode] = (got, float(ge.item()), float(gs.item()))
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert _err(out["tile"][0], out["full"][0]) < tol
+    assert out["tile"][1] == pytest.approx(out["full"][1], rel=tol * 10)
+    assert out["tile"][2] == pytest.approx(out["full"][2], rel=tol * 10)
+    gx_r, ge_r, gs_r = oracle.lj_vjp(cfg.pos, cfg.box[0], RC, G, 0.7, shift=1)
+    assert _err(out["tile"][0], gx_r) < (1e-11 if prec == "fp64" else 1e-5)
