@@ -9,7 +9,8 @@ so that the two sides see bit-identical inputs.
 Workloads follow the paper's evaluation setup (Sec. 4, "Performance
 evaluation"): LJ units with m = eps = sigma = 1, density 0.8442, cutoff 2.5,
 skin 0.3, time step 0.005; a bead-spring polymer melt at density 0.85 with a
-purely repulsive LJ cutoff 2^(1/6) and skin 0.4.  The paper starts the LJ
+purely repulsive LJ cutoff 2^(1/6) and skin 0.4, with linear chains or, as
+in the paper, rings of 200 beads.  The paper starts the LJ
 fluid from a "cubic lattice"; the workloads here use the FCC lattice (four
 sites per cubic unit cell), which is the usual reading for rho = 0.8442.
 
@@ -24,7 +25,8 @@ import numpy as np
 
 __all__ = [
     "Config", "fcc_lattice", "maxwell_velocities", "jitter", "lj_fluid",
-    "random_walk_chains", "lattice_chains", "lj_slab", "lj_sphere", "replica_batch", "CONFIGS",
+    "random_walk_chains", "lattice_chains", "ring_cycle", "lattice_rings", "lj_slab",
+    "lj_sphere", "replica_batch", "CONFIGS",
 ]
 
 # Basis of the FCC conventional cubic cell, in units of the lattice constant.
@@ -95,6 +97,7 @@ class Config:
     steps: int
     shift: int = 1
     bonds: np.ndarray | None = None
+    angles: np.ndarray | None = None
 
     @property
     def n(self):
@@ -185,6 +188,56 @@ def lattice_chains(shape, length, rho=0.85, seed=3, temperature=1.0, dt=0.005,
                   2.0 ** (1.0 / 6.0), 0.4, dt, temperature, steps, shift=1, bonds=bonds)
 
 
+def ring_cycle(ny, nz):
+    """A closed path through the 2 x ny x nz block of lattice sites (x, y, z)
+    that steps between lattice neighbours only (ny even): a boustrophedon over
+    the (y, z) layer at x = 0 from (0, 0, 0) to (0, 0, nz - 1) (rows along y,
+    one row per z), then the same path backwards in the layer x = 1, which
+    ends next to the start."""
+    assert nz % 2 == 0
+    layer = []
+    for z in range(nz):
+        ys = range(ny) if z % 2 == 0 else range(ny - 1, -1, -1)
+        layer.extend((y, z) for y in ys)
+    return [(0, y, z) for y, z in layer] + [(1, y, z) for y, z in reversed(layer)]
+
+
+def lattice_rings(shape, block=(2, 10, 10), rho=0.85, seed=7, temperature=1.0, dt=0.005,
+                  steps=1000):
+    """Ring polymers on a simple-cubic lattice of shape (mx, my, mz) with
+    spacing (1/rho)^(1/3): the lattice is cut into blocks of 2 x by x bz
+    sites and each block holds one ring along ``ring_cycle`` (2 by bz beads,
+    every bond one lattice spacing, no two beads overlapping).  Returns the
+    ring bonds (closing bond included) and one angle triple per bead with the
+    bead in the middle."""
+    mx, my, mz = shape
+    bx, by, bz = block
+    assert bx == 2 and mx % bx == 0 and my % by == 0 and mz % bz == 0
+    cyc = np.array(ring_cycle(by, bz), dtype=np.int64)
+    length = cyc.shape[0]
+    a = (1.0 / rho) ** (1.0 / 3.0)
+    corners = np.stack(np.meshgrid(np.arange(0, mx, bx), np.arange(0, my, by),
+                                   np.arange(0, mz, bz), indexing="ij"), axis=-1).reshape(-1, 3)
+    sites = (corners[:, None, :] + cyc[None, :, :]).reshape(-1, 3)
+    n = sites.shape[0]
+    pos = (sites.astype(np.float64) + 0.5) * a
+    vel = maxwell_velocities(n, temperature, 1.0, seed=seed)
+    nring = corners.shape[0]
+    k = np.arange(length)
+    base = (np.arange(nring) * length)[:, None]
+    me = (base + k[None, :]).ravel()
+    nxt = (base + (k[None, :] + 1) % length).ravel()
+    prv = (base + (k[None, :] - 1) % length).ravel()
+    bonds = np.stack([me, nxt], axis=1).astype(np.int32)
+    angles = np.stack([prv, me, nxt], axis=1).astype(np.int32)
+    one = np.ones((1, 1))
+    return Config(f"ring_melt_{nring}x{length}", pos, vel,
+                  np.array([[mx * a, my * a, mz * a]]), np.array([n], dtype=np.int64),
+                  np.zeros(n, np.int32), 1, one.copy(), one.copy(), np.ones(1),
+                  2.0 ** (1.0 / 6.0), 0.4, dt, temperature, steps, shift=1, bonds=bonds,
+                  angles=angles)
+
+
 def lj_slab(m=50, rho=0.8, temperature=0.85, seed=4, dt=0.005, steps=1000):
     """FCC slab of m^3 unit cells at density rho, centred in z in a box whose
     z edge is three times the slab thickness (vacuum on both sides)."""
@@ -271,6 +324,7 @@ CONFIGS = {
                              name="lj_fcc64_n1048576"),
     "kg_melt": lambda: lattice_chains((80, 80, 128), 200, seed=3),
     "kg_melt_random_walk": lambda: random_walk_chains(4096, 200, seed=3),
+    "ring_melt": lambda: lattice_rings((80, 80, 50), seed=7),
     "lj_slab": lambda: lj_slab(50, seed=4),
     "lj_sphere": lambda: lj_sphere(seed=6),
     "replicas": lambda: replica_batch(256, seed=5),

@@ -94,10 +94,16 @@ def _load():
     lib.orc_fene_forces.restype = i64
     lib.orc_fene_forces.argtypes = [i32, _D, _D, _D, _D, i64, _I, _I, dbl, dbl,
                                     _D, _D, _D, _D, _D]
+    lib.orc_angle_triple.restype = ctypes.c_int
+    lib.orc_angle_triple.argtypes = [_D, _D, dbl, _D, _D, _D]
+    lib.orc_angle_forces.restype = i64
+    lib.orc_angle_forces.argtypes = [i32, _D, _D, _D, _D, i64, _I, _I, _I, dbl,
+                                     _D, _D, _D, _D, _D]
     lib.orc_md_run_ext.restype = i64
     lib.orc_md_run_ext.argtypes = [i32, _D, _D, _D, _D, _D, _D, _I, i32, _D, _D, _D, _D, dbl,
-                                   i32, dbl, dbl, i32, i64, _I, _I, dbl, dbl, dbl, dbl,
-                                   ctypes.c_uint64, ctypes.c_uint64, _U8, _D, _D, _D, _D, _D]
+                                   i32, dbl, dbl, i32, i64, _I, _I, dbl, dbl, i64, _I, _I, _I,
+                                   dbl, dbl, dbl, ctypes.c_uint64, ctypes.c_uint64, _U8, _D,
+                                   _D, _D, _D, _D]
     _lib = lib
     return lib
 
@@ -364,13 +370,46 @@ def fene_forces(pos, box, bonds, K=30.0, R0=1.5):
     return np.stack([fx, fy, fz], axis=1), e.value, w.value, int(broken)
 
 
+def angle_triple(d1, d2, K=1.5):
+    """Cosine angle term of one triple from its two bond vectors d1 = x_a - x_b,
+    d2 = x_c - x_b: (U, F_a, F_c, ok); F_b = -F_a - F_c."""
+    d1 = _f64(d1).ravel().copy()
+    d2 = _f64(d2).ravel().copy()
+    fa, fc = np.zeros(3), np.zeros(3)
+    u = ctypes.c_double()
+    ok = _load().orc_angle_triple(_d(d1), _d(d2), float(K), ctypes.byref(u), _d(fa), _d(fc))
+    return u.value, fa, fc, bool(ok)
+
+
+def _triples(angles):
+    angles = np.ascontiguousarray(np.asarray(angles).reshape(-1, 3), dtype=np.int32)
+    return tuple(np.ascontiguousarray(angles[:, k]) for k in range(3))
+
+
+def angle_forces(pos, box, angles, K=1.5):
+    """Angle forces [N,3], energy, virial and degenerate-triple count for
+    triples given as atom indices [Na,3] (middle bead in column 1)."""
+    lib = _load()
+    x, y, z = _planes(pos)
+    n = x.shape[0]
+    ia, ib, ic = _triples(angles)
+    fx, fy, fz = (np.zeros(n) for _ in range(3))
+    e = ctypes.c_double(0.0)
+    w = ctypes.c_double(0.0)
+    bad = lib.orc_angle_forces(n, _d(x), _d(y), _d(z), _d(_f64(box).ravel().copy()),
+                               ia.shape[0], _i(ia), _i(ib), _i(ic), float(K),
+                               _d(fx), _d(fy), _d(fz), ctypes.byref(e), ctypes.byref(w))
+    return np.stack([fx, fy, fz], axis=1), e.value, w.value, int(bad)
+
+
 def md_run_ext(pos, vel, box, rc, skin, dt, steps, eps=1.0, sig=1.0, types=None, mass=None,
-               shift=1, bonds=None, K=30.0, R0=1.5, gamma=0.0, temperature=1.0, seed=0,
-               step0=0):
-    """Velocity Verlet with LJ, optional FENE bonds ([Nb,2] atom indices) and
-    optional Langevin thermostat (noise counter step0 for the initial forces,
-    step0 + 1 + s for step s).  Returns final state, rebuild flags, energies
-    and the number of broken-bond events."""
+               shift=1, bonds=None, K=30.0, R0=1.5, angles=None, Ka=1.5, gamma=0.0,
+               temperature=1.0, seed=0, step0=0):
+    """Velocity Verlet with LJ, optional FENE bonds ([Nb,2] atom indices),
+    optional cosine angle terms ([Na,3] atom indices, middle bead in column 1)
+    and optional Langevin thermostat (noise counter step0 for the initial
+    forces, step0 + 1 + s for step s).  Returns final state, rebuild flags,
+    energies and the number of broken-bond and degenerate-angle events."""
     lib = _load()
     x, y, z = (p.copy() for p in _planes(pos))
     vx, vy, vz = (p.copy() for p in _planes(vel))
@@ -383,13 +422,15 @@ def md_run_ext(pos, vel, box, rc, skin, dt, steps, eps=1.0, sig=1.0, types=None,
     bonds = np.ascontiguousarray(bonds, dtype=np.int32)
     bi = np.ascontiguousarray(bonds[:, 0])
     bj = np.ascontiguousarray(bonds[:, 1])
+    ia, ib, ic = _triples(np.zeros((0, 3), np.int32) if angles is None else angles)
     reb = np.zeros(max(steps, 1), np.uint8)
     ep, ek = np.zeros(steps + 1), np.zeros(steps + 1)
     fx, fy, fz = (np.zeros(n) for _ in range(3))
     r = lib.orc_md_run_ext(n, _d(x), _d(y), _d(z), _d(vx), _d(vy), _d(vz), _i(t), nt, _d(m),
                            _d(e_t), _d(s_t), _d(_f64(box).ravel().copy()), float(rc), int(shift),
                            float(skin), float(dt), int(steps), bonds.shape[0], _i(bi), _i(bj),
-                           float(K), float(R0), float(gamma), float(temperature), int(seed),
+                           float(K), float(R0), ia.shape[0], _i(ia), _i(ib), _i(ic), float(Ka),
+                           float(gamma), float(temperature), int(seed),
                            int(step0), reb.ctypes.data_as(_U8), _d(ep), _d(ek), _d(fx), _d(fy),
                            _d(fz))
     if r < 0:

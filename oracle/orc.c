@@ -17,8 +17,9 @@
  *     Verlet list = pairs within r_cut + r_skin          (Sec. 2.1.2)
  *   - velocity Verlet in two half steps (Integrate1 / Integrate2) with a
  *     skin-triggered re-binning                          (Sec. 2.1, Fig. 1)
- *   - FENE bonds and the purely repulsive LJ of the polymer melt, and a
- *     Langevin thermostat                                 (Sec. 4, setup)
+ *   - FENE bonds and the purely repulsive LJ of the polymer melt, the
+ *     cosine angle term on bonded triples of the ring melt, and a Langevin
+ *     thermostat                                           (Sec. 4, setup)
  * Gradients of forces and energy with respect to positions and to the
  * (epsilon, sigma) tables are the analytic derivatives of Eq. lj.
  *
@@ -535,6 +536,64 @@ EXPORT int64_t orc_fene_forces(int32_t n, const double *x, const double *y,
     return broken;
 }
 
+/* ------------------------------------------------------ cosine angle term */
+
+/* Angle term of the ring-polymer melt (Sec. 4, setup: a cosine potential on
+ * the triples of consecutive beads).  For the triple (a, b, c) with middle
+ * bead b, d1 = x_a - x_b and d2 = x_c - x_b (minimum image),
+ *     cos t = d1.d2 / (|d1| |d2|),   U = K (1 + cos t),
+ * so a straight triple (t = pi) costs nothing.  The forces are -grad U:
+ *     dcos/dx_a = d2 / (|d1| |d2|) - cos t d1 / |d1|^2,   F_a = -K dcos/dx_a,
+ *     dcos/dx_c = d1 / (|d1| |d2|) - cos t d2 / |d2|^2,   F_c = -K dcos/dx_c,
+ *     F_b = -F_a - F_c.
+ * Returns 0 (U and the forces left at 0) when a bond vector has zero length. */
+EXPORT int orc_angle_triple(const double *d1, const double *d2, double K, double *u,
+                            double *fa, double *fc)
+{
+    double r11 = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2];
+    double r22 = d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2];
+    *u = 0.0;
+    for (int k = 0; k < 3; ++k) fa[k] = fc[k] = 0.0;
+    if (!(r11 > 0.0) || !(r22 > 0.0)) return 0;
+    double r1 = sqrt(r11), r2 = sqrt(r22);
+    double c = (d1[0] * d2[0] + d1[1] * d2[1] + d1[2] * d2[2]) / (r1 * r2);
+    *u = K * (1.0 + c);
+    for (int k = 0; k < 3; ++k) {
+        fa[k] = -K * (d2[k] / (r1 * r2) - c * d1[k] / r11);
+        fc[k] = -K * (d1[k] / (r1 * r2) - c * d2[k] / r22);
+    }
+    return 1;
+}
+
+/* Adds the angle forces of the triples (ia[t], ib[t], ic[t]) (atom indices,
+ * ib the middle bead); adds their energy and virial (sum over the triple of
+ * x . F, i.e. d1.F_a + d2.F_c); returns the number of degenerate triples. */
+EXPORT int64_t orc_angle_forces(int32_t n, const double *x, const double *y,
+                                const double *z, const double *L, int64_t na,
+                                const int32_t *ia, const int32_t *ib, const int32_t *ic,
+                                double K, double *fx, double *fy, double *fz,
+                                double *energy, double *virial)
+{
+    (void)n;
+    int64_t bad = 0;
+    double e = 0.0, w = 0.0, d1[3], d2[3], fa[3], fc[3], u;
+    for (int64_t t = 0; t < na; ++t) {
+        int32_t a = ia[t], b = ib[t], c = ic[t];
+        dist2(x, y, z, L, a, b, &d1[0], &d1[1], &d1[2]);
+        dist2(x, y, z, L, c, b, &d2[0], &d2[1], &d2[2]);
+        if (!orc_angle_triple(d1, d2, K, &u, fa, fc)) { ++bad; continue; }
+        fx[a] += fa[0]; fy[a] += fa[1]; fz[a] += fa[2];
+        fx[c] += fc[0]; fy[c] += fc[1]; fz[c] += fc[2];
+        fx[b] -= fa[0] + fc[0]; fy[b] -= fa[1] + fc[1]; fz[b] -= fa[2] + fc[2];
+        e += u;
+        w += d1[0] * fa[0] + d1[1] * fa[1] + d1[2] * fa[2] +
+             d2[0] * fc[0] + d2[1] * fc[1] + d2[2] * fc[2];
+    }
+    *energy += e;
+    *virial += w;
+    return bad;
+}
+
 /* ------------------------------------------- MD with bonds and a thermostat */
 
 static int64_t total_forces(int32_t n, const double *x, const double *y, const double *z,
@@ -542,7 +601,9 @@ static int64_t total_forces(int32_t n, const double *x, const double *y, const d
                             const int32_t *type, int32_t nt, const double *mass,
                             const double *eps, const double *sig, const double *L,
                             double rc, int32_t shift, int64_t nb, const int32_t *bi,
-                            const int32_t *bj, double K, double R0, double gamma,
+                            const int32_t *bj, double K, double R0, int64_t na,
+                            const int32_t *ia, const int32_t *ib, const int32_t *ic,
+                            double Ka, double gamma,
                             double temperature, double dt, uint64_t seed, uint64_t step,
                             const int32_t *ids, double *fx, double *fy, double *fz,
                             double *energy, int64_t *broken)
@@ -551,6 +612,7 @@ static int64_t total_forces(int32_t n, const double *x, const double *y, const d
     int64_t np = orc_lj_forces(n, x, y, z, type, nt, eps, sig, L, rc, shift, fx, fy, fz, &e, &w);
     if (np < 0) return np;
     if (nb > 0) *broken += orc_fene_forces(n, x, y, z, L, nb, bi, bj, K, R0, fx, fy, fz, &e, &w);
+    if (na > 0) *broken += orc_angle_forces(n, x, y, z, L, na, ia, ib, ic, Ka, fx, fy, fz, &e, &w);
     if (gamma > 0.0)
         orc_langevin(n, vx, vy, vz, type, mass, ids, gamma, temperature, dt, seed, step,
                      fx, fy, fz);
@@ -559,20 +621,23 @@ static int64_t total_forces(int32_t n, const double *x, const double *y, const d
 }
 
 /* Velocity Verlet (Sec. 2.1, Fig. 1) with LJ pair forces, optional FENE bonds
- * (pairs bi[b]-bj[b] of atom indices, the polymer melt of Sec. 4) and an
+ * (pairs bi[b]-bj[b] of atom indices, the polymer melt of Sec. 4), optional
+ * cosine angle terms on triples ia[t]-ib[t]-ic[t] (the ring melt) and an
  * optional Langevin thermostat (Sec. 4: equilibration to a target T).  The
  * thermostat force is evaluated with the velocity at the time of the force
  * evaluation (after Integrate1) and noise counter step0 for the initial force
  * evaluation, step0 + 1 + s for step s; atom ids are the indices.  Records the
- * rebuild test like orc_md_run, the potential energy (LJ + FENE) and the
- * kinetic energy.  Returns the number of broken-bond events (>= 0), or a
- * negative error. */
+ * rebuild test like orc_md_run, the potential energy (LJ + FENE + angle) and
+ * the kinetic energy.  Returns the number of broken-bond and degenerate-angle
+ * events (>= 0), or a negative error. */
 EXPORT int64_t orc_md_run_ext(int32_t n, double *x, double *y, double *z, double *vx,
                               double *vy, double *vz, const int32_t *type, int32_t nt,
                               const double *mass, const double *eps, const double *sig,
                               const double *L, double rc, int32_t shift, double skin,
                               double dt, int32_t steps, int64_t nb, const int32_t *bi,
-                              const int32_t *bj, double K, double R0, double gamma,
+                              const int32_t *bj, double K, double R0, int64_t na,
+                              const int32_t *ia, const int32_t *ib, const int32_t *ic,
+                              double Ka, double gamma,
                               double temperature, uint64_t seed, uint64_t step0,
                               uint8_t *rebuild, double *epot, double *ekin,
                               double *fx, double *fy, double *fz)
@@ -588,8 +653,8 @@ EXPORT int64_t orc_md_run_ext(int32_t n, double *x, double *y, double *z, double
     int64_t broken = 0, rc_ = 0;
     double e = 0.0;
     rc_ = total_forces(n, x, y, z, vx, vy, vz, type, nt, mass, eps, sig, L, rc, shift, nb, bi,
-                       bj, K, R0, gamma, temperature, dt, seed, step0, ids, fx, fy, fz, &e,
-                       &broken);
+                       bj, K, R0, na, ia, ib, ic, Ka, gamma, temperature, dt, seed, step0, ids,
+                       fx, fy, fz, &e, &broken);
     double k = 0.0;
     for (int32_t i = 0; i < n; ++i) {
         double m = mass[type ? type[i] : 0];
@@ -621,8 +686,8 @@ EXPORT int64_t orc_md_run_ext(int32_t n, double *x, double *y, double *z, double
             memcpy(zb, z, sizeof(double) * n);
         }
         rc_ = total_forces(n, x, y, z, vx, vy, vz, type, nt, mass, eps, sig, L, rc, shift, nb,
-                           bi, bj, K, R0, gamma, temperature, dt, seed, step0 + 1 + (uint64_t)s,
-                           ids, fx, fy, fz, &e, &broken);
+                           bi, bj, K, R0, na, ia, ib, ic, Ka, gamma, temperature, dt, seed,
+                           step0 + 1 + (uint64_t)s, ids, fx, fy, fz, &e, &broken);
         if (rc_ < 0) goto done;
         k = 0.0;
         for (int32_t i = 0; i < n; ++i) {

@@ -3,6 +3,7 @@ geometry of the inputs; no arithmetic of the method)."""
 import math
 
 import numpy as np
+import pytest
 
 import md_inputs
 
@@ -30,3 +31,28 @@ def test_sphere_workload_size():
     assert cfg.n == 2580188 and cfg.box.tolist() == [[271.0, 271.0, 271.0]]
     frac = cfg.n / 0.8442 / 271.0 ** 3
     assert abs(frac - 0.154) < 0.002
+
+
+def test_ring_melt_geometry():
+    cfg = md_inputs.CONFIGS["ring_melt"]()
+    a = (1.0 / 0.85) ** (1.0 / 3.0)
+    assert cfg.n == 320_000 and cfg.bonds.shape == (320_000, 2)
+    assert cfg.angles.shape == (320_000, 3)
+    assert cfg.n / np.prod(cfg.box[0]) == pytest.approx(0.85, rel=1e-12)
+    # every bond, the closing one included, is one lattice spacing long
+    d = cfg.pos[cfg.bonds[:, 0]] - cfg.pos[cfg.bonds[:, 1]]
+    np.testing.assert_allclose(np.linalg.norm(d, axis=1), a, rtol=1e-12)
+    # rings of 200: bead k of ring r bonds to bead k+1 mod 200 of the same ring
+    ring = cfg.bonds // 200
+    assert np.array_equal(ring[:, 0], ring[:, 1])
+    assert np.array_equal(cfg.bonds[:, 1] % 200, (cfg.bonds[:, 0] % 200 + 1) % 200)
+    # each bead is the middle of exactly one triple, between its two partners
+    assert np.array_equal(np.sort(cfg.angles[:, 1]), np.arange(cfg.n))
+    nxt = np.empty(cfg.n, np.int64)
+    nxt[cfg.bonds[:, 0]] = cfg.bonds[:, 1]
+    assert np.array_equal(cfg.angles[:, 2], nxt[cfg.angles[:, 1]])
+    assert np.array_equal(nxt[cfg.angles[:, 0]], cfg.angles[:, 1])
+    # one bead per lattice site
+    sites = np.round(cfg.pos / a - 0.5).astype(np.int64)
+    key = (sites[:, 0] * 80 + sites[:, 1]) * 50 + sites[:, 2]
+    assert np.unique(key).shape[0] == cfg.n

@@ -391,6 +391,84 @@ def test_fene_forces_sum_and_broken_count():
     assert f[0, 0] == pytest.approx(fr1 * 0.8, rel=1e-14)
 
 
+# ------------------------------------------------------ cosine angle term
+
+def test_angle_closed_forms():
+    K = 1.5
+    # straight triple: U = K (1 + cos pi) = 0, no force
+    u, fa, fc, ok = oracle.angle_triple([1.1, 0, 0], [-0.9, 0, 0], K)
+    assert ok and u == pytest.approx(0.0, abs=1e-15)
+    assert np.abs(fa).max() < 1e-15 and np.abs(fc).max() < 1e-15
+    # right angle, a on +x at r1 and c on +y at r2: U = K; -grad U opens the
+    # angle: F_a = -(K / r1) y, F_c = -(K / r2) x
+    r1, r2 = 1.2, 0.9
+    u, fa, fc, ok = oracle.angle_triple([r1, 0, 0], [0, r2, 0], K)
+    assert u == pytest.approx(K, rel=1e-15)
+    np.testing.assert_allclose(fa, [0.0, -K / r1, 0.0], rtol=1e-15, atol=1e-16)
+    np.testing.assert_allclose(fc, [-K / r2, 0.0, 0.0], rtol=1e-15, atol=1e-16)
+    # 120 degrees: cos = -1/2, U = K / 2; |F_a| = K sin(t) / r1
+    t = 2.0 * math.pi / 3.0
+    u, fa, fc, ok = oracle.angle_triple([r1, 0, 0], [r2 * math.cos(t), r2 * math.sin(t), 0], K)
+    assert u == pytest.approx(0.5 * K, rel=1e-14)
+    assert np.linalg.norm(fa) == pytest.approx(K * math.sin(t) / r1, rel=1e-14)
+    assert np.linalg.norm(fc) == pytest.approx(K * math.sin(t) / r2, rel=1e-14)
+    # folded onto itself: U = 2K, a stationary point (no force)
+    u, fa, fc, ok = oracle.angle_triple([1.0, 0, 0], [0.7, 0, 0], K)
+    assert u == pytest.approx(2.0 * K, rel=1e-15)
+    assert np.abs(fa).max() < 1e-15 and np.abs(fc).max() < 1e-15
+    # a zero-length bond vector is reported, not evaluated
+    assert not oracle.angle_triple([0, 0, 0], [1.0, 0, 0], K)[3]
+
+
+def test_angle_forces_are_minus_the_gradient_and_conserve_momentum():
+    rng = np.random.default_rng(11)
+    K, h = 1.5, 1e-6
+    for _ in range(20):
+        d1 = rng.normal(size=3)
+        d2 = rng.normal(size=3)
+        u, fa, fc, ok = oracle.angle_triple(d1, d2, K)
+        assert ok
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = h
+            # moving a shifts d1, moving c shifts d2; moving b shifts both
+            ga = (oracle.angle_triple(d1 + e, d2, K)[0] - oracle.angle_triple(d1 - e, d2, K)[0]) / (2 * h)
+            gc = (oracle.angle_triple(d1, d2 + e, K)[0] - oracle.angle_triple(d1, d2 - e, K)[0]) / (2 * h)
+            gb = (oracle.angle_triple(d1 - e, d2 - e, K)[0]
+                  - oracle.angle_triple(d1 + e, d2 + e, K)[0]) / (2 * h)
+            assert fa[k] == pytest.approx(-ga, abs=1e-8)
+            assert fc[k] == pytest.approx(-gc, abs=1e-8)
+            assert -(fa[k] + fc[k]) == pytest.approx(-gb, abs=1e-8)
+        # rotation invariance: no torque about the middle bead; the term is
+        # scale invariant, so its virial d1.F_a + d2.F_c vanishes
+        assert np.abs(np.cross(d1, fa) + np.cross(d2, fc)).max() < 1e-13
+        assert abs(d1 @ fa + d2 @ fc) < 1e-13
+
+
+def test_angle_forces_minimum_image_and_sums():
+    box = np.array([6.0, 7.0, 8.0])
+    rng = np.random.default_rng(12)
+    # three beads of a bent triple whose bonds cross the x and z faces
+    base = np.array([[5.6, 3.0, 7.7], [0.3, 3.4, 7.9], [0.6, 4.3, 0.5]])
+    tri = np.array([[0, 1, 2]])
+    f, e, w, bad = oracle.angle_forces(base, box, tri)
+    unwrapped = base + np.array([[0, 0, 0], [6.0, 0, 0], [6.0, 0, 8.0]])
+    d1, d2 = unwrapped[0] - unwrapped[1], unwrapped[2] - unwrapped[1]
+    u, fa, fc, _ = oracle.angle_triple(d1, d2)
+    assert bad == 0 and e == pytest.approx(u, rel=1e-14)
+    np.testing.assert_allclose(f[0], fa, rtol=1e-14)
+    np.testing.assert_allclose(f[2], fc, rtol=1e-14)
+    np.testing.assert_allclose(f[1], -(fa + fc), rtol=1e-14)
+    # a ring: total force zero, virial zero, energy = sum of the triples
+    cfg = md_inputs.lattice_rings((4, 8, 8), block=(2, 4, 4))
+    pos = cfg.pos + rng.normal(scale=0.05, size=cfg.pos.shape)
+    f, e, w, bad = oracle.angle_forces(pos, cfg.box[0], cfg.angles)
+    assert bad == 0
+    assert np.abs(f.sum(axis=0)).max() < 1e-12 and abs(w) < 1e-12
+    ref = sum(oracle.angle_triple(pos[a] - pos[b], pos[c] - pos[b])[0] for a, b, c in cfg.angles)
+    assert e == pytest.approx(ref, rel=1e-13)
+
+
 # ------------------------------------------- MD with bonds and a thermostat
 
 def test_md_run_ext_reduces_to_nve_run():
@@ -414,6 +492,29 @@ def test_bonded_nve_conserves_energy_with_dt_squared_error():
         fl.append(np.sqrt(np.mean((etot - etot.mean()) ** 2)))
         assert np.abs(r["vel"].sum(axis=0)).max() < 1e-10     # bonds conserve momentum
     assert 3.0 < fl[0] / fl[1] < 5.2
+
+
+def test_ring_melt_nve_conserves_energy_with_dt_squared_error():
+    # purely repulsive LJ + FENE + cosine angle term on rings, no thermostat
+    cfg = md_inputs.lattice_rings((4, 8, 8), block=(2, 4, 4), seed=9, temperature=1.0)
+    assert cfg.n == 256 and cfg.angles.shape == (256, 3)
+    fl = []
+    for dt, steps in ((0.004, 100), (0.002, 200)):
+        r = oracle.md_run_ext(cfg.pos, cfg.vel, cfg.box[0], cfg.rc, cfg.skin, dt, steps,
+                              bonds=cfg.bonds, angles=cfg.angles)
+        assert r["broken"] == 0
+        etot = r["epot"] + r["ekin"]
+        fl.append(np.sqrt(np.mean((etot - etot.mean()) ** 2)))
+        assert np.abs(r["vel"].sum(axis=0)).max() < 1e-10
+    assert 3.0 < fl[0] / fl[1] < 5.2
+    # the angle term is in the potential energy: it starts at K per corner
+    r0 = oracle.md_run_ext(cfg.pos, cfg.vel, cfg.box[0], cfg.rc, cfg.skin, 0.004, 0,
+                           bonds=cfg.bonds)
+    r1 = oracle.md_run_ext(cfg.pos, cfg.vel, cfg.box[0], cfg.rc, cfg.skin, 0.004, 0,
+                           bonds=cfg.bonds, angles=cfg.angles)
+    corners = sum(1 for a, b, c in cfg.angles
+                  if abs((cfg.pos[a] - cfg.pos[b]) @ (cfg.pos[c] - cfg.pos[b])) < 1e-9)
+    assert r1["epot"][0] - r0["epot"][0] == pytest.approx(1.5 * corners, rel=1e-12)
 
 
 def test_broken_bond_is_counted():
