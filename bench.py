@@ -196,7 +196,8 @@ def time_sections(s, step_ms, pair_ms, nsteps=200, nrep=10):
 
 def time_workload(name, steps, warmup=10):
     """Throughput of one of the other workloads (FP32-mixed, graphed steps):
-    the polymer melt (purely repulsive LJ + FENE + Langevin), the LJ slab
+    the polymer melts (purely repulsive LJ + FENE + Langevin: linear chains,
+    and the paper's rings with the cosine angle term), the LJ slab
     and the LJ sphere in vacuum (Langevin) and the batch of uneven replicas
     (NVE), plus, for the batch,
     one force + adjoint evaluation of a force-matching loss."""
@@ -205,15 +206,15 @@ def time_workload(name, steps, warmup=10):
     from paper_2109_10876_amd import MDSystem
     from paper_2109_10876_amd import autotune
     cfg = md_inputs.CONFIGS[name]()
-    lang = {"kg_melt": (0.5, 1.0, 3), "lj_slab": (1.0, 0.85, 4),
+    lang = {"kg_melt": (0.5, 1.0, 3), "ring_melt": (0.5, 1.0, 7), "lj_slab": (1.0, 0.85, 4),
             "lj_sphere": (1.0, 0.1, 6)}.get(name)
     ntypes = int(np.atleast_2d(np.asarray(cfg.eps)).shape[0])
 
     def make(mode="full", tile_cells=None, tile_rows=(1, 1)):
         return MDSystem(cfg.natoms, cfg.box, cfg.pos, cfg.vel, cfg.types, cfg.eps, cfg.sig,
                         cfg.mass, rc=cfg.rc, skin=cfg.skin, dt=cfg.dt, shift=cfg.shift,
-                        bonds=cfg.bonds, langevin=lang, prec="mixed", mode=mode,
-                        tile_cells=tile_cells, tile_rows=tile_rows)
+                        bonds=cfg.bonds, angles=cfg.angles, langevin=lang, prec="mixed",
+                        mode=mode, tile_cells=tile_cells, tile_rows=tile_rows)
     from paper_2109_10876_amd import _abi
     if ntypes <= _abi.MD_TILE_MAX_TYPES:
         # list form and launch shape from the autotuner (untimed)
@@ -435,7 +436,8 @@ def main():
     }
     if not args.no_other:
         other = {}
-        for name, steps in (("kg_melt", 300), ("lj_slab", 300), ("lj_sphere", 100),
+        for name, steps in (("kg_melt", 300), ("ring_melt", 300), ("lj_slab", 300),
+                            ("lj_sphere", 100),
                             ("replicas", 200)):
             log(f"[{name}] timing {steps} steps")
             try:

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 2
+#define MD_ABI_VERSION 3
 
 /* ------------------------------------------------------------ return codes */
 #define MD_OK            0
@@ -69,6 +69,7 @@ extern "C" {
 #define MD_MAX_ATOMS  0x03FFFFFF    /* total atoms per call                       */
 #define MD_MAX_TYPES  8             /* atom types                                 */
 #define MD_MAX_BONDS  4             /* bonds per atom                             */
+#define MD_MAX_ANGLES 8             /* angle triples an atom belongs to           */
 #define MD_TILE_SLOTS 3072          /* staged atoms per tile (MD_TILE_FULL)       */
 #define MD_TILE_MAX_CELLS 64        /* cells per tile along x                     */
 #define MD_TILE_MAX_ROWS  2         /* cell rows per tile along y and along z     */
@@ -194,6 +195,18 @@ typedef struct md_bonds {
     const int32_t *count;     /* [N] bonds of the atom with id a                  */
     const int32_t *partner;   /* [max_bonds * N] partner ids                      */
 } md_bonds;
+
+/* Angle triples (a, b, c), b the middle bead, stored once per member atom so
+ * that each atom can sum its own share: slot k (< count[a]) of the atom with
+ * id a names the triple (tri[(3k) N + a], tri[(3k+1) N + a],
+ * tri[(3k+2) N + a]) of atom ids, and the atom itself is one of the three.
+ * A triple names three distinct atoms. */
+typedef struct md_angles {
+    int32_t max_angles;       /* slots per atom, 1 .. MD_MAX_ANGLES                */
+    int32_t _pad;
+    const int32_t *count;     /* [N] triples of the atom with id a                 */
+    const int32_t *tri;       /* [3 * max_angles * N] member ids, by slot and role */
+} md_angles;
 
 /* ---------------------------------------------------------------- plumbing */
 
@@ -369,6 +382,22 @@ int md_lj_forces_vjp(const md_batch *b, const md_atoms *atoms, const md_nlist *n
 int md_fene_forces(const md_batch *b, const md_atoms *atoms, const md_bonds *bonds,
                    double K, double R0, double *energy, double *virial, void *ws,
                    size_t ws_bytes, uint32_t *status, void *stream);
+
+/* Cosine angle term of the ring-polymer melt (Sec. 4 of the paper: a cosine
+ * potential on the triples of consecutive beads): for a triple (a, b, c) with
+ * d1 = x_a - x_b, d2 = x_c - x_b (minimum image) and cos t = d1.d2/(|d1||d2|),
+ * U = K (1 + cos t), zero for a straight triple, and the forces are -grad U.
+ * Forces are ADDED to fx, fy, fz.  Needs atoms->where.  A triple with a
+ * zero-length bond vector contributes nothing and raises MD_F_NONFINITE.
+ * energy/virial ([R], optional) receive the angle energy and virial
+ * (d1.F_a + d2.F_c per triple, zero up to rounding: the term is scale
+ * invariant) per replica, reduced in a fixed order.  Each atom sums its own
+ * share of its triples: deterministic, no atomics.  MD_EINVAL for a missing
+ * pointer, max_angles outside 1 .. MD_MAX_ANGLES or K negative or not
+ * finite. */
+int md_angle_forces(const md_batch *b, const md_atoms *atoms, const md_angles *angles,
+                    double K, double *energy, double *virial, void *ws, size_t ws_bytes,
+                    uint32_t *status, void *stream);
 
 /* Langevin thermostat in force form (Sec. 4: particles equilibrated to a
  * target temperature T): F_i += -gamma m_i v_i + sqrt(2 gamma m_i T / dt) xi_i

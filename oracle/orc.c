@@ -644,7 +644,7 @@ EXPORT int64_t orc_md_run_ext(int32_t n, double *x, double *y, double *z, double
 {
     double *xb = malloc(sizeof(double) * n), *yb = malloc(sizeof(double) * n),
            *zb = malloc(sizeof(double) * n);
-    int32_t *ids = malloc(sizeof(int32_t) * n);
+    int32_t *ids = calloc((size_t)n + 1, sizeof(int32_t));
     if (!xb || !yb || !zb || !ids) { free(xb); free(yb); free(zb); free(ids); return -2; }
     for (int32_t i = 0; i < n; ++i) ids[i] = i;
     memcpy(xb, x, sizeof(double) * n);

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmd.so")
 
 # Constants mirrored from md.h.
-MD_ABI_VERSION = 2
+MD_ABI_VERSION = 3
 MD_OK = 0
 MD_EINVAL = -1
 MD_EBOX = -2
@@ -41,6 +41,7 @@ MD_IDX_MASK = 0x03FFFFFF
 MD_MAX_ATOMS = 0x03FFFFFF
 MD_MAX_TYPES = 8
 MD_MAX_BONDS = 4
+MD_MAX_ANGLES = 8
 MD_TUNE_PAIR_BATCH = 0
 MD_TUNE_TILE_THREADS = 1
 MD_TUNE_TILE_STAGE_PACKED = 2
@@ -52,7 +53,8 @@ EXPORTS = (
     "md_plan_fill",
     "md_tile_plan",
     "md_workspace_bytes", "md_cell_sort", "md_verlet_build", "md_lj_forces",
-    "md_vv_step", "md_lj_forces_vv", "md_lj_forces_vjp", "md_fene_forces", "md_langevin",
+    "md_vv_step", "md_lj_forces_vv", "md_lj_forces_vjp", "md_fene_forces", "md_angle_forces",
+    "md_langevin",
 )
 
 _vp = ctypes.c_void_p
@@ -85,6 +87,10 @@ class MdLj(ctypes.Structure):
 
 class MdBonds(ctypes.Structure):
     _fields_ = [("max_bonds", _i32), ("_pad", _i32), ("count", _vp), ("partner", _vp)]
+
+
+class MdAngles(ctypes.Structure):
+    _fields_ = [("max_angles", _i32), ("_pad", _i32), ("count", _vp), ("tri", _vp)]
 
 
 class MDError(RuntimeError):
@@ -156,6 +162,9 @@ def load():
     lib.md_fene_forces.restype = ctypes.c_int
     lib.md_fene_forces.argtypes = [P(MdBatch), P(MdAtoms), P(MdBonds), _dbl, _dbl, _vp, _vp,
                                    _vp, ctypes.c_size_t, _vp, _vp]
+    lib.md_angle_forces.restype = ctypes.c_int
+    lib.md_angle_forces.argtypes = [P(MdBatch), P(MdAtoms), P(MdAngles), _dbl, _vp, _vp, _vp,
+                                    ctypes.c_size_t, _vp, _vp]
     lib.md_langevin.restype = ctypes.c_int
     lib.md_langevin.argtypes = [P(MdBatch), P(MdAtoms), _vp, _i32, _dbl, _dbl, _dbl,
                                 ctypes.c_uint64, _vp, _vp, _vp]

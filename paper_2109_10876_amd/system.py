@@ -52,7 +52,8 @@ class MDSystem:
 
     def __init__(self, natoms, box, pos, vel, types=None, eps=1.0, sig=1.0, mass=None,
                  rc=2.5, skin=0.3, dt=0.005, shift=1, mode="full", prec="fp64",
-                 max_nbr=None, pos4=None, bonds=None, fene=(30.0, 1.5), langevin=None,
+                 max_nbr=None, pos4=None, bonds=None, fene=(30.0, 1.5), angles=None,
+                 angle_K=1.5, langevin=None,
                  tile_cells=None, tile_rows=(1, 1), fuse=True, device="cuda"):
         self.lib = abi.load()
         self.dev = torch.device(device)
@@ -195,6 +196,36 @@ class MDSystem:
             self.fene_K, self.fene_R0 = float(fene[0]), float(fene[1])
             self.energy_bond = torch.zeros(self.R, dtype=torch.float64, device=d)
             self.virial_bond = torch.zeros(self.R, dtype=torch.float64, device=d)
+        # ---- optional cosine angle terms (id triples [Na,3], middle bead second),
+        # each triple stored in the slot table of all three of its atoms
+        self.angles = None
+        if angles is not None and len(angles):
+            tri = np.asarray(angles, np.int64).reshape(-1, 3)
+            if tri.min() < 0 or tri.max() >= self.N:
+                raise ValueError("an angle triple names an atom outside the system")
+            if np.any((tri[:, 0] == tri[:, 1]) | (tri[:, 1] == tri[:, 2]) |
+                      (tri[:, 0] == tri[:, 2])):
+                raise ValueError("an angle triple names one atom twice")
+            owner = tri.T.ravel()                          # role-major: a's, b's, c's
+            which = np.tile(np.arange(tri.shape[0]), 3)
+            order = np.lexsort((which, owner))             # by atom, then by triple
+            owner, which = owner[order], which[order]
+            cnt = np.bincount(owner, minlength=self.N).astype(np.int32)
+            if cnt.max() > abi.MD_MAX_ANGLES:
+                raise ValueError(f"an atom belongs to more than {abi.MD_MAX_ANGLES} triples")
+            ma = max(1, int(cnt.max()))
+            start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+            slot = np.arange(owner.shape[0]) - start[owner]
+            table = np.full((ma, 3, self.N), -1, np.int32)
+            for r in range(3):
+                table[slot, r, owner] = tri[which, r]
+            self.angle_count = i32(cnt)
+            self.angle_tri = i32(np.ascontiguousarray(table.reshape(3 * ma, self.N)))
+            self.angles = abi.MdAngles(ma, 0, self.angle_count.data_ptr(),
+                                       self.angle_tri.data_ptr())
+            self.angle_K = float(angle_K)
+            self.energy_angle = torch.zeros(self.R, dtype=torch.float64, device=d)
+            self.virial_angle = torch.zeros(self.R, dtype=torch.float64, device=d)
         self.langevin_cfg = None
         if langevin is not None:
             gamma, temp, seed = langevin[:3]
@@ -205,6 +236,7 @@ class MDSystem:
         # pure pair forces on tile lists: the force call also advances the
         # step (md_lj_forces_vv); bonds or a thermostat need the split calls
         self.fuse = bool(fuse) and self.mode == abi.MD_TILE_FULL and self.bonds is None \
+            and self.angles is None \
             and self.langevin_cfg is None and self.ntypes == 1
         if self.fuse and self.pos4 is None:
             self._pos.append((z64(), z64(), z64()))
@@ -326,6 +358,12 @@ class MDSystem:
             self.fene_K, self.fene_R0, _ptr(self.energy_bond), _ptr(self.virial_bond),
             _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
 
+    def angle(self):
+        check("md_angle_forces", self.lib.md_angle_forces(
+            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.angles),
+            self.angle_K, _ptr(self.energy_angle), _ptr(self.virial_angle),
+            _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
+
     def langevin(self):
         gamma, temp, seed = self.langevin_cfg
         check("md_langevin", self.lib.md_langevin(
@@ -334,10 +372,13 @@ class MDSystem:
             self.stream))
 
     def all_forces(self):
-        """Pair forces, then (if configured) bond forces and the thermostat."""
+        """Pair forces, then (if configured) bond and angle forces and the
+        thermostat."""
         self.forces()
         if self.bonds is not None:
             self.fene()
+        if self.angles is not None:
+            self.angle()
         if self.langevin_cfg is not None:
             self.langevin()
 

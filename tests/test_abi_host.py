@@ -162,6 +162,29 @@ def test_calls_reject_bad_arguments_without_a_gpu():
     assert lib.md_vv_step(P(ok), P(full), 4, 0.005, 8, 1, 0.3, 8, None, 8, 1 << 30, None, None) == abi.MD_EINVAL
 
 
+def test_angle_forces_reject_bad_arguments_without_a_gpu():
+    lib = abi.load()
+    P = ctypes.byref
+    ok = abi.MdBatch(1, 1000, 27, 4, 8, 8, 8, 8, 8, 8)
+    full = abi.MdAtoms(*([8] * 17))
+    ang = abi.MdAngles(3, 0, 8, 8)
+    big = 1 << 30
+    assert lib.md_angle_forces(P(abi.MdBatch()), P(full), P(ang), 1.5, None, None, 8, big,
+                               None, None) == abi.MD_EINVAL
+    assert lib.md_angle_forces(P(ok), P(full), None, 1.5, None, None, 8, big,
+                               None, None) == abi.MD_EINVAL
+    for m in (0, abi.MD_MAX_ANGLES + 1):
+        assert lib.md_angle_forces(P(ok), P(full), P(abi.MdAngles(m, 0, 8, 8)), 1.5, None, None,
+                                   8, big, None, None) == abi.MD_EINVAL
+    assert lib.md_angle_forces(P(ok), P(full), P(abi.MdAngles(3, 0, 8, None)), 1.5, None, None,
+                               8, big, None, None) == abi.MD_EINVAL
+    for K in (-1.0, float("inf"), float("nan")):
+        assert lib.md_angle_forces(P(ok), P(full), P(ang), K, None, None, 8, big,
+                                   None, None) == abi.MD_EINVAL
+    assert lib.md_angle_forces(P(ok), P(full), P(ang), 1.5, None, None, 8, 16,
+                               None, None) == abi.MD_ENOWS
+
+
 def test_kernel_timing_arguments_and_empty_read():
     # no launch is timed on the host: start and an empty read touch no GPU
     import ctypes
