@@ -375,7 +375,8 @@ int md_lj_forces_vjp(const md_batch *b, const md_atoms *atoms, const md_nlist *n
  * Kremer and Grest): U(r) = -(1/2) K R0^2 ln(1 - r^2/R0^2) with force factor
  * fr = -K / (1 - r^2/R0^2), minimum-image bond vector.  Forces are ADDED to
  * fx, fy, fz (call after md_lj_forces).  Needs atoms->where (id -> current
- * index, kept by md_cell_sort).  A bond with r >= R0 contributes nothing and
+ * index, kept by md_cell_sort), and the ids of replica r must be the range
+ * [atom_off[r], atom_off[r+1]) (the work is spread over ids).  A bond with r >= R0 contributes nothing and
  * raises MD_F_BOND_BROKEN.  energy/virial ([R], optional) receive the bond
  * energy and virial per replica, reduced in a fixed order.  Each atom sums
  * its own bonds: deterministic, no atomics. */
@@ -387,7 +388,9 @@ int md_fene_forces(const md_batch *b, const md_atoms *atoms, const md_bonds *bon
  * potential on the triples of consecutive beads): for a triple (a, b, c) with
  * d1 = x_a - x_b, d2 = x_c - x_b (minimum image) and cos t = d1.d2/(|d1||d2|),
  * U = K (1 + cos t), zero for a straight triple, and the forces are -grad U.
- * Forces are ADDED to fx, fy, fz.  Needs atoms->where.  A triple with a
+ * Forces are ADDED to fx, fy, fz.  Needs atoms->where, and the ids of
+ * replica r must be the range [atom_off[r], atom_off[r+1]), as for
+ * md_fene_forces.  A triple with a
  * zero-length bond vector contributes nothing and raises MD_F_NONFINITE.
  * energy/virial ([R], optional) receive the angle energy and virial
  * (d1.F_a + d2.F_c per triple, zero up to rounding: the term is scale

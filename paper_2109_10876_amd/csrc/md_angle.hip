@@ -7,11 +7,14 @@
 // triple) and its forces, -grad U, are
 //     F_a = -K (d2 / (r1 r2) - cos t d1 / r1^2),
 //     F_c = -K (d1 / (r1 r2) - cos t d2 / r2^2),   F_b = -F_a - F_c.
-// One thread per atom walks the triples its atom belongs to (indexed by the
-// stable id, partners found through where[id]) and keeps the force on its
-// own bead only, so no two threads write one atom: deterministic, no
-// atomics.  The middle bead's thread adds the triple's energy and virial
-// (d1.F_a + d2.F_c), so each triple is counted once.
+// One thread per atom id walks the triples that atom belongs to and keeps
+// the force on its own bead only, so no two threads write one atom:
+// deterministic, no atomics.  Threads run in id order, not in the current
+// (cell-sorted) order: the id-indexed triple table is then read coalesced,
+// and the beads of a chain, consecutive ids, sit in nearby cells, so the
+// position gathers of a wave stay local too.  The middle bead's thread adds
+// the triple's energy and virial (d1.F_a + d2.F_c), so each triple is
+// counted once.
 #include <cmath>
 
 #include "md_common.hpp"
@@ -23,7 +26,7 @@ struct AngleArgs {
     const int32_t *atom_off, *unit_rep, *unit_off;
     const double *box;
     const double *x, *y, *z;
-    const int32_t *id, *where;
+    const int32_t *where;
     const int32_t *acount, *tri;
     int32_t N, max_angles;
     double K;
@@ -37,11 +40,11 @@ __global__ __launch_bounds__(kUnit) void k_angle(AngleArgs a)
     __shared__ double red[kWavesPerUnit];
     const int u = blockIdx.x;
     const Unit w = unit_of(u, a.unit_rep, a.unit_off, a.atom_off);
-    const int i = w.begin + threadIdx.x;
+    const int me = w.begin + threadIdx.x;   // atom id; ids of a replica span its range
     double e = 0.0, vir = 0.0;
-    if (i < w.end) {
+    if (me < w.end) {
         const double Lx = a.box[3 * w.rep], Ly = a.box[3 * w.rep + 1], Lz = a.box[3 * w.rep + 2];
-        const int me = a.id[i];
+        const int i = a.where[me];
         const int nt = min(a.acount[me], a.max_angles);
         double fx = 0.0, fy = 0.0, fz = 0.0;
         bool bad = false;
@@ -113,7 +116,7 @@ extern "C" int md_angle_forces(const md_batch *b, const md_atoms *atoms, const m
     int e = check_batch(b);
     if (e != MD_OK) return e;
     if (!atoms || !atoms->x || !atoms->y || !atoms->z || !atoms->fx || !atoms->fy ||
-        !atoms->fz || !atoms->id || !atoms->where || !angles || !angles->count ||
+        !atoms->fz || !atoms->where || !angles || !angles->count ||
         !angles->tri || !ws)
         return MD_EINVAL;
     if (angles->max_angles < 1 || angles->max_angles > MD_MAX_ANGLES) return MD_EINVAL;
@@ -122,7 +125,7 @@ extern "C" int md_angle_forces(const md_batch *b, const md_atoms *atoms, const m
     if (ws_bytes < l.total) return MD_ENOWS;
     double *partial = ws_at<double>(ws, l.partial);
     AngleArgs a{b->atom_off, b->unit_rep, b->unit_off, b->box, atoms->x, atoms->y, atoms->z,
-                atoms->id, atoms->where, angles->count, angles->tri, b->N,
+                atoms->where, angles->count, angles->tri, b->N,
                 angles->max_angles, K, atoms->fx, atoms->fy, atoms->fz, partial, status};
     hipStream_t s = as_stream(stream);
     hipLaunchKernelGGL(k_angle, dim3(b->n_units), dim3(kUnit), 0, s, a);
