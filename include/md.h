@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 3
+#define MD_ABI_VERSION 4
 
 /* ------------------------------------------------------------ return codes */
 #define MD_OK            0
@@ -58,6 +58,8 @@ extern "C" {
 #define MD_HALF 0         /* each unordered pair stored once (Newton's third law) */
 #define MD_FULL 1         /* each pair stored for both atoms                      */
 #define MD_TILE_FULL 2    /* full list in tile-local form (see "Tile-local lists")  */
+#define MD_BY_ID 0        /* bonded table keyed by atom id, naming atom ids        */
+#define MD_BY_INDEX 1     /* bonded table keyed by current index, naming indices   */
 #define MD_FP64 0         /* all pair arithmetic in double precision              */
 #define MD_FP32_MIXED 1   /* distances, cutoff test and force accumulation in
                              double; reciprocal and LJ polynomial in single     */
@@ -189,23 +191,28 @@ typedef struct md_lj {
 /* Bonds, indexed by original atom id (stable across re-sorts): partner k of
  * the atom whose id is a is partner[k * N + a] (an id), k < count[a].  Each
  * bond is listed for both of its atoms. */
+/* Bonds, stored for both of their atoms.  With order MD_BY_ID, column a
+ * belongs to the atom with id a and partner entries are atom ids in [0, N);
+ * with MD_BY_INDEX (written by md_bonded_reindex), column i belongs to the
+ * atom now at index i and entries are current indices, valid until the next
+ * md_cell_sort moves atoms. */
 typedef struct md_bonds {
     int32_t max_bonds;        /* columns of partner, 1 .. MD_MAX_BONDS            */
-    int32_t _pad;
-    const int32_t *count;     /* [N] bonds of the atom with id a                  */
-    const int32_t *partner;   /* [max_bonds * N] partner ids                      */
+    int32_t order;            /* MD_BY_ID or MD_BY_INDEX                          */
+    const int32_t *count;     /* [N] bonds of atom a                              */
+    const int32_t *partner;   /* [max_bonds * N] partners, slot k at k N + a      */
 } md_bonds;
 
 /* Angle triples (a, b, c), b the middle bead, stored once per member atom so
- * that each atom can sum its own share: slot k (< count[a]) of the atom with
- * id a names the triple (tri[(3k) N + a], tri[(3k+1) N + a],
- * tri[(3k+2) N + a]) of atom ids, and the atom itself is one of the three.
- * A triple names three distinct atoms. */
+ * that each atom can sum its own share: slot k (< count[a]) of atom a names
+ * the triple (tri[(3k) N + a], tri[(3k+1) N + a], tri[(3k+2) N + a]), and
+ * atom a is one of the three.  A triple names three distinct atoms.  Keys and
+ * entries are ids or current indices as for md_bonds. */
 typedef struct md_angles {
     int32_t max_angles;       /* slots per atom, 1 .. MD_MAX_ANGLES                */
-    int32_t _pad;
-    const int32_t *count;     /* [N] triples of the atom with id a                 */
-    const int32_t *tri;       /* [3 * max_angles * N] member ids, by slot and role */
+    int32_t order;            /* MD_BY_ID or MD_BY_INDEX                           */
+    const int32_t *count;     /* [N] triples of atom a                             */
+    const int32_t *tri;       /* [3 * max_angles * N] members, by slot and role    */
 } md_angles;
 
 /* ---------------------------------------------------------------- plumbing */
@@ -374,12 +381,12 @@ int md_lj_forces_vjp(const md_batch *b, const md_atoms *atoms, const md_nlist *n
 /* FENE bonds of the bead-spring polymer melt (Sec. 4 of the paper, after
  * Kremer and Grest): U(r) = -(1/2) K R0^2 ln(1 - r^2/R0^2) with force factor
  * fr = -K / (1 - r^2/R0^2), minimum-image bond vector.  Forces are ADDED to
- * fx, fy, fz (call after md_lj_forces).  Needs atoms->where (id -> current
- * index, kept by md_cell_sort), and the ids of replica r must be the range
- * [atom_off[r], atom_off[r+1]) (the work is spread over ids).  A bond with r >= R0 contributes nothing and
- * raises MD_F_BOND_BROKEN.  energy/virial ([R], optional) receive the bond
- * energy and virial per replica, reduced in a fixed order.  Each atom sums
- * its own bonds: deterministic, no atomics. */
+ * fx, fy, fz (call after md_lj_forces).  A table keyed by id needs
+ * atoms->where (id -> current index, kept by md_cell_sort); a table keyed by
+ * index (md_bonded_reindex) is read in the atoms' own order.  A bond with
+ * r >= R0 contributes nothing and raises MD_F_BOND_BROKEN.  energy/virial
+ * ([R], optional) receive the bond energy and virial per replica, reduced in
+ * a fixed order.  Each atom sums its own bonds: deterministic, no atomics. */
 int md_fene_forces(const md_batch *b, const md_atoms *atoms, const md_bonds *bonds,
                    double K, double R0, double *energy, double *virial, void *ws,
                    size_t ws_bytes, uint32_t *status, void *stream);
@@ -388,19 +395,38 @@ int md_fene_forces(const md_batch *b, const md_atoms *atoms, const md_bonds *bon
  * potential on the triples of consecutive beads): for a triple (a, b, c) with
  * d1 = x_a - x_b, d2 = x_c - x_b (minimum image) and cos t = d1.d2/(|d1||d2|),
  * U = K (1 + cos t), zero for a straight triple, and the forces are -grad U.
- * Forces are ADDED to fx, fy, fz.  Needs atoms->where, and the ids of
- * replica r must be the range [atom_off[r], atom_off[r+1]), as for
- * md_fene_forces.  A triple with a
+ * Forces are ADDED to fx, fy, fz.  A table keyed by id needs atoms->where,
+ * and the ids of replica r must then be the range [atom_off[r],
+ * atom_off[r+1]) (that work is spread over ids); a table keyed by index
+ * (md_bonded_reindex) is read in the atoms' own order.  A triple with a
  * zero-length bond vector contributes nothing and raises MD_F_NONFINITE.
  * energy/virial ([R], optional) receive the angle energy and virial
  * (d1.F_a + d2.F_c per triple, zero up to rounding: the term is scale
  * invariant) per replica, reduced in a fixed order.  Each atom sums its own
  * share of its triples: deterministic, no atomics.  MD_EINVAL for a missing
- * pointer, max_angles outside 1 .. MD_MAX_ANGLES or K negative or not
- * finite. */
+ * pointer, max_angles outside 1 .. MD_MAX_ANGLES, an unknown order or K
+ * negative or not finite. */
 int md_angle_forces(const md_batch *b, const md_atoms *atoms, const md_angles *angles,
                     double K, double *energy, double *virial, void *ws, size_t ws_bytes,
                     uint32_t *status, void *stream);
+
+/* Bonded tables in the atoms' current (cell-sorted) order: for every atom
+ * at index i of a replica whose gate is set (every replica when gate is
+ * NULL; pass md_cell_sort's gate), copies the MD_BY_ID tables' column id[i]
+ * into column i of the outputs, with every member id translated to its
+ * current index through atoms->where.  Unused slots are set to -1.  The
+ * outputs then form MD_BY_INDEX tables of the same max_bonds / max_angles for
+ * md_fene_forces and md_angle_forces, which read them coalesced and gather
+ * positions from nearby cells.  Call after each md_cell_sort that moved
+ * atoms.  bonds or angles may be NULL (their outputs are then not touched);
+ * outputs: bond_count [N], bond_partner [max_bonds N], angle_count [N],
+ * angle_tri [3 max_angles N].  Member ids must lie in [0, N).  MD_EINVAL for
+ * an input table not keyed by id, a missing output or atoms->id/where, or a
+ * slot count out of range. */
+int md_bonded_reindex(const md_batch *b, const md_atoms *atoms, const md_bonds *bonds,
+                      int32_t *bond_count, int32_t *bond_partner, const md_angles *angles,
+                      int32_t *angle_count, int32_t *angle_tri, const uint32_t *gate,
+                      void *stream);
 
 /* Langevin thermostat in force form (Sec. 4: particles equilibrated to a
  * target temperature T): F_i += -gamma m_i v_i + sqrt(2 gamma m_i T / dt) xi_i

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmd.so")
 
 # Constants mirrored from md.h.
-MD_ABI_VERSION = 3
+MD_ABI_VERSION = 4
 MD_OK = 0
 MD_EINVAL = -1
 MD_EBOX = -2
@@ -29,6 +29,8 @@ MD_F_TILE_OVERFLOW = 0x8
 MD_HALF = 0
 MD_FULL = 1
 MD_TILE_FULL = 2
+MD_BY_ID = 0
+MD_BY_INDEX = 1
 MD_TILE_SLOTS = 3072
 MD_TILE_MAX_CELLS = 64
 MD_TILE_MAX_ROWS = 2
@@ -54,7 +56,7 @@ EXPORTS = (
     "md_tile_plan",
     "md_workspace_bytes", "md_cell_sort", "md_verlet_build", "md_lj_forces",
     "md_vv_step", "md_lj_forces_vv", "md_lj_forces_vjp", "md_fene_forces", "md_angle_forces",
-    "md_langevin",
+    "md_bonded_reindex", "md_langevin",
 )
 
 _vp = ctypes.c_void_p
@@ -86,11 +88,11 @@ class MdLj(ctypes.Structure):
 
 
 class MdBonds(ctypes.Structure):
-    _fields_ = [("max_bonds", _i32), ("_pad", _i32), ("count", _vp), ("partner", _vp)]
+    _fields_ = [("max_bonds", _i32), ("order", _i32), ("count", _vp), ("partner", _vp)]
 
 
 class MdAngles(ctypes.Structure):
-    _fields_ = [("max_angles", _i32), ("_pad", _i32), ("count", _vp), ("tri", _vp)]
+    _fields_ = [("max_angles", _i32), ("order", _i32), ("count", _vp), ("tri", _vp)]
 
 
 class MDError(RuntimeError):
@@ -165,6 +167,9 @@ def load():
     lib.md_angle_forces.restype = ctypes.c_int
     lib.md_angle_forces.argtypes = [P(MdBatch), P(MdAtoms), P(MdAngles), _dbl, _vp, _vp, _vp,
                                     ctypes.c_size_t, _vp, _vp]
+    lib.md_bonded_reindex.restype = ctypes.c_int
+    lib.md_bonded_reindex.argtypes = [P(MdBatch), P(MdAtoms), P(MdBonds), _vp, _vp, P(MdAngles),
+                                      _vp, _vp, _vp, _vp]
     lib.md_langevin.restype = ctypes.c_int
     lib.md_langevin.argtypes = [P(MdBatch), P(MdAtoms), _vp, _i32, _dbl, _dbl, _dbl,
                                 ctypes.c_uint64, _vp, _vp, _vp]

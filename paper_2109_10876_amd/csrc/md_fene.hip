@@ -3,9 +3,12 @@
 // The paper's polymer melt (Sec. 4) bonds consecutive monomers with the FENE
 // potential U = -(1/2) K R0^2 ln(1 - r^2/R0^2); the force on i from its
 // partner j is fr d with fr = -K / (1 - r^2/R0^2), d = x_i - x_j (minimum
-// image).  One thread per atom walks its own bond row (bonds are indexed by
-// the stable atom id, partners found through where[id]); each bond is seen
+// image).  One thread per atom walks its own bond row; each bond is seen
 // from both of its atoms, so energy and virial are halved.  No atomics.
+// Threads run in the atoms' current (cell-sorted) order.  A table keyed by
+// id is reached through id[i] and names partners by id (found through
+// where[]); a table keyed by index (md_bonded_reindex) is read coalesced and
+// names the partners' indices directly.
 #include "md_common.hpp"
 
 namespace md {
@@ -15,7 +18,7 @@ struct FeneArgs {
     const int32_t *atom_off, *unit_rep, *unit_off;
     const double *box;
     const double *x, *y, *z;
-    const int32_t *id, *where;
+    const int32_t *id, *where;   // used for tables keyed by id
     const int32_t *bcount, *bpartner;
     int32_t N, max_bonds;
     double K, R02;
@@ -24,6 +27,7 @@ struct FeneArgs {
     uint32_t *status;
 };
 
+template <int ORDER>
 __global__ __launch_bounds__(kUnit) void k_fene(FeneArgs a)
 {
     __shared__ double red[kWavesPerUnit];
@@ -33,17 +37,22 @@ __global__ __launch_bounds__(kUnit) void k_fene(FeneArgs a)
     double e = 0.0, vir = 0.0;
     if (i < w.end) {
         const double Lx = a.box[3 * w.rep], Ly = a.box[3 * w.rep + 1], Lz = a.box[3 * w.rep + 2];
+        // d/L through the reciprocal rounds to the same image as the
+        // division except within rounding of |d| = L/2, where the image is
+        // ambiguous anyway
+        const double ix = 1.0 / Lx, iy = 1.0 / Ly, iz = 1.0 / Lz;
         const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
-        const int me = a.id[i];
+        const int me = ORDER == MD_BY_ID ? a.id[i] : i;   // column of the table
         const int nb = min(a.bcount[me], a.max_bonds);
         double fx = 0.0, fy = 0.0, fz = 0.0;
         bool broken = false;
         for (int k = 0; k < nb; ++k) {
-            const int j = a.where[a.bpartner[size_t(k) * a.N + me]];
+            const int p = a.bpartner[size_t(k) * a.N + me];
+            const int j = ORDER == MD_BY_ID ? a.where[p] : p;
             double dx = xi - a.x[j], dy = yi - a.y[j], dz = zi - a.z[j];
-            dx -= Lx * rint(dx / Lx);
-            dy -= Ly * rint(dy / Ly);
-            dz -= Lz * rint(dz / Lz);
+            dx -= Lx * rint(dx * ix);
+            dy -= Ly * rint(dy * iy);
+            dz -= Lz * rint(dz * iz);
             const double r2 = dx * dx + dy * dy + dz * dz;
             const double q = 1.0 - r2 / a.R02;
             if (!(q > 0.0)) {
@@ -81,9 +90,10 @@ extern "C" int md_fene_forces(const md_batch *b, const md_atoms *atoms, const md
     int e = check_batch(b);
     if (e != MD_OK) return e;
     if (!atoms || !atoms->x || !atoms->y || !atoms->z || !atoms->fx || !atoms->fy ||
-        !atoms->fz || !atoms->id || !atoms->where || !bonds || !bonds->count ||
-        !bonds->partner || !ws)
+        !atoms->fz || !bonds || !bonds->count || !bonds->partner || !ws)
         return MD_EINVAL;
+    if (bonds->order != MD_BY_ID && bonds->order != MD_BY_INDEX) return MD_EINVAL;
+    if (bonds->order == MD_BY_ID && (!atoms->id || !atoms->where)) return MD_EINVAL;
     if (bonds->max_bonds < 1 || bonds->max_bonds > MD_MAX_BONDS) return MD_EINVAL;
     if (!(K >= 0.0) || !(R0 > 0.0)) return MD_EINVAL;
     const WsLayout l = ws_layout(b);
@@ -93,7 +103,10 @@ extern "C" int md_fene_forces(const md_batch *b, const md_atoms *atoms, const md
                atoms->id, atoms->where, bonds->count, bonds->partner, b->N, bonds->max_bonds,
                K, R0 * R0, atoms->fx, atoms->fy, atoms->fz, partial, status};
     hipStream_t s = as_stream(stream);
-    hipLaunchKernelGGL(k_fene, dim3(b->n_units), dim3(kUnit), 0, s, a);
+    if (bonds->order == MD_BY_ID)
+        hipLaunchKernelGGL(k_fene<MD_BY_ID>, dim3(b->n_units), dim3(kUnit), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_fene<MD_BY_INDEX>, dim3(b->n_units), dim3(kUnit), 0, s, a);
     if (energy || virial) launch_finalize_sum2(b->R, b->unit_off, partial, 0, energy, virial, s);
     return launch_status();
 }

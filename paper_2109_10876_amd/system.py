@@ -53,7 +53,7 @@ class MDSystem:
     def __init__(self, natoms, box, pos, vel, types=None, eps=1.0, sig=1.0, mass=None,
                  rc=2.5, skin=0.3, dt=0.005, shift=1, mode="full", prec="fp64",
                  max_nbr=None, pos4=None, bonds=None, fene=(30.0, 1.5), angles=None,
-                 angle_K=1.5, langevin=None,
+                 angle_K=1.5, bonded_order="index", langevin=None,
                  tile_cells=None, tile_rows=(1, 1), fuse=True, device="cuda"):
         self.lib = abi.load()
         self.dev = torch.device(device)
@@ -178,6 +178,8 @@ class MDSystem:
         self.bonds = None
         if bonds is not None and len(bonds):
             bonds = np.asarray(bonds, np.int64).reshape(-1, 2)
+            if bonds.min() < 0 or bonds.max() >= self.N:
+                raise ValueError("a bond names an atom outside the system")
             u_ = np.concatenate([bonds[:, 0], bonds[:, 1]])
             v_ = np.concatenate([bonds[:, 1], bonds[:, 0]])
             order = np.argsort(u_, kind="stable")
@@ -191,7 +193,7 @@ class MDSystem:
             mb = max(1, int(cnt.max()))
             self.bond_count = i32(cnt)
             self.bond_partner = i32(np.ascontiguousarray(part[:mb]))
-            self.bonds = abi.MdBonds(mb, 0, self.bond_count.data_ptr(),
+            self.bonds = abi.MdBonds(mb, abi.MD_BY_ID, self.bond_count.data_ptr(),
                                      self.bond_partner.data_ptr())
             self.fene_K, self.fene_R0 = float(fene[0]), float(fene[1])
             self.energy_bond = torch.zeros(self.R, dtype=torch.float64, device=d)
@@ -221,11 +223,29 @@ class MDSystem:
                 table[slot, r, owner] = tri[which, r]
             self.angle_count = i32(cnt)
             self.angle_tri = i32(np.ascontiguousarray(table.reshape(3 * ma, self.N)))
-            self.angles = abi.MdAngles(ma, 0, self.angle_count.data_ptr(),
+            self.angles = abi.MdAngles(ma, abi.MD_BY_ID, self.angle_count.data_ptr(),
                                        self.angle_tri.data_ptr())
             self.angle_K = float(angle_K)
             self.energy_angle = torch.zeros(self.R, dtype=torch.float64, device=d)
             self.virial_angle = torch.zeros(self.R, dtype=torch.float64, device=d)
+        # ---- the bonded tables the kernels read: keyed by id as given, or
+        # (default) re-keyed to the cell-sorted order after every re-sort
+        if bonded_order not in ("index", "id"):
+            raise ValueError("bonded_order is 'index' or 'id'")
+        self.bonded_by_index = bonded_order == "index"
+        self._bonds_k, self._angles_k = self.bonds, self.angles
+        if self.bonded_by_index and self.bonds is not None:
+            self.bond_count_ix = torch.zeros_like(self.bond_count)
+            self.bond_partner_ix = torch.zeros_like(self.bond_partner)
+            self._bonds_k = abi.MdBonds(self.bonds.max_bonds, abi.MD_BY_INDEX,
+                                        self.bond_count_ix.data_ptr(),
+                                        self.bond_partner_ix.data_ptr())
+        if self.bonded_by_index and self.angles is not None:
+            self.angle_count_ix = torch.zeros_like(self.angle_count)
+            self.angle_tri_ix = torch.zeros_like(self.angle_tri)
+            self._angles_k = abi.MdAngles(self.angles.max_angles, abi.MD_BY_INDEX,
+                                          self.angle_count_ix.data_ptr(),
+                                          self.angle_tri_ix.data_ptr())
         self.langevin_cfg = None
         if langevin is not None:
             gamma, temp, seed = langevin[:3]
@@ -312,6 +332,16 @@ class MDSystem:
             ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.scratch),
             _ptr(self.cell_start), _ptr(self.ws), self.ws_bytes,
             _ptr(self.gate) if gated else None, _ptr(self.status), self.stream))
+        if self.bonded_by_index and (self.bonds is not None or self.angles is not None):
+            check("md_bonded_reindex", self.lib.md_bonded_reindex(
+                ctypes.byref(self.batch), ctypes.byref(self.atoms),
+                ctypes.byref(self.bonds) if self.bonds is not None else None,
+                _ptr(getattr(self, "bond_count_ix", None)),
+                _ptr(getattr(self, "bond_partner_ix", None)),
+                ctypes.byref(self.angles) if self.angles is not None else None,
+                _ptr(getattr(self, "angle_count_ix", None)),
+                _ptr(getattr(self, "angle_tri_ix", None)),
+                _ptr(self.gate) if gated else None, self.stream))
 
     def build(self, gated=True):
         check("md_verlet_build", self.lib.md_verlet_build(
@@ -354,13 +384,13 @@ class MDSystem:
 
     def fene(self):
         check("md_fene_forces", self.lib.md_fene_forces(
-            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.bonds),
+            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self._bonds_k),
             self.fene_K, self.fene_R0, _ptr(self.energy_bond), _ptr(self.virial_bond),
             _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
 
     def angle(self):
         check("md_angle_forces", self.lib.md_angle_forces(
-            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.angles),
+            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self._angles_k),
             self.angle_K, _ptr(self.energy_angle), _ptr(self.virial_angle),
             _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
 

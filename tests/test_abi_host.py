@@ -37,7 +37,8 @@ def test_header_constants_match_binding():
                  "MD_UNIT_ATOMS", "MD_IDX_BITS", "MD_MAX_TYPES", "MD_TILE_FULL",
                  "MD_TILE_SLOTS", "MD_TILE_MAX_CELLS", "MD_TILE_MAX_ROWS", "MD_TILE_MAX_TYPES",
                  "MD_TUNE_PAIR_BATCH", "MD_TUNE_TILE_THREADS", "MD_TUNE_TILE_STAGE_PACKED",
-                 "MD_TUNE_TILE_SLOTS"):
+                 "MD_TUNE_TILE_SLOTS", "MD_MAX_BONDS", "MD_MAX_ANGLES", "MD_BY_ID",
+                 "MD_BY_INDEX"):
         m = re.search(rf"#define\s+{name}\s+(-?\w+)", src)
         assert m, name
         assert int(m.group(1), 0) == getattr(abi, name), name
@@ -238,3 +239,47 @@ def test_fused_step_next_position_buffers_are_checked():
     assert call(atoms, X + 8 * 500, far, far + (1 << 20)) == abi.MD_EINVAL   # overlaps x
     assert call(atoms, far, far + (1 << 20), Z) == abi.MD_EINVAL     # overlaps z
     assert call(packed, far, far + (1 << 20), far + (2 << 20)) == abi.MD_EINVAL  # pos4 set
+
+
+def test_bonded_tables_check_their_order_without_a_gpu():
+    lib = abi.load()
+    P = ctypes.byref
+    ok = abi.MdBatch(1, 1000, 27, 4, 8, 8, 8, 8, 8, 8)
+    full = abi.MdAtoms(*([8] * 17))
+    big = 1 << 30
+    for order in (-1, 2):
+        assert lib.md_fene_forces(P(ok), P(full), P(abi.MdBonds(2, order, 8, 8)), 30.0, 1.5,
+                                  None, None, 8, big, None, None) == abi.MD_EINVAL
+        assert lib.md_angle_forces(P(ok), P(full), P(abi.MdAngles(3, order, 8, 8)), 1.5, None,
+                                   None, 8, big, None, None) == abi.MD_EINVAL
+    # tables keyed by id need where[]; keyed by index they do not (short
+    # workspace reached instead, before any launch)
+    nowhere = abi.MdAtoms(*([8] * 15), None, 8)
+    assert lib.md_fene_forces(P(ok), P(nowhere), P(abi.MdBonds(2, abi.MD_BY_ID, 8, 8)), 30.0,
+                              1.5, None, None, 8, big, None, None) == abi.MD_EINVAL
+    assert lib.md_fene_forces(P(ok), P(nowhere), P(abi.MdBonds(2, abi.MD_BY_INDEX, 8, 8)), 30.0,
+                              1.5, None, None, 8, 16, None, None) == abi.MD_ENOWS
+    assert lib.md_angle_forces(P(ok), P(nowhere), P(abi.MdAngles(3, abi.MD_BY_ID, 8, 8)), 1.5,
+                               None, None, 8, big, None, None) == abi.MD_EINVAL
+    assert lib.md_angle_forces(P(ok), P(nowhere), P(abi.MdAngles(3, abi.MD_BY_INDEX, 8, 8)), 1.5,
+                               None, None, 8, 16, None, None) == abi.MD_ENOWS
+    # the re-index pass: inputs keyed by id, outputs present, counts in range
+    bid = abi.MdBonds(2, abi.MD_BY_ID, 8, 8)
+    aid = abi.MdAngles(3, abi.MD_BY_ID, 8, 8)
+    assert lib.md_bonded_reindex(P(ok), P(full), None, None, None, None, None, None, None,
+                                 None) == abi.MD_OK          # nothing to do, nothing launched
+    assert lib.md_bonded_reindex(P(ok), P(nowhere), P(bid), 8, 8, None, None, None, None,
+                                 None) == abi.MD_EINVAL
+    assert lib.md_bonded_reindex(P(ok), P(full), P(abi.MdBonds(2, abi.MD_BY_INDEX, 8, 8)), 8, 8,
+                                 None, None, None, None, None) == abi.MD_EINVAL
+    assert lib.md_bonded_reindex(P(ok), P(full), P(bid), 8, None, None, None, None, None,
+                                 None) == abi.MD_EINVAL
+    assert lib.md_bonded_reindex(P(ok), P(full), P(abi.MdBonds(abi.MD_MAX_BONDS + 1, 0, 8, 8)),
+                                 8, 8, None, None, None, None, None) == abi.MD_EINVAL
+    assert lib.md_bonded_reindex(P(ok), P(full), None, None, None, P(aid), 8, None, None,
+                                 None) == abi.MD_EINVAL
+    assert lib.md_bonded_reindex(P(ok), P(full), None, None, None,
+                                 P(abi.MdAngles(abi.MD_MAX_ANGLES + 1, 0, 8, 8)), 8, 8, None,
+                                 None) == abi.MD_EINVAL
+    assert lib.md_bonded_reindex(P(abi.MdBatch()), P(full), P(bid), 8, 8, None, None, None, None,
+                                 None) == abi.MD_EINVAL

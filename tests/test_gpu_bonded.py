@@ -248,3 +248,29 @@ def test_ring_melt_full_size_after_graphed_steps():
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-5
     # the bonded terms are FP64 on both sides
     assert float(s.energy_angle[0]) == pytest.approx(e_a, rel=1e-11)
+
+
+def test_bonded_tables_by_index_match_by_id():
+    # tables re-keyed to the cell-sorted order after each re-sort give the
+    # same per-atom sums in the same slot order: identical trajectories
+    print("case: bonded tables by index vs by id", flush=True)
+    cfg = _rings((8, 8, 8), 31)
+    a = _system(cfg, langevin=(0.5, 1.0, 3, 0), bonded_order="index")
+    b = _system(cfg, langevin=(0.5, 1.0, 3, 0), bonded_order="id")
+    for s in (a, b):
+        s.setup()
+        s.run_graphed(40, k=8)
+        assert s.ensure_list() == 0
+    assert np.array_equal(a.positions(), b.positions())
+    assert np.array_equal(a.forces_np(), b.forces_np())
+    assert float(a.energy_angle[0]) == pytest.approx(float(b.energy_angle[0]), rel=1e-12)
+    assert float(a.energy_bond[0]) == pytest.approx(float(b.energy_bond[0]), rel=1e-12)
+    # the re-keyed tables name current indices: the partners of atom i are
+    # the atoms whose ids the id-keyed table lists for id[i]
+    ids = a.id.cpu().numpy()
+    where = np.empty_like(ids)
+    where[ids] = np.arange(ids.shape[0])
+    bp = a.bond_partner.cpu().numpy()
+    np.testing.assert_array_equal(a.bond_partner_ix.cpu().numpy(), where[bp[:, ids]])
+    tri = a.angle_tri.cpu().numpy()
+    np.testing.assert_array_equal(a.angle_tri_ix.cpu().numpy(), where[tri[:, ids]])
