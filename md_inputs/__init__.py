@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "Config", "fcc_lattice", "maxwell_velocities", "jitter", "lj_fluid",
     "random_walk_chains", "lattice_chains", "ring_cycle", "lattice_rings", "lj_slab",
-    "lj_sphere", "replica_batch", "CONFIGS",
+    "lj_sphere", "replica_batch", "retyped", "CONFIGS",
 ]
 
 # Basis of the FCC conventional cubic cell, in units of the lattice constant.
@@ -314,6 +314,20 @@ def replica_batch(nrep=256, nmin=500, nmax=20000, rho=0.8442, temperature=1.0,
                   np.array(box_l, dtype=np.float64), sizes.astype(np.int64),
                   np.concatenate(typ_l), 2, eps, sig, np.ones(2), 2.5, 0.3, dt,
                   temperature, steps)
+
+
+def retyped(cfg, ntypes, seed=0):
+    """The same configuration with atom types drawn uniformly from
+    [0, ntypes) and one symmetric (eps, sigma) table with entries uniform in
+    [0.8, 1.2]."""
+    rng = np.random.default_rng(seed)
+    types = rng.integers(0, ntypes, size=cfg.n).astype(np.int32)
+    eps = rng.uniform(0.8, 1.2, size=(ntypes, ntypes))
+    sig = rng.uniform(0.8, 1.2, size=(ntypes, ntypes))
+    eps = np.triu(eps) + np.triu(eps, 1).T
+    sig = np.triu(sig) + np.triu(sig, 1).T
+    return dataclasses.replace(cfg, name=f"{cfg.name}_t{ntypes}", types=types, ntypes=ntypes,
+                               eps=eps, sig=sig, mass=np.ones(ntypes))
 
 
 # The five workloads, by name.  Each entry builds its Config on demand.

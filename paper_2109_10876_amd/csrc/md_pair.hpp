@@ -6,6 +6,8 @@
 // on i from j is fr d with d = x_i - x_j.
 #pragma once
 
+#include <type_traits>
+
 #include "md_common.hpp"
 
 namespace md {
@@ -121,6 +123,60 @@ __device__ __forceinline__ void lj_pair_masked(const PolyConst &pc, double dx, d
         const float w = q3 * fmaf(pc.Af, q3, -pc.Bf);
         const float frf = in ? w * q : 0.0f;
         c.ef += in ? fmaf(q3, fmaf(pc.Cf, q3, -pc.Df), -pc.ushf) : 0.0f;
+        c.wf = fmaf(frf, r2f, c.wf);
+        fr = static_cast<double>(frf);
+    }
+    c.fx = fma(fr, dx, c.fx);
+    c.fy = fma(fr, dy, c.fy);
+    c.fz = fma(fr, dz, c.fz);
+}
+
+// The same pair terms from the force constants of one type pair alone:
+// with A = 48 eps s12 and B = 24 eps s6 the energy constants are C = A/12
+// and D = B/6, so U = q3 (A q3 - 2B) / 12 - ush.  Three constants per type
+// pair fit in registers, so a two-type list selects them per entry instead
+// of reading a table.
+template <int PREC>
+struct PairAB {
+    using T = std::conditional_t<PREC == MD_FP64, double, float>;
+    T A, B, ush;
+};
+
+template <int PREC>
+__device__ __forceinline__ PairAB<PREC> pair_ab(const PolyConst &p)
+{
+    if constexpr (PREC == MD_FP64) return PairAB<PREC>{p.A, p.B, p.ush};
+    else return PairAB<PREC>{p.Af, p.Bf, p.ushf};
+}
+
+template <int PREC>
+__device__ __forceinline__ PairAB<PREC> select_ab(bool second, const PairAB<PREC> &k0,
+                                                  const PairAB<PREC> &k1)
+{
+    return PairAB<PREC>{second ? k1.A : k0.A, second ? k1.B : k0.B, second ? k1.ush : k0.ush};
+}
+
+template <int PREC>
+__device__ __forceinline__ void lj_pair_ab(const PairAB<PREC> &k, double dx, double dy,
+                                           double dz, double rc2, Acc &c)
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const bool in = r2 < rc2;
+    double fr;
+    if constexpr (PREC == MD_FP64) {
+        const double q = rcp_f64(r2);
+        const double q3 = q * q * q;
+        const double t = k.A * q3;
+        fr = in ? q3 * (t - k.B) * q : 0.0;
+        c.ed += in ? (q3 * (1.0 / 12.0)) * (t - 2.0 * k.B) - k.ush : 0.0;
+        c.wd = fma(fr, r2, c.wd);
+    } else {
+        const float r2f = static_cast<float>(r2);
+        const float q = __builtin_amdgcn_rcpf(r2f);
+        const float q3 = q * q * q;
+        const float t = k.A * q3;
+        const float frf = in ? q3 * (t - k.B) * q : 0.0f;
+        c.ef += in ? (q3 * (1.0f / 12.0f)) * (t - 2.0f * k.B) - k.ush : 0.0f;
         c.wf = fmaf(frf, r2f, c.wf);
         fr = static_cast<double>(frf);
     }

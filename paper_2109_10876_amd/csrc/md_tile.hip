@@ -18,18 +18,21 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 // Typed lists: LJ constants of type pair (ti, tj) at ti * kTileMaxTypes + tj.
 constexpr int kTileMaxTypes = MD_TILE_MAX_TYPES;
 
-template <class SH, int PREC, int U, bool P4, bool TYPED, bool FUSE>
+// TY: 0 one atom type; 2 two types, the constants of this atom's two type
+// pairs held in registers and selected per entry; 4 up to four types, the
+// constants read per entry from an LDS table.
+template <class SH, int PREC, int U, bool P4, int TY, bool FUSE>
 __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
 {
     constexpr int TB = SH::TB, CAP = SH::CAP;
     __shared__ TileStage<CAP, SH::MAXC> st;
     __shared__ double red[4][TB / kWave];
-    __shared__ PolyConst ptab[TYPED ? kTileMaxTypes * kTileMaxTypes : 1];
+    __shared__ PolyConst ptab[TY ? kTileMaxTypes * kTileMaxTypes : 1];
     const int t = xcd_chunked(blockIdx.x, gridDim.x, kTileXcdChunk);
     const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
     const PolyConst pc = poly_const(a.eps[0], a.sig[0], a.rc, a.shift);
     const double rc2 = a.rc * a.rc;
-    if (TYPED) {
+    if (TY) {
         // filled before staging, whose barriers publish it
         const int nt = a.tile_types;
         if (threadIdx.x < nt * nt) {
@@ -65,7 +68,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
             yi = a.y[i];
             zi = a.z[i];
             n = min(a.count[i], a.max_nbr);
-            ti4 = TYPED ? a.type[i] * kTileMaxTypes : 0;
+            ti4 = TY ? a.type[i] * kTileMaxTypes : 0;
 #pragma unroll
             for (int b = 0; b < NB; ++b)
                 cur[b] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a.idx) + i +
@@ -84,6 +87,11 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
         constexpr int kY = int(sizeof(double)) * decltype(st)::kStride;
         while (hk < nh) {
             Acc c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
+            PairAB<PREC> k0{}, k1{};
+            if (TY == 2) {
+                k0 = pair_ab<PREC>(ptab[ti4]);
+                k1 = pair_ab<PREC>(ptab[ti4 + 1]);
+            }
             const u32x4 *lb = reinterpret_cast<const u32x4 *>(a.idx) + i;
             u32x4 nxt[NB];
             for (int k = 0; k < n; k += U) {
@@ -102,16 +110,21 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
 #pragma unroll
                 for (int q = 0; q < U; ++q) {
                     // typed entries carry the type in the low 3 bits
-                    const unsigned e = TYPED ? ent[q] & ~7u : ent[q];
+                    const unsigned e = TY ? ent[q] & ~7u : ent[q];
                     const char *pq = stb + min(e, unsigned(CAP * 8));
                     px[q] = *reinterpret_cast<const double *>(pq);
                     py[q] = *reinterpret_cast<const double *>(pq + kY);
                     pz[q] = *reinterpret_cast<const double *>(pq + 2 * kY);
                 }
 #pragma unroll
-                for (int q = 0; q < U; ++q)
-                    lj_pair_masked<PREC>(TYPED ? ptab[ti4 + (ent[q] & 7)] : pc, xi - px[q],
+                for (int q = 0; q < U; ++q) {
+                    if (TY == 2)
+                        lj_pair_ab<PREC>(select_ab<PREC>(ent[q] & 1u, k0, k1), xi - px[q],
                                          yi - py[q], zi - pz[q], rc2, c);
+                    else
+                        lj_pair_masked<PREC>(TY ? ptab[ti4 + (ent[q] & 7)] : pc, xi - px[q],
+                                             yi - py[q], zi - pz[q], rc2, c);
+                }
 #pragma unroll
                 for (int b = 0; b < NB; ++b) cur[b] = nxt[b];
             }
@@ -164,7 +177,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
                 yi = a.y[i];
                 zi = a.z[i];
                 n = min(a.count[i], a.max_nbr);
-                ti4 = TYPED ? a.type[i] * kTileMaxTypes : 0;
+                ti4 = TY ? a.type[i] * kTileMaxTypes : 0;
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
                     cur[b] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a.idx) + i +
@@ -333,17 +346,20 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
         else hipLaunchKernelGGL((k_tile_lj<SH, P, U, false, T, F>), grid, blk, 0, s, a);    \
     } while (0)
         if (fuse) {
-            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, false, true);
-            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, false, true);
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 0, true);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, true);
+        } else if (typed && p->ntypes == 2) {
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 2, false);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 2, false);
         } else if (typed) {
-            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, true, false);
-            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, true, false);
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 4, false);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 4, false);
         } else if (prec == MD_FP64) {
-            if (big) MD_TILE_LAUNCH(MD_FP64, 16, false, false);
-            else MD_TILE_LAUNCH(MD_FP64, 8, false, false);
+            if (big) MD_TILE_LAUNCH(MD_FP64, 16, 0, false);
+            else MD_TILE_LAUNCH(MD_FP64, 8, 0, false);
         } else {
-            if (big) MD_TILE_LAUNCH(MD_FP32_MIXED, 16, false, false);
-            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, false, false);
+            if (big) MD_TILE_LAUNCH(MD_FP32_MIXED, 16, 0, false);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, false);
         }
 #undef MD_TILE_LAUNCH
     });

@@ -544,15 +544,19 @@ def test_tile_batch_equals_each_replica_alone():
         assert float(t.ke[0]) == float(s.ke[r])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_typed_tile_lists_on_the_two_type_replica_batch(prec):
-    # two atom types with one symmetric (eps, sigma) table: tile-list entries
-    # carry the neighbour's type; forces and energy per replica against the
-    # oracle, and the pair set against the global full list
+@pytest.mark.parametrize("prec,ntypes", [("fp64", 2), ("mixed", 2), ("fp64", 3),
+                                          ("mixed", 4)])
+def test_typed_tile_lists_on_the_replica_batch(prec, ntypes):
+    # several atom types with one symmetric (eps, sigma) table: tile-list
+    # entries carry the neighbour's type (two types: constants selected in
+    # registers; three or four: read from a table); forces and energy per
+    # replica against the oracle, and the pair set against the global list
     cfg = md_inputs.replica_batch(nrep=5, nmin=500, nmax=6000, seed=23)
-    say(f"case: typed tile batch {prec}")
+    if ntypes != 2:
+        cfg = md_inputs.retyped(cfg, ntypes, seed=29)
+    say(f"case: typed tile batch {prec} ntypes={ntypes}")
     s = _system(cfg, mode="tile", prec=prec, tile_rows=(2, 2))
-    assert s.nlist.tile_types == 2
+    assert s.nlist.tile_types == ntypes
     s.setup()
     assert s.ensure_list() == 0
     f = s.forces_np()
