@@ -210,11 +210,11 @@ def time_workload(name, steps, warmup=10):
             "lj_sphere": (1.0, 0.1, 6)}.get(name)
     ntypes = int(np.atleast_2d(np.asarray(cfg.eps)).shape[0])
 
-    def make(mode="full", tile_cells=None, tile_rows=(1, 1)):
+    def make(mode="full", tile_cells=None, tile_rows=(1, 1), fuse=True):
         return MDSystem(cfg.natoms, cfg.box, cfg.pos, cfg.vel, cfg.types, cfg.eps, cfg.sig,
                         cfg.mass, rc=cfg.rc, skin=cfg.skin, dt=cfg.dt, shift=cfg.shift,
                         bonds=cfg.bonds, angles=cfg.angles, langevin=lang, prec="mixed",
-                        mode=mode, tile_cells=tile_cells, tile_rows=tile_rows)
+                        mode=mode, tile_cells=tile_cells, tile_rows=tile_rows, fuse=fuse)
     from paper_2109_10876_amd import _abi
     if ntypes <= _abi.MD_TILE_MAX_TYPES:
         # list form and launch shape from the autotuner (untimed)
@@ -223,7 +223,8 @@ def time_workload(name, steps, warmup=10):
     else:
         tuned = {"mode": "full", "batch": 4}
     autotune.apply(tuned)
-    s = make(tuned["mode"], tuned.get("tile_cells"), tuple(tuned.get("tile_rows", (1, 1))))
+    s = make(tuned["mode"], tuned.get("tile_cells"), tuple(tuned.get("tile_rows", (1, 1))),
+             tuned.get("fuse", True))
     s.setup()
     s.ensure_list()
     s.run_graphed(warmup, k=25)

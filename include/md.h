@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 4
+#define MD_ABI_VERSION 5
 
 /* ------------------------------------------------------------ return codes */
 #define MD_OK            0
@@ -215,6 +215,17 @@ typedef struct md_angles {
     const int32_t *tri;       /* [3 * max_angles * N] members, by slot and role    */
 } md_angles;
 
+/* Langevin thermostat of md_lj_forces_vv: the force of md_langevin (same
+ * normals, same counter) with these parameters. */
+typedef struct md_thermostat {
+    double gamma;             /* friction, >= 0                                   */
+    double temperature;       /* target T, >= 0                                   */
+    uint64_t seed;            /* Philox key                                       */
+    uint64_t *step;           /* device, one uint64: the noise counter, read by
+                                 every atom and then advanced by one            */
+    const double *mass;       /* [ntypes] device: m of each type                  */
+} md_thermostat;
+
 /* ---------------------------------------------------------------- plumbing */
 
 int         md_abi_version(void);
@@ -333,11 +344,15 @@ int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
  * Integrate2 and the next step's Integrate1 directly): on return fx, fy, fz
  * hold the forces at the positions on entry, velocities and positions are
  * advanced, gate[r] and ke[r] (optional) are set as by md_vv_step phase 3,
- * energy/virial as by md_lj_forces.  Pure pair forces only: MD_TILE_FULL
- * lists of one atom type (MD_EUNSUPPORTED otherwise); a step that adds bond
- * or thermostat forces uses md_lj_forces and md_vv_step.  The same
- * arithmetic as those two calls in sequence, so trajectories are bitwise
- * equal; the kinetic energy is summed in another order.  New positions:
+ * energy/virial as by md_lj_forces.  Pair forces of one atom type over
+ * MD_TILE_FULL lists (MD_EUNSUPPORTED otherwise), optionally with the
+ * Langevin thermostat: with thermo set, each atom's force also receives the
+ * md_langevin force (velocity on entry, noise counter *thermo->step, which
+ * is then advanced by one) before the integrator uses it, as md_lj_forces,
+ * md_langevin and md_vv_step phase 3 in sequence would.  A step that adds
+ * bond forces uses the separate calls.  The same arithmetic as those calls
+ * in sequence, so trajectories agree to rounding of the thermostat sum (and
+ * bitwise without it); the kinetic energy is summed in another order.  New positions:
  * with x_next, y_next, z_next NULL they are staged in the workspace and
  * copied back into atoms->x, y, z (and the packed copy, if set); with all
  * three given ([N] device each, not overlapping atoms->x, y, z; atoms->pos4
@@ -347,8 +362,9 @@ int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
 int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlist *nl, const md_lj *p,
                     int32_t prec, double dt, const double *inv_mass, int32_t ntypes,
                     double skin, uint32_t *gate, double *ke, double *energy, double *virial,
-                    double *x_next, double *y_next, double *z_next, void *ws,
-                    size_t ws_bytes, uint32_t *status, void *stream);
+                    double *x_next, double *y_next, double *z_next,
+                    const md_thermostat *thermo, void *ws, size_t ws_bytes,
+                    uint32_t *status, void *stream);
 
 /* Velocity-Verlet update (Sec. 2.1, Fig. 1: Integrate1 / Integrate2).
  *  phase 1: v += dt/2 F/m; x += dt v; gate[r] = 1 if some atom of replica r

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmd.so")
 
 # Constants mirrored from md.h.
-MD_ABI_VERSION = 4
+MD_ABI_VERSION = 5
 MD_OK = 0
 MD_EINVAL = -1
 MD_EBOX = -2
@@ -95,6 +95,11 @@ class MdAngles(ctypes.Structure):
     _fields_ = [("max_angles", _i32), ("order", _i32), ("count", _vp), ("tri", _vp)]
 
 
+class MdThermostat(ctypes.Structure):
+    _fields_ = [("gamma", _dbl), ("temperature", _dbl), ("seed", ctypes.c_uint64),
+                ("step", _vp), ("mass", _vp)]
+
+
 class MDError(RuntimeError):
     """A libmd call returned a negative MD_E* code."""
 
@@ -155,8 +160,8 @@ def load():
                                _vp, ctypes.c_size_t, _vp, _vp]
     lib.md_lj_forces_vv.restype = ctypes.c_int
     lib.md_lj_forces_vv.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32, _dbl,
-                                    _vp, _i32, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                    ctypes.c_size_t, _vp, _vp]
+                                    _vp, _i32, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    P(MdThermostat), _vp, ctypes.c_size_t, _vp, _vp]
     lib.md_lj_forces_vjp.restype = ctypes.c_int
     lib.md_lj_forces_vjp.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32,
                                      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,

@@ -11,7 +11,9 @@ timing a short graphed run of the real step for each candidate:
     (1 x 1, 2 x 1 or 2 x 2 in y x z) and cells per tile along x, the last
     swept the paper's way -- from the fewest (largest) tiles that fit, make
     tiles smaller (more of them) while the time keeps dropping;
-  * neighbour-gather batch (MD_TUNE_PAIR_BATCH).
+  * neighbour-gather batch (MD_TUNE_PAIR_BATCH);
+  * on tile lists, the fused force + integrator call or the split calls
+    (when the factory takes ``fuse``).
 
 Results are cached as JSON keyed by the device name and a coarse workload
 signature (atom count bucket, mean atoms per cell, replicas, types), so a
@@ -21,6 +23,7 @@ fixed candidate, and within round-off across candidates).
 """
 from __future__ import annotations
 
+import inspect
 import json
 import math
 import os
@@ -58,8 +61,9 @@ def _time(make, cand, steps, warmup):
     """ms per graphed step of a system built for ``cand``."""
     lib = abi.load()
     _apply(lib, cand)
+    extra = {"fuse": cand["fuse"]} if "fuse" in cand else {}
     s = make(mode=cand["mode"], tile_cells=cand.get("tile_cells"),
-             tile_rows=tuple(cand.get("tile_rows", (1, 1))))
+             tile_rows=tuple(cand.get("tile_rows", (1, 1))), **extra)
     s.setup()
     s.ensure_list()
     s.run_graphed(warmup, k=min(25, max(1, warmup)))
@@ -80,8 +84,8 @@ def _time(make, cand, steps, warmup):
 
 def tune(make, key, steps=40, warmup=10, cache=DEFAULT_CACHE, retune=False, log=None):
     """Pick the fastest candidate for ``make(mode=..., tile_cells=...,
-    tile_rows=...)`` (a factory returning an MDSystem) and remember it under
-    ``key``.
+    tile_rows=...[, fuse=...])`` (a factory returning an MDSystem) and
+    remember it under ``key``.
 
     Returns (best candidate dict, list of (candidate, ms) trials)."""
     table = {}
@@ -136,6 +140,12 @@ def tune(make, key, steps=40, warmup=10, cache=DEFAULT_CACHE, retune=False, log=
         for batch in (8,):
             run(dict(best, batch=batch))
         best = dict(min(trials, key=lambda t: t[1])[0])
+        # the fused force + integrator call against the split calls (for a
+        # factory that takes ``fuse``): with a thermostat the fused kernel
+        # also draws the noise, which pays on some workloads and not others
+        if "fuse" in inspect.signature(make).parameters:
+            run(dict(best, fuse=False))
+            best = dict(min(trials, key=lambda t: t[1])[0])
     _apply(abi.load(), best)
     if cache:
         table[key] = {"best": best, "trials": trials}

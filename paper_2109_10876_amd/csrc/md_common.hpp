@@ -267,6 +267,12 @@ struct VVFuse {
     double *ke;
     uint32_t *gate;
     bool copy_back;   // xn/yn/zn are workspace: copy them into atoms->x/y/z
+    // Langevin thermostat (step == nullptr: none)
+    const int32_t *id;
+    const double *mass;
+    double gamma, kT_dt2;   // 2 T / dt
+    uint32_t seed_lo, seed_hi;
+    uint64_t *step;
 };
 
 int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const md_lj *p,

@@ -312,8 +312,8 @@ extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlis
                                const md_lj *p, int32_t prec, double dt, const double *inv_mass,
                                int32_t ntypes, double skin, uint32_t *gate, double *ke,
                                double *energy, double *virial, double *x_next, double *y_next,
-                               double *z_next, void *ws, size_t ws_bytes, uint32_t *status,
-                               void *stream)
+                               double *z_next, const md_thermostat *thermo, void *ws,
+                               size_t ws_bytes, uint32_t *status, void *stream)
 {
     using namespace md;
     int e = check_batch(b);
@@ -329,6 +329,9 @@ extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlis
     if (ntypes < 1 || ntypes > MD_MAX_TYPES || (ntypes > 1 && !atoms->type)) return MD_EINVAL;
     if (prec != MD_FP64 && prec != MD_FP32_MIXED) return MD_EINVAL;
     if (!(skin >= 0.0) || !(dt > 0.0)) return MD_EINVAL;
+    if (thermo && (!thermo->step || !thermo->mass || !atoms->id || !(thermo->gamma >= 0.0) ||
+                   !(thermo->temperature >= 0.0)))
+        return MD_EINVAL;
     const WsLayout l = ws_layout(b);
     if (ws_bytes < l.total) return MD_ENOWS;
     if (!tile_list_ok(b, nl) || !nl->cell_start || nl->tile_types > 1) return MD_EINVAL;
@@ -347,7 +350,13 @@ extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlis
     const VVFuse f{atoms->vx, atoms->vy, atoms->vz, atoms->xb, atoms->yb, atoms->zb, inv_mass,
                    ntypes, 0.5 * dt, dt, 0.25 * skin * skin,
                    given ? x_next : xw, given ? y_next : xw + b->N,
-                   given ? z_next : xw + 2 * size_t(b->N), ke, gate, !given};
+                   given ? z_next : xw + 2 * size_t(b->N), ke, gate, !given,
+                   thermo ? atoms->id : nullptr, thermo ? thermo->mass : nullptr,
+                   thermo ? thermo->gamma : 0.0,
+                   thermo ? 2.0 * thermo->temperature / dt : 0.0,
+                   thermo ? static_cast<uint32_t>(thermo->seed) : 0u,
+                   thermo ? static_cast<uint32_t>(thermo->seed >> 32) : 0u,
+                   thermo ? thermo->step : nullptr};
     return tile_forces(b, atoms, nl, p, prec, 0, nl->cell_start, energy, virial,
                        ws_at<double>(ws, l.tile_partial), md_tune_get(MD_TUNE_PAIR_BATCH), &f,
                        status, as_stream(stream));

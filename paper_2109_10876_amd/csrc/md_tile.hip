@@ -8,6 +8,7 @@
 // (built by md_tile_build.hip), reading neighbours from LDS: no image
 // arithmetic and no L2 gathers in the pair loop.
 #include "md_pair.hpp"
+#include "md_philox.hpp"
 #include "md_tile.hpp"
 
 namespace md {
@@ -20,8 +21,9 @@ constexpr int kTileMaxTypes = MD_TILE_MAX_TYPES;
 
 // TY: 0 one atom type; 2 two types, the constants of this atom's two type
 // pairs held in registers and selected per entry; 4 up to four types, the
-// constants read per entry from an LDS table.
-template <class SH, int PREC, int U, bool P4, int TY, bool FUSE>
+// constants read per entry from an LDS table.  FUSE: 0 forces only; 1 then
+// md_vv_step phase 3 per atom; 2 the thermostat force added before it.
+template <class SH, int PREC, int U, bool P4, int TY, int FUSE>
 __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
 {
     constexpr int TB = SH::TB, CAP = SH::CAP;
@@ -135,29 +137,43 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
             }
             e_acc += 0.5 * ed;
             w_acc += 0.5 * wd;
-            if (a.accumulate) {
-                a.fx[i] += c.fx;
-                a.fy[i] += c.fy;
-                a.fz[i] += c.fz;
-            } else {
-                a.fx[i] = c.fx;
-                a.fy[i] = c.fy;
-                a.fz[i] = c.fz;
+            double gx = c.fx, gy = c.fy, gz = c.fz;   // the atom's force
+            if (FUSE == 2) {
+                // md_langevin's force, with the velocity on entry
+                const VVFuse &f = a.vv;
+                const double m = f.mass[f.ntypes > 1 ? a.type[i] : 0];
+                double g[3];
+                thermostat_normals(static_cast<uint32_t>(f.id[i]), *f.step, f.seed_lo, f.seed_hi,
+                                   g);
+                const double amp = sqrt(f.gamma * m * f.kT_dt2);
+                const double gm = f.gamma * m;
+                gx += -gm * f.vx[i] + amp * g[0];
+                gy += -gm * f.vy[i] + amp * g[1];
+                gz += -gm * f.vz[i] + amp * g[2];
             }
-            if (a.status && !isfinite(c.fx + c.fy + c.fz + ed)) atomicOr(a.status, MD_F_NONFINITE);
+            if (a.accumulate) {
+                a.fx[i] += gx;
+                a.fy[i] += gy;
+                a.fz[i] += gz;
+            } else {
+                a.fx[i] = gx;
+                a.fy[i] = gy;
+                a.fz[i] = gz;
+            }
+            if (a.status && !isfinite(gx + gy + gz + ed)) atomicOr(a.status, MD_F_NONFINITE);
             if (FUSE) {
                 // md_vv_step phase 3 on this atom with the force just computed
                 const VVFuse &f = a.vv;
                 const double im = f.inv_mass[f.ntypes > 1 ? a.type[i] : 0];
                 const double k = f.hdt * im;
                 double vx = f.vx[i], vy = f.vy[i], vz = f.vz[i];
-                vx = fma(k, c.fx, vx);
-                vy = fma(k, c.fy, vy);
-                vz = fma(k, c.fz, vz);
+                vx = fma(k, gx, vx);
+                vy = fma(k, gy, vy);
+                vz = fma(k, gz, vz);
                 ke_acc += 0.5 * (vx * vx + vy * vy + vz * vz) / im;
-                vx = fma(k, c.fx, vx);
-                vy = fma(k, c.fy, vy);
-                vz = fma(k, c.fz, vz);
+                vx = fma(k, gx, vx);
+                vy = fma(k, gy, vy);
+                vz = fma(k, gz, vz);
                 const double x = fma(f.dt, vx, xi);
                 const double y = fma(f.dt, vy, yi);
                 const double z = fma(f.dt, vz, zi);
@@ -238,8 +254,12 @@ __global__ __launch_bounds__(kUnit) void k_copy_next(int32_t n, const double *__
 __global__ __launch_bounds__(kFin) void k_tile_finalize(const int32_t *tile_off,
                                                         const double *tpart, double *energy,
                                                         double *virial, double *ke,
-                                                        uint32_t *gate, double lim2)
+                                                        uint32_t *gate, double lim2,
+                                                        uint64_t *step)
 {
+    // the thermostat's noise counter advances once per call, after every
+    // tile has read it
+    if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += 1u;
     constexpr int kW = kFin / kWave;
     __shared__ double red[4][kW];
     const int r = blockIdx.x;
@@ -345,21 +365,24 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
         if (p4) hipLaunchKernelGGL((k_tile_lj<SH, P, U, true, T, F>), grid, blk, 0, s, a);  \
         else hipLaunchKernelGGL((k_tile_lj<SH, P, U, false, T, F>), grid, blk, 0, s, a);    \
     } while (0)
-        if (fuse) {
-            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 0, true);
-            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, true);
+        if (fuse && vvf->step) {
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 0, 2);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, 2);
+        } else if (fuse) {
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 0, 1);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, 1);
         } else if (typed && p->ntypes == 2) {
-            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 2, false);
-            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 2, false);
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 2, 0);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 2, 0);
         } else if (typed) {
-            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 4, false);
-            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 4, false);
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 4, 0);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 4, 0);
         } else if (prec == MD_FP64) {
-            if (big) MD_TILE_LAUNCH(MD_FP64, 16, 0, false);
-            else MD_TILE_LAUNCH(MD_FP64, 8, 0, false);
+            if (big) MD_TILE_LAUNCH(MD_FP64, 16, 0, 0);
+            else MD_TILE_LAUNCH(MD_FP64, 8, 0, 0);
         } else {
-            if (big) MD_TILE_LAUNCH(MD_FP32_MIXED, 16, 0, false);
-            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, false);
+            if (big) MD_TILE_LAUNCH(MD_FP32_MIXED, 16, 0, 0);
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, 0);
         }
 #undef MD_TILE_LAUNCH
     });
@@ -368,7 +391,8 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
     uint32_t *gate = fuse ? vvf->gate : nullptr;
     if (energy || virial || ke || gate)
         hipLaunchKernelGGL(k_tile_finalize, dim3(b->R), dim3(kFin), 0, s, nl->tile_off, tpart,
-                           energy, virial, ke, gate, fuse ? vvf->lim2 : 0.0);
+                           energy, virial, ke, gate, fuse ? vvf->lim2 : 0.0,
+                           fuse ? vvf->step : nullptr);
     if (fuse && vvf->copy_back)
         hipLaunchKernelGGL(k_copy_next, dim3((b->N + kUnit - 1) / kUnit), dim3(kUnit), 0, s, b->N,
                            vvf->xn, vvf->yn, vvf->zn, atoms->x, atoms->y, atoms->z, atoms->pos4);

@@ -253,11 +253,16 @@ class MDSystem:
             self.langevin_cfg = (float(gamma), float(temp), int(seed))
             self.mass_t = f64(mass)
             self.noise_step = torch.tensor([int(step0)], dtype=torch.int64, device=d)
-        # pure pair forces on tile lists: the force call also advances the
-        # step (md_lj_forces_vv); bonds or a thermostat need the split calls
+        # pair forces of one type on tile lists, with or without the
+        # thermostat: the force call also advances the step
+        # (md_lj_forces_vv); bonds or angles need the split calls
         self.fuse = bool(fuse) and self.mode == abi.MD_TILE_FULL and self.bonds is None \
-            and self.angles is None \
-            and self.langevin_cfg is None and self.ntypes == 1
+            and self.angles is None and self.ntypes == 1
+        self.thermo = None
+        if self.langevin_cfg is not None:
+            gamma, temp, seed = self.langevin_cfg
+            self.thermo = abi.MdThermostat(gamma, temp, seed, self.noise_step.data_ptr(),
+                                           self.mass_t.data_ptr())
         if self.fuse and self.pos4 is None:
             self._pos.append((z64(), z64(), z64()))
             self._atoms.append(self._atoms_struct(self._pos[1]))
@@ -356,8 +361,8 @@ class MDSystem:
             _ptr(self.virial), _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
 
     def forces_vv(self):
-        """Forces at the current positions, then velocity-Verlet phase 3, in
-        one call (pure pair forces on tile lists)."""
+        """Forces at the current positions (plus the thermostat, if any), then
+        velocity-Verlet phase 3, in one call (pair forces on tile lists)."""
         two = len(self._pos) == 2
         nxt = self._pos[self._par ^ 1] if two else (None, None, None)
         check("md_lj_forces_vv", self.lib.md_lj_forces_vv(
@@ -365,6 +370,7 @@ class MDSystem:
             ctypes.byref(self.lj), self.prec, self.dt, _ptr(self.inv_mass), self.ntypes,
             self.skin, _ptr(self.gate), _ptr(self.ke), _ptr(self.energy), _ptr(self.virial),
             _ptr(nxt[0]), _ptr(nxt[1]), _ptr(nxt[2]),
+            ctypes.byref(self.thermo) if self.thermo is not None else None,
             _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
         if two:
             self._par ^= 1   # the next positions are now the current ones

@@ -274,3 +274,49 @@ def test_bonded_tables_by_index_match_by_id():
     np.testing.assert_array_equal(a.bond_partner_ix.cpu().numpy(), where[bp[:, ids]])
     tri = a.angle_tri.cpu().numpy()
     np.testing.assert_array_equal(a.angle_tri_ix.cpu().numpy(), where[tri[:, ids]])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fused_step_with_thermostat_matches_oracle(prec):
+    # pure LJ on tile lists with the Langevin thermostat: md_lj_forces_vv adds
+    # the thermostat force inside the force kernel; the trajectory and the
+    # rebuild schedule against the oracle's (same Philox noise)
+    print(f"case: fused step with thermostat {prec}", flush=True)
+    cfg = md_inputs.lj_fluid(8, temperature=1.0, seed=41)
+    steps = 60 if prec == "fp64" else 20   # mixed: the short-horizon bar
+    s = _system(cfg, langevin=(1.0, 0.85, 77, 5), mode="tile", prec=prec)
+    assert s.fuse and s.thermo is not None
+    s.setup()
+    s.run(steps, check_every=0)
+    assert s.ensure_list() == 0
+    assert int(s.noise_step.item()) == 5 + 1 + steps
+    ref = oracle.md_run_ext(cfg.pos, cfg.vel, cfg.box[0], cfg.rc, cfg.skin, cfg.dt, steps,
+                            gamma=1.0, temperature=0.85, seed=77, step0=5)
+    tol = 1e-9 if prec == "fp64" else 1e-6
+    assert np.abs(s.positions() - ref["pos"]).max() < tol
+    assert np.abs(s.velocities() - ref["vel"]).max() < 10 * tol
+
+
+def test_fused_step_with_thermostat_equals_split_calls_and_graphs():
+    # the fused call (eager and graphed) against md_lj_forces + md_langevin +
+    # md_vv_step: the same trajectory up to rounding of the thermostat sum
+    import torch
+    print("case: fused thermostat vs split, graphed", flush=True)
+    cfg = md_inputs.lj_fluid(8, temperature=1.0, seed=42)
+    lv = (0.7, 1.1, 99, 0)
+    a = _system(cfg, langevin=lv, mode="tile", prec="fp64")
+    b = _system(cfg, langevin=lv, mode="tile", prec="fp64", fuse=False)
+    c = _system(cfg, langevin=lv, mode="tile", prec="fp64")
+    assert a.fuse and not b.fuse
+    for s in (a, b, c):
+        s.setup()
+    a.run(37, check_every=0)
+    b.run(37, check_every=0)
+    c.run_graphed(37, k=6)
+    for s in (a, b, c):
+        assert s.ensure_list() == 0
+        assert int(s.noise_step.item()) == 38
+    assert np.abs(a.positions() - b.positions()).max() < 1e-10
+    assert np.abs(a.velocities() - b.velocities()).max() < 1e-9
+    assert np.array_equal(a.positions(), c.positions())
+    torch.cuda.synchronize()
