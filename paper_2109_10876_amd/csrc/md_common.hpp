@@ -275,10 +275,12 @@ struct VVFuse {
     uint64_t *step;
 };
 
+// chunk_sums: chunk_rows rows of kTilePartials doubles of scratch for the
+// two-stage sums of a single replica of many tiles (null: one stage).
 int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const md_lj *p,
                 int32_t prec, int32_t accumulate, const int32_t *cell_start, double *energy,
-                double *virial, double *tpart, int batch, const VVFuse *vvf, uint32_t *status,
-                hipStream_t s);
+                double *virial, double *tpart, double *chunk_sums, int chunk_rows, int batch,
+                const VVFuse *vvf, uint32_t *status, hipStream_t s);
 
 // Adjoint over tile-local lists (md_tile_vjp.hip); arguments as md_lj_forces_vjp.
 int tile_vjp(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const md_lj *p,

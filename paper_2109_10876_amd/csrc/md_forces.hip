@@ -286,8 +286,9 @@ extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_n
         if (p->ntypes > 1 ? (nl->tile_types != p->ntypes || !atoms->type) : nl->tile_types > 1)
             return MD_EINVAL;
         return tile_forces(b, atoms, nl, p, prec, accumulate, nl->cell_start, energy, virial,
-                           ws_at<double>(ws, l.tile_partial), md_tune_get(MD_TUNE_PAIR_BATCH),
-                           nullptr, status, as_stream(stream));
+                           ws_at<double>(ws, l.tile_partial), ws_at<double>(ws, l.partial),
+                           b->n_units, md_tune_get(MD_TUNE_PAIR_BATCH), nullptr, status,
+                           as_stream(stream));
     }
     ForceArgs a{b->atom_off, b->unit_rep, b->unit_off, b->box, atoms->x, atoms->y, atoms->z,
                 atoms->pos4, atoms->type, nl->count, nl->idx, nl->ld, nl->max_nbr, p->eps,
@@ -358,6 +359,7 @@ extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlis
                    thermo ? static_cast<uint32_t>(thermo->seed >> 32) : 0u,
                    thermo ? thermo->step : nullptr};
     return tile_forces(b, atoms, nl, p, prec, 0, nl->cell_start, energy, virial,
-                       ws_at<double>(ws, l.tile_partial), md_tune_get(MD_TUNE_PAIR_BATCH), &f,
-                       status, as_stream(stream));
+                       ws_at<double>(ws, l.tile_partial), ws_at<double>(ws, l.partial),
+                       b->n_units, md_tune_get(MD_TUNE_PAIR_BATCH), &f, status,
+                       as_stream(stream));
 }

@@ -251,33 +251,28 @@ __global__ __launch_bounds__(kUnit) void k_copy_next(int32_t n, const double *__
 
 // Per replica: fixed-order sums of its tiles' partials (energy, virial,
 // kinetic energy) and the largest displacement (the rebuild gate).
-__global__ __launch_bounds__(kFin) void k_tile_finalize(const int32_t *tile_off,
-                                                        const double *tpart, double *energy,
-                                                        double *virial, double *ke,
-                                                        uint32_t *gate, double lim2,
-                                                        uint64_t *step)
+// Fixed-order sums of the per-tile partials in rows [t0, t1) of tp (stride
+// kTilePartials): E, W, KE summed, the displacement maximum taken.  The
+// four reductions share one barrier; wave totals are then summed in wave
+// order, as by block_sum_n.  Thread 0 returns the results.
+__device__ __forceinline__ void tile_sums(int t0, int t1, const double *tp, bool want_ke,
+                                          bool want_gate, double out[4])
 {
-    // the thermostat's noise counter advances once per call, after every
-    // tile has read it
-    if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += 1u;
     constexpr int kW = kFin / kWave;
     __shared__ double red[4][kW];
-    const int r = blockIdx.x;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, m = 0.0;
 #pragma unroll 4
-    for (int t = tile_off[r] + threadIdx.x; t < tile_off[r + 1]; t += kFin) {
-        const double *tp = tpart + size_t(t) * kTilePartials;
-        s0 += tp[0];
-        s1 += tp[1];
-        if (ke) s2 += tp[2];
-        if (gate) m = fmax(m, tp[3]);
+    for (int t = t0 + threadIdx.x; t < t1; t += kFin) {
+        const double *q = tp + size_t(t) * kTilePartials;
+        s0 += q[0];
+        s1 += q[1];
+        if (want_ke) s2 += q[2];
+        if (want_gate) m = fmax(m, q[3]);
     }
-    // the four reductions share one barrier; wave totals are then summed in
-    // wave order, as by block_sum_n
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
-    if (ke) s2 = wave_sum(s2);
-    if (gate) m = wave_max(m);
+    if (want_ke) s2 = wave_sum(s2);
+    if (want_gate) m = wave_max(m);
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
     if (lane == 0) {
         red[0][wid] = s0;
@@ -294,11 +289,53 @@ __global__ __launch_bounds__(kFin) void k_tile_finalize(const int32_t *tile_off,
             k += red[2][q];
             d = fmax(d, red[3][q]);
         }
-        if (energy) energy[r] = e;
-        if (virial) virial[r] = w;
-        if (ke) ke[r] = k;
-        if (gate) gate[r] = d > lim2 ? 1u : 0u;
+        out[0] = e;
+        out[1] = w;
+        out[2] = k;
+        out[3] = d;
     }
+}
+
+// Per replica r, the sums over its tiles [tile_off[r], tile_off[r+1]); with
+// tile_off null (one replica of many tiles), over the n_rows chunk sums
+// that k_tile_chunk_sums wrote to tpart.
+__global__ __launch_bounds__(kFin) void k_tile_finalize(const int32_t *tile_off, int n_rows,
+                                                        const double *tpart, double *energy,
+                                                        double *virial, double *ke,
+                                                        uint32_t *gate, double lim2,
+                                                        uint64_t *step)
+{
+    // the thermostat's noise counter advances once per call, after every
+    // tile has read it
+    if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += 1u;
+    const int r = blockIdx.x;
+    const int t0 = tile_off ? tile_off[r] : 0, t1 = tile_off ? tile_off[r + 1] : n_rows;
+    double v[4];
+    tile_sums(t0, t1, tpart, ke != nullptr, gate != nullptr, v);
+    if (threadIdx.x == 0) {
+        if (energy) energy[r] = v[0];
+        if (virial) virial[r] = v[1];
+        if (ke) ke[r] = v[2];
+        if (gate) gate[r] = v[3] > lim2 ? 1u : 0u;
+    }
+}
+
+// First stage for a single replica of many tiles (one workgroup would read
+// them all): block c sums tiles [c kTileChunk, (c+1) kTileChunk) into row c
+// of out, in the same fixed order.
+constexpr int kTileChunk = 4096;
+constexpr int kTileChunkedFrom = 4 * kTileChunk;
+static_assert(kPartials == kTilePartials, "chunk sums use the per-unit partial rows");
+
+__global__ __launch_bounds__(kFin) void k_tile_chunk_sums(int n_tiles, const double *tpart,
+                                                          double *out, bool want_ke,
+                                                          bool want_gate)
+{
+    const int c = blockIdx.x;
+    double v[4];
+    tile_sums(c * kTileChunk, min((c + 1) * kTileChunk, n_tiles), tpart, want_ke, want_gate, v);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kTilePartials; ++q) out[size_t(c) * kTilePartials + q] = v[q];
 }
 
 }  // namespace
@@ -335,8 +372,8 @@ int tile_max_cells()
 
 int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const md_lj *p,
                 int32_t prec, int32_t accumulate, const int32_t *cell_start, double *energy,
-                double *virial, double *tpart, int batch, const VVFuse *vvf, uint32_t *status,
-                hipStream_t s)
+                double *virial, double *tpart, double *chunk_sums, int chunk_rows, int batch,
+                const VVFuse *vvf, uint32_t *status, hipStream_t s)
 {
     TileArgs a = tile_args(b, atoms, nl);
     a.cell_start = cell_start;
@@ -389,10 +426,19 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
     timing_end(timed, s);
     double *ke = fuse ? vvf->ke : nullptr;
     uint32_t *gate = fuse ? vvf->gate : nullptr;
-    if (energy || virial || ke || gate)
-        hipLaunchKernelGGL(k_tile_finalize, dim3(b->R), dim3(kFin), 0, s, nl->tile_off, tpart,
+    const int n_chunks = (nl->n_tiles + kTileChunk - 1) / kTileChunk;
+    if ((energy || virial || ke || gate) && b->R == 1 && nl->n_tiles >= kTileChunkedFrom &&
+        chunk_sums && n_chunks <= chunk_rows) {
+        hipLaunchKernelGGL(k_tile_chunk_sums, dim3(n_chunks), dim3(kFin), 0, s, nl->n_tiles,
+                           tpart, chunk_sums, ke != nullptr, gate != nullptr);
+        hipLaunchKernelGGL(k_tile_finalize, dim3(1), dim3(kFin), 0, s, nullptr, n_chunks,
+                           chunk_sums, energy, virial, ke, gate, fuse ? vvf->lim2 : 0.0,
+                           fuse ? vvf->step : nullptr);
+    } else if (energy || virial || ke || gate) {
+        hipLaunchKernelGGL(k_tile_finalize, dim3(b->R), dim3(kFin), 0, s, nl->tile_off, 0, tpart,
                            energy, virial, ke, gate, fuse ? vvf->lim2 : 0.0,
                            fuse ? vvf->step : nullptr);
+    }
     if (fuse && vvf->copy_back)
         hipLaunchKernelGGL(k_copy_next, dim3((b->N + kUnit - 1) / kUnit), dim3(kUnit), 0, s, b->N,
                            vvf->xn, vvf->yn, vvf->zn, atoms->x, atoms->y, atoms->z, atoms->pos4);

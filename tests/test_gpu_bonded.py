@@ -320,3 +320,27 @@ def test_fused_step_with_thermostat_equals_split_calls_and_graphs():
     assert np.abs(a.velocities() - b.velocities()).max() < 1e-9
     assert np.array_equal(a.positions(), c.positions())
     torch.cuda.synchronize()
+
+
+def test_sums_over_many_tiles_of_one_replica():
+    # a sparse droplet in a large box: one replica of more than 16384 tiles,
+    # whose energy, virial, kinetic energy and gate are summed in two stages
+    print("case: two-stage tile sums", flush=True)
+    cfg = md_inputs.lj_sphere(20000, 120.0, seed=12)
+    cfg.pos = md_inputs.jitter(cfg.pos, 0.05, seed=13)
+    s = _system(cfg, prec="fp64", mode="tile", tile_rows=(1, 1), tile_cells=1)
+    assert s.R == 1 and s.nlist.n_tiles >= 16384
+    s.setup()
+    assert s.ensure_list() == 0
+    f_ref, e_ref, w_ref = oracle.lj_forces(cfg.pos, cfg.box[0], cfg.rc, shift=1)
+    assert float(s.energy[0]) == pytest.approx(e_ref, rel=1e-10)
+    assert float(s.virial[0]) == pytest.approx(w_ref, rel=1e-10)
+    # the fused call's kinetic energy and gate against the split calls'
+    b = _system(cfg, prec="fp64", mode="tile", tile_rows=(1, 1), tile_cells=1, fuse=False)
+    b.setup()
+    for x in (s, b):
+        x.run(12, check_every=0)
+        assert x.ensure_list() == 0
+    assert np.array_equal(s.positions(), b.positions())
+    assert float(s.ke[0]) == pytest.approx(float(b.ke[0]), rel=1e-12)
+    assert float(s.energy[0]) == pytest.approx(float(b.energy[0]), rel=1e-12)
