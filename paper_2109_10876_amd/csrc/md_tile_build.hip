@@ -240,7 +240,10 @@ int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_sta
     a.rl2 = rl2;
     a.need = need;
     a.status = status;
-    const dim3 grid(gated_grid(nl->n_tiles, gate != nullptr));
+    // one workgroup per tile, gated or not: the hardware hands tiles to
+    // whichever workgroup slot frees first, so uneven tiles (vacuum, surface)
+    // balance themselves; a gated-off tile costs a launch slot only
+    const dim3 grid(nl->n_tiles);
     const bool p4 = tile_stage_packed() && atoms->pos4;
     with_tile_shape([&](auto sh) {
         using SH = decltype(sh);
