@@ -50,15 +50,15 @@ FLOPS_PER_ATOM_VV = 36
 # in); each entry: source hash of the kernel's files and calibrated bytes per
 # launch for the FP32-mixed and FP64 paths.
 COUNTED_TRAFFIC = {
-    "tile_fused": {"src_sha256_16": "3dbca71df49087ea",
-                   "bytes_per_launch": {"mixed": 422623309, "fp64": 423511483}},
-    "tile": {"src_sha256_16": "3dbca71df49087ea",
-             "bytes_per_launch": {"mixed": 319711199, "fp64": 320810102}},
+    "tile_fused": {"src_sha256_16": "9c1adc5184860695",
+                   "bytes_per_launch": {"mixed": 422519817, "fp64": 423439837}},
+    "tile": {"src_sha256_16": "9c1adc5184860695",
+             "bytes_per_launch": {"mixed": 319612705, "fp64": 320713247}},
 }
 
 FORCE_KERNEL_SOURCES = {
     "full": ("md_forces.hip", "md_pair.hpp", "md_common.hpp"),
-    "tile": ("md_tile.hip", "md_tile.hpp", "md_pair.hpp", "md_common.hpp"),
+    "tile": ("md_tile.hip", "md_tile.hpp", "md_pair.hpp", "md_philox.hpp", "md_common.hpp"),
 }
 
 
