@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 5
+#define MD_ABI_VERSION 6
 
 /* ------------------------------------------------------------ return codes */
 #define MD_OK            0
@@ -176,6 +176,15 @@ typedef struct md_nlist {
                                  md_verlet_build and read by md_lj_forces,
                                  md_lj_forces_vv and md_lj_forces_vjp (which also
                                  keeps per-tile sums in it); part of the list  */
+    int32_t *tile_active;     /* MD_TILE_FULL, optional, one replica only:
+                                 [2 n_tiles + 1], zero-filled before the first
+                                 build.  md_verlet_build lists the tiles that
+                                 have home atoms: tile_active[0] = their count,
+                                 tile_active[1 ..] the tiles in ascending order
+                                 (the rest is its bookkeeping).  md_lj_forces
+                                 and md_lj_forces_vv then give workgroups to
+                                 listed tiles only, so the vacuum of a sparse
+                                 system costs no staging.  NULL: every tile. */
 } md_nlist;
 
 /* Lennard-Jones parameters (Eq. lj: U = 4 eps [(sig/r)^12 - (sig/r)^6] for

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmd.so")
 
 # Constants mirrored from md.h.
-MD_ABI_VERSION = 5
+MD_ABI_VERSION = 6
 MD_OK = 0
 MD_EINVAL = -1
 MD_EBOX = -2
@@ -80,7 +80,8 @@ class MdNlist(ctypes.Structure):
                 ("count", _vp), ("idx", _vp), ("n_tiles", _i32), ("tile_py", _i32),
                 ("tile_pz", _i32), ("tile_types", _i32),
                 ("tile_rep", _vp), ("tile_off", _vp), ("tile_need", _vp), ("cell_start", _vp),
-                ("tile_src_cap", _i32), ("_pad", _i32), ("tile_src", _vp)]
+                ("tile_src_cap", _i32), ("_pad", _i32), ("tile_src", _vp),
+                ("tile_active", _vp)]
 
 
 class MdLj(ctypes.Structure):

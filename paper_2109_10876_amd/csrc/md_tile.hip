@@ -30,7 +30,21 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
     __shared__ TileStage<CAP, SH::MAXC> st;
     __shared__ double red[4][TB / kWave];
     __shared__ PolyConst ptab[TY ? kTileMaxTypes * kTileMaxTypes : 1];
-    const int t = xcd_chunked(blockIdx.x, gridDim.x, kTileXcdChunk);
+    // launch slot -> tile; with the occupied-tile list, slot k takes its
+    // k-th tile and writes its partials to row k, and slots past the list
+    // write an empty row and leave
+    const int lt = xcd_chunked(blockIdx.x, gridDim.x, kTileXcdChunk);
+    int t = lt;
+    if (a.active) {
+        if (lt >= a.active[0]) {
+            if (threadIdx.x == 0)
+                for (int q = 0; q < kTilePartials; ++q)
+                    a.tpart[size_t(lt) * kTilePartials + q] = 0.0;
+            return;
+        }
+        t = min(max(a.active[1 + lt], 0), a.n_tiles - 1);
+    }
+    const int row = lt;   // partial row: the tile itself, or its place in the list
     const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
     const PolyConst pc = poly_const(a.eps[0], a.sig[0], a.rc, a.shift);
     const double rc2 = a.rc * a.rc;
@@ -78,7 +92,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
             return true;
         });
     if (total < 0) {
-        if (threadIdx.x < kTilePartials) a.tpart[size_t(t) * kTilePartials + threadIdx.x] = 0.0;
+        if (threadIdx.x < kTilePartials) a.tpart[size_t(row) * kTilePartials + threadIdx.x] = 0.0;
         return;
     }
     double e_acc = 0.0, w_acc = 0.0, ke_acc = 0.0, d2_max = 0.0;
@@ -225,7 +239,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
             ks += red[2][q];
             dm = fmax(dm, red[3][q]);
         }
-        double *tp = a.tpart + size_t(t) * kTilePartials;
+        double *tp = a.tpart + size_t(row) * kTilePartials;
         tp[0] = es;
         tp[1] = ws;
         tp[2] = FUSE ? ks : 0.0;
@@ -346,6 +360,7 @@ bool tile_list_ok(const md_batch *b, const md_nlist *nl)
 {
     return nl->n_tiles >= 1 && nl->n_tiles <= b->C && nl->tile_rep && nl->tile_off &&
            (reinterpret_cast<uintptr_t>(nl->idx) & 15) == 0 && nl->tile_src &&
+           (nl->tile_active == nullptr || b->R == 1) &&
            nl->tile_src_cap == tile_capacity() &&
            nl->max_nbr % 16 == 0 && nl->ld <= kTileMaxLd && nl->tile_types >= 0 &&
            nl->tile_types <= MD_TILE_MAX_TYPES &&
@@ -386,6 +401,7 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
     a.fz = atoms->fz;
     a.accumulate = accumulate;
     a.tpart = tpart;
+    a.active = nl->tile_active;   // one replica only (checked by the callers)
     if (vvf) a.vv = *vvf;
     a.status = status;
     const dim3 grid(nl->n_tiles);

@@ -474,6 +474,7 @@ struct TileArgs {
     VVFuse vv;        // FUSE variant only
     uint32_t *status;
     int32_t R;
+    int32_t *active;  // occupied-tile list (md_nlist.tile_active) or null
 };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }

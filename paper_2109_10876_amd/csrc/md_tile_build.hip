@@ -69,7 +69,10 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
         const int t = xcd_chunked(lt, a.n_tiles, kTileXcdChunk);
         const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
         if (a.gate != nullptr && a.gate[s.rep] == 0u) continue;
-        if (tile_home_atoms(s, a.cell_start) == 0) continue;
+        const int home = tile_home_atoms(s, a.cell_start);
+        // occupancy for the occupied-tile list (listed by k_tile_compact)
+        if (a.active && threadIdx.x == 0) a.active[1 + a.n_tiles + t] = home > 0 ? 1 : 0;
+        if (home == 0) continue;
         const int total =
             stage_tile<TB, P4>(s, a.cell_start, a.x, a.y, a.z, a.pos4, st, CAP,
                                a.tile_src + size_t(t) * tab_stride(CAP), [] { return true; });
@@ -228,6 +231,39 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
 }
 
+// The occupied-tile list of one replica: the tiles whose flag the build set,
+// in ascending order, after the count.  One workgroup scans the flags in
+// passes of kFin tiles (each wave's prefix from a ballot, the waves' totals
+// from LDS).  Skipped when the gate is 0 (the list is still valid).
+__global__ __launch_bounds__(kFin) void k_tile_compact(int n_tiles, const uint32_t *gate,
+                                                       int32_t *active)
+{
+    if (gate && gate[0] == 0u) return;
+    constexpr int kW = kFin / kWave;
+    __shared__ int wsum[kW];
+    const int32_t *occ = active + 1 + n_tiles;
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    int carry = 0;
+    for (int base = 0; base < n_tiles; base += kFin) {
+        const int t = base + threadIdx.x;
+        const bool on = t < n_tiles && occ[t] != 0;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(on);
+        const int below = int(__builtin_amdgcn_mbcnt_hi(
+            uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
+        if (lane == 0) wsum[wid] = int(__popcll(m));
+        __syncthreads();
+        int before = carry, total = carry;
+        for (int w = 0; w < kW; ++w) {
+            before += w < wid ? wsum[w] : 0;
+            total += wsum[w];
+        }
+        if (on) active[1 + before + below] = t;
+        carry = total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) active[0] = carry;
+}
+
 }  // namespace
 
 int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_start, double rl2,
@@ -240,6 +276,7 @@ int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_sta
     a.rl2 = rl2;
     a.need = need;
     a.status = status;
+    a.active = nl->tile_active;   // one replica only (checked by the caller)
     // one workgroup per tile, gated or not: the hardware hands tiles to
     // whichever workgroup slot frees first, so uneven tiles (vacuum, surface)
     // balance themselves; a gated-off tile costs a launch slot only
@@ -250,6 +287,9 @@ int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_sta
         if (p4) hipLaunchKernelGGL((k_tile_build<SH, true>), grid, dim3(SH::TB), 0, s, a);
         else hipLaunchKernelGGL((k_tile_build<SH, false>), grid, dim3(SH::TB), 0, s, a);
     });
+    if (nl->tile_active)
+        hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(kFin), 0, s, nl->n_tiles, gate,
+                           nl->tile_active);
     return launch_status();
 }
 

@@ -26,6 +26,15 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _empty_cell_fraction(pos, box, ncell):
+    """Host-side launch planning: the fraction of the cells of one box that
+    hold no atom."""
+    nc = np.asarray(ncell).astype(np.int64)
+    c = np.minimum((np.mod(pos, box) * nc / box).astype(np.int64), nc - 1)
+    occ = np.unique((c[:, 2] * nc[1] + c[:, 1]) * nc[0] + c[:, 0]).shape[0]
+    return 1.0 - occ / float(np.prod(nc))
+
+
 def _occupied_cell_density(pos, natoms, box, ncell):
     """Host-side launch planning: mean atoms per non-empty cell of the cell
     grid, for the replica where it is largest."""
@@ -54,7 +63,8 @@ class MDSystem:
                  rc=2.5, skin=0.3, dt=0.005, shift=1, mode="full", prec="fp64",
                  max_nbr=None, pos4=None, bonds=None, fene=(30.0, 1.5), angles=None,
                  angle_K=1.5, bonded_order="index", langevin=None,
-                 tile_cells=None, tile_rows=(1, 1), fuse=True, device="cuda"):
+                 tile_cells=None, tile_rows=(1, 1), fuse=True, sparse_tiles=None,
+                 device="cuda"):
         self.lib = abi.load()
         self.dev = torch.device(device)
         natoms = np.asarray(natoms, dtype=np.int32).ravel()
@@ -141,6 +151,15 @@ class MDSystem:
         self.tile_need = torch.zeros(1, dtype=torch.int32, device=d)
         self.tile_cells, self.n_tiles = 0, 0
         self.tile_py, self.tile_pz = (int(tile_rows[0]), int(tile_rows[1]))
+        # occupied-tile list (one replica): on by default when most cells start
+        # empty (a droplet or slab in vacuum), so empty tiles get no workgroup
+        if sparse_tiles is None:
+            sparse_tiles = (self.mode == abi.MD_TILE_FULL and self.R == 1 and
+                            _empty_cell_fraction(pos, box[0], self.h_ncell[0]) > 0.5)
+        self.sparse_tiles = bool(sparse_tiles) and self.mode == abi.MD_TILE_FULL
+        if self.sparse_tiles and self.R != 1:
+            raise ValueError("the occupied-tile list covers one replica")
+        self.tile_active = None
         if self.mode == abi.MD_TILE_FULL:
             if tile_cells is None:
                 # cells per tile: staged neighbourhood 9 (m + 2) nu within 92% of
@@ -309,6 +328,9 @@ class MDSystem:
         self.tile_src_cap = self.lib.md_tile_capacity()
         self.tile_src = torch.zeros(n * (self.tile_src_cap + 128), dtype=torch.int32,
                                     device=self.dev)
+        if self.sparse_tiles:
+            # count, list, per-tile occupancy; written by the build
+            self.tile_active = torch.zeros(2 * n + 1, dtype=torch.int32, device=self.dev)
 
     def _alloc_list(self, max_nbr):
         self.max_nbr = (int(max_nbr) + 15) // 16 * 16   # tile lists pad to 16 entries
@@ -325,7 +347,8 @@ class MDSystem:
             self.tile_rep.data_ptr() if tiled else None,
             self.tile_off.data_ptr() if tiled else None,
             self.tile_need.data_ptr(), self.cell_start.data_ptr() if tiled else None,
-            self.tile_src_cap if tiled else 0, 0, self.tile_src.data_ptr() if tiled else None)
+            self.tile_src_cap if tiled else 0, 0, self.tile_src.data_ptr() if tiled else None,
+            self.tile_active.data_ptr() if tiled and self.tile_active is not None else None)
 
     @property
     def stream(self):

@@ -214,6 +214,15 @@ def test_tile_list_needs_a_staging_table_of_the_current_capacity():
     for bad in (nl(None, cap), nl(16, cap + 1), nl(16, 0)):
         assert lib.md_verlet_build(P(ok), P(full), 16, 2.5, 0.3, P(bad), None, None, None,
                                    None) == abi.MD_EINVAL
+    # the occupied-tile list covers one replica only
+    two = abi.MdBatch(2, 1000, 27, 4, 8, 8, 8, 8, 8, 8)
+    listed = abi.MdNlist(abi.MD_TILE_FULL, 64, 1024, 1, 16, 16, 1, 1, 1, 0, 16, 16, None, 16,
+                         cap, 0, 16, 16)
+    lj1 = abi.MdLj(1, 1, 2.5, 8, 8)
+    assert lib.md_verlet_build(P(two), P(full), 16, 2.5, 0.3, P(listed), None, None, None,
+                               None) == abi.MD_EINVAL
+    assert lib.md_lj_forces(P(two), P(full), P(listed), P(lj1), 0, 0, None, None, 8, 1 << 30,
+                            None, None) == abi.MD_EINVAL
 
 
 def test_fused_step_next_position_buffers_are_checked():

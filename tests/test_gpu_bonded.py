@@ -344,3 +344,33 @@ def test_sums_over_many_tiles_of_one_replica():
     assert np.array_equal(s.positions(), b.positions())
     assert float(s.ke[0]) == pytest.approx(float(b.ke[0]), rel=1e-12)
     assert float(s.energy[0]) == pytest.approx(float(b.energy[0]), rel=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_occupied_tile_list_on_a_droplet(prec):
+    # a droplet in vacuum: the build lists the tiles that have home atoms and
+    # the force kernels give workgroups to those only; forces, energies and a
+    # thermostatted fused trajectory equal the every-tile launch bit for bit
+    print(f"case: occupied-tile list {prec}", flush=True)
+    cfg = md_inputs.lj_sphere(2000, 30.0, seed=9)
+    cfg.pos = md_inputs.jitter(cfg.pos, 0.08, seed=11)
+    a = _system(cfg, prec=prec, mode="tile", langevin=(1.0, 0.5, 21, 0))
+    b = _system(cfg, prec=prec, mode="tile", langevin=(1.0, 0.5, 21, 0), sparse_tiles=False)
+    assert a.sparse_tiles and not b.sparse_tiles and a.fuse and b.fuse
+    for s in (a, b):
+        s.setup()
+        assert s.ensure_list() == 0
+    # the list: the tiles with home atoms, ascending
+    act = a.tile_active.cpu().numpy()
+    occupied = [t for t, (home, _) in enumerate(a.tile_slot_table()) if len(home)]
+    assert 0 < act[0] < a.n_tiles // 2
+    assert list(act[1:1 + act[0]]) == occupied
+    assert np.array_equal(a.forces_np(), b.forces_np())
+    assert float(a.energy[0]) == pytest.approx(float(b.energy[0]), rel=1e-12)
+    assert float(a.virial[0]) == pytest.approx(float(b.virial[0]), rel=1e-12)
+    for s in (a, b):
+        s.run_graphed(30, k=5)
+        assert s.ensure_list() == 0
+    assert np.array_equal(a.positions(), b.positions())
+    assert np.array_equal(a.velocities(), b.velocities())
+    assert float(a.ke[0]) == pytest.approx(float(b.ke[0]), rel=1e-12)
