@@ -374,3 +374,73 @@ def test_occupied_tile_list_on_a_droplet(prec):
     assert np.array_equal(a.positions(), b.positions())
     assert np.array_equal(a.velocities(), b.velocities())
     assert float(a.ke[0]) == pytest.approx(float(b.ke[0]), rel=1e-12)
+
+
+def _sampled_force_error(s, cfg, n_sample, seed, types=None):
+    # forces on the current positions (thermostat excluded) against O(N)
+    # oracle loops for sampled atoms of replica 0 .. R-1
+    import torch
+    s.forces()
+    torch.cuda.synchronize()
+    f = s.forces_np()
+    pos = s.positions()
+    off = cfg.atom_off()
+    rng = np.random.default_rng(seed)
+    got, ref = [], []
+    for r in range(cfg.nrep):
+        a, b = off[r], off[r + 1]
+        planes = tuple(np.ascontiguousarray(pos[a:b, k]) for k in range(3))
+        t = None if types is None else np.ascontiguousarray(types[a:b])
+        for i in rng.choice(b - a, n_sample, replace=False):
+            ref.append(oracle.lj_force_one(int(i), None, cfg.box[r], cfg.rc, cfg.eps, cfg.sig,
+                                           t, shift=cfg.shift, planes=planes)[0])
+            got.append(f[a + i])
+    got, ref = np.array(got), np.array(ref)
+    return np.linalg.norm(got - ref) / np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name", ["lj_sphere", "lj_slab"])
+def test_inhomogeneous_full_size_after_graphed_steps(name):
+    # the paper's sphere (2.58 M atoms) and the slab (500,000) in the
+    # benchmark's form: tile lists 3 x 2 x 2 with 2048 slots, the occupied-tile
+    # launch, the thermostat fused into the force call, FP32-mixed, graphed
+    print(f"case: {name} full size", flush=True)
+    from paper_2109_10876_amd import _abi as abi
+    lib = abi.load()
+    lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, 2048)
+    try:
+        cfg = md_inputs.CONFIGS[name]()
+        lang = {"lj_sphere": (1.0, 0.1, 6), "lj_slab": (1.0, 0.85, 4)}[name]
+        s = _system(cfg, langevin=lang, mode="tile", prec="mixed", tile_rows=(2, 2),
+                    tile_cells=3)
+        assert s.sparse_tiles and s.fuse
+        s.setup()
+        s.run_graphed(50, k=25)
+        assert s.ensure_list() == 0
+        err = _sampled_force_error(s, cfg, 64, seed=5)
+        print(f"  sampled e_F = {err:.3e}", flush=True)
+        assert err < 1e-5
+    finally:
+        lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, 0)
+
+
+def test_replica_batch_full_size_after_graphed_steps():
+    # the 256 uneven two-type replicas (2.62 M atoms) in the benchmark's form:
+    # typed tile lists of 1 x 2 x 2 cells with 2048 slots, FP32-mixed, graphed;
+    # sampled atoms of every replica against the oracle
+    print("case: replicas full size", flush=True)
+    from paper_2109_10876_amd import _abi as abi
+    lib = abi.load()
+    lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, 2048)
+    try:
+        cfg = md_inputs.CONFIGS["replicas"]()
+        s = _system(cfg, mode="tile", prec="mixed", tile_rows=(2, 2), tile_cells=1)
+        assert s.nlist.tile_types == 2 and not s.sparse_tiles
+        s.setup()
+        s.run_graphed(30, k=10)
+        assert s.ensure_list() == 0
+        err = _sampled_force_error(s, cfg, 2, seed=6, types=cfg.types)
+        print(f"  sampled e_F = {err:.3e}", flush=True)
+        assert err < 1e-5
+    finally:
+        lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, 0)
