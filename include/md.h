@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 6
+#define MD_ABI_VERSION 7
 
 /* ------------------------------------------------------------ return codes */
 #define MD_OK            0
@@ -383,11 +383,15 @@ int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlist *nl, cons
  *  phase 3: phase 2 immediately followed by phase 1 in one pass (ke is taken
  *           between the two half kicks).
  * inv_mass: [ntypes] device array of 1/m.  gate is required for phases 1 and
- * 3; ke is optional. */
+ * 3; ke is optional.  thermo (optional, phases 2 and 3 only, MD_EINVAL for
+ * phase 1): before its half kick each atom adds the md_langevin force, with
+ * the velocity on entry and noise counter *thermo->step (then advanced by
+ * one), to fx, fy, fz, so that the calls md_langevin then md_vv_step become
+ * one pass (the forces were evaluated at that velocity). */
 int md_vv_step(const md_batch *b, md_atoms *atoms, int32_t phase, double dt,
                const double *inv_mass, int32_t ntypes, double skin,
-               uint32_t *gate, double *ke, void *ws, size_t ws_bytes,
-               uint32_t *status, void *stream);
+               uint32_t *gate, double *ke, const md_thermostat *thermo, void *ws,
+               size_t ws_bytes, uint32_t *status, void *stream);
 
 /* Vector-Jacobian product of md_lj_forces: given G = dL/dF (planes gfx,
  * gfy, gfz, [N] each, same atom order) and gE ([R], dL/dE_r, optional),

@@ -11,7 +11,10 @@
 //
 // One thread per atom; per-unit partials of the kinetic energy (fixed-order
 // sum) and of the maximum displacement, then one workgroup per replica.
-#include "md_common.hpp"
+// With the thermostat (phases 2 and 3), each atom first adds md_langevin's
+// force to the force it is about to use, with the velocity on entry (the one
+// the forces were evaluated with) and the same Philox normals.
+#include "md_philox.hpp"
 
 namespace md {
 namespace {
@@ -20,15 +23,22 @@ struct VVArgs {
     const int32_t *atom_off, *unit_rep, *unit_off;
     double *x, *y, *z, *vx, *vy, *vz;
     double *pos4;
-    const double *fx, *fy, *fz, *xb, *yb, *zb;
+    double *fx, *fy, *fz;
+    const double *xb, *yb, *zb;
     const int32_t *type;
     const double *inv_mass;
     int32_t ntypes;
     double hdt, dt;
     double *partial;
+    // thermostat (LANG variant)
+    const int32_t *id;
+    const double *mass;
+    double gamma, kT_dt2;   // 2 T / dt
+    uint32_t seed_lo, seed_hi;
+    const uint64_t *step;
 };
 
-template <int PHASE>
+template <int PHASE, bool LANG>
 __global__ __launch_bounds__(kUnit) void k_vv(VVArgs a)
 {
     __shared__ double red[kWavesPerUnit];
@@ -38,8 +48,21 @@ __global__ __launch_bounds__(kUnit) void k_vv(VVArgs a)
     double ke = 0.0, d2 = 0.0;
     if (i < w.end) {
         const double im = a.inv_mass[a.ntypes > 1 ? a.type[i] : 0];
-        const double fx = a.fx[i], fy = a.fy[i], fz = a.fz[i];
+        double fx = a.fx[i], fy = a.fy[i], fz = a.fz[i];
         double vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
+        if (LANG) {
+            const double m = a.mass[a.ntypes > 1 ? a.type[i] : 0];
+            double g[3];
+            thermostat_normals(static_cast<uint32_t>(a.id[i]), *a.step, a.seed_lo, a.seed_hi, g);
+            const double amp = sqrt(a.gamma * m * a.kT_dt2);
+            const double gm = a.gamma * m;
+            fx += -gm * vx + amp * g[0];
+            fy += -gm * vy + amp * g[1];
+            fz += -gm * vz + amp * g[2];
+            a.fx[i] = fx;
+            a.fy[i] = fy;
+            a.fz[i] = fz;
+        }
         const double k = a.hdt * im;
         if (PHASE >= 2) {   // Integrate2 (phase 2, first half of phase 3)
             vx = fma(k, fx, vx);
@@ -78,8 +101,11 @@ __global__ __launch_bounds__(kUnit) void k_vv(VVArgs a)
 // Per replica: kinetic energy (fixed-order sum) and the rebuild gate.
 __global__ __launch_bounds__(kFin) void k_vv_finalize(const int32_t *unit_off,
                                                       const double *partial, double lim2,
-                                                      double *ke, uint32_t *gate)
+                                                      double *ke, uint32_t *gate,
+                                                      uint64_t *step)
 {
+    // the thermostat's noise counter advances after every atom has read it
+    if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += 1u;
     __shared__ double red[kFin / kWave];
     const int r = blockIdx.x;
     const int u0 = unit_off[r], u1 = unit_off[r + 1];
@@ -102,7 +128,8 @@ __global__ __launch_bounds__(kFin) void k_vv_finalize(const int32_t *unit_off,
 
 extern "C" int md_vv_step(const md_batch *b, md_atoms *atoms, int32_t phase, double dt,
                           const double *inv_mass, int32_t ntypes, double skin, uint32_t *gate,
-                          double *ke, void *ws, size_t ws_bytes, uint32_t *status, void *stream)
+                          double *ke, const md_thermostat *thermo, void *ws, size_t ws_bytes,
+                          uint32_t *status, void *stream)
 {
     using namespace md;
     (void)status;
@@ -115,21 +142,32 @@ extern "C" int md_vv_step(const md_batch *b, md_atoms *atoms, int32_t phase, dou
         return MD_EINVAL;
     if (phase != 2 && (!gate || !atoms->xb || !atoms->yb || !atoms->zb)) return MD_EINVAL;
     if (!(skin >= 0.0)) return MD_EINVAL;
+    if (thermo && (phase == 1 || !thermo->step || !thermo->mass || !atoms->id ||
+                   !(thermo->gamma >= 0.0) || !(thermo->temperature >= 0.0) || !(dt > 0.0)))
+        return MD_EINVAL;
     const WsLayout l = ws_layout(b);
     if (ws_bytes < l.total) return MD_ENOWS;
     double *partial = ws_at<double>(ws, l.partial);
     VVArgs a{b->atom_off, b->unit_rep, b->unit_off, atoms->x, atoms->y, atoms->z, atoms->vx,
              atoms->vy, atoms->vz, atoms->pos4, atoms->fx, atoms->fy, atoms->fz, atoms->xb, atoms->yb,
-             atoms->zb, atoms->type, inv_mass, ntypes, 0.5 * dt, dt, partial};
+             atoms->zb, atoms->type, inv_mass, ntypes, 0.5 * dt, dt, partial,
+             atoms->id, thermo ? thermo->mass : nullptr, thermo ? thermo->gamma : 0.0,
+             thermo ? 2.0 * thermo->temperature / dt : 0.0,
+             thermo ? static_cast<uint32_t>(thermo->seed) : 0u,
+             thermo ? static_cast<uint32_t>(thermo->seed >> 32) : 0u,
+             thermo ? thermo->step : nullptr};
     hipStream_t s = as_stream(stream);
     const dim3 grid(b->n_units), block(kUnit);
-    if (phase == 1) hipLaunchKernelGGL(k_vv<1>, grid, block, 0, s, a);
-    else if (phase == 2) hipLaunchKernelGGL(k_vv<2>, grid, block, 0, s, a);
-    else hipLaunchKernelGGL(k_vv<3>, grid, block, 0, s, a);
+    if (phase == 1) hipLaunchKernelGGL((k_vv<1, false>), grid, block, 0, s, a);
+    else if (phase == 2 && thermo) hipLaunchKernelGGL((k_vv<2, true>), grid, block, 0, s, a);
+    else if (phase == 2) hipLaunchKernelGGL((k_vv<2, false>), grid, block, 0, s, a);
+    else if (thermo) hipLaunchKernelGGL((k_vv<3, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_vv<3, false>), grid, block, 0, s, a);
     double *ke_out = phase >= 2 ? ke : nullptr;
     uint32_t *gate_out = phase != 2 ? gate : nullptr;
-    if (ke_out || gate_out)
+    uint64_t *step = thermo ? thermo->step : nullptr;
+    if (ke_out || gate_out || step)
         hipLaunchKernelGGL(k_vv_finalize, dim3(b->R), dim3(kFin), 0, s, b->unit_off, partial,
-                           0.25 * skin * skin, ke_out, gate_out);
+                           0.25 * skin * skin, ke_out, gate_out, step);
     return launch_status();
 }

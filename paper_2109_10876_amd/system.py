@@ -282,6 +282,10 @@ class MDSystem:
             gamma, temp, seed = self.langevin_cfg
             self.thermo = abi.MdThermostat(gamma, temp, seed, self.noise_step.data_ptr(),
                                            self.mass_t.data_ptr())
+        # without the fused call, the thermostat force of a step is added by
+        # the half kick that uses it (md_vv_step with the thermostat), not by
+        # a separate md_langevin call; only the initial forces call it
+        self.vv_thermo = self.thermo is not None and not self.fuse
         if self.fuse and self.pos4 is None:
             self._pos.append((z64(), z64(), z64()))
             self._atoms.append(self._atoms_struct(self._pos[1]))
@@ -399,9 +403,11 @@ class MDSystem:
             self._par ^= 1   # the next positions are now the current ones
 
     def vv(self, phase):
+        thermo = self.thermo if self.vv_thermo and phase >= 2 else None
         check("md_vv_step", self.lib.md_vv_step(
             ctypes.byref(self.batch), ctypes.byref(self.atoms), int(phase), self.dt,
             _ptr(self.inv_mass), self.ntypes, self.skin, _ptr(self.gate), _ptr(self.ke),
+            ctypes.byref(thermo) if thermo is not None else None,
             _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
 
     def vjp(self, gfx, gfy, gfz, gE, gx, geps=None, gsig=None):
@@ -430,15 +436,16 @@ class MDSystem:
             gamma, temp, self.dt, seed, _ptr(self.noise_step), _ptr(self.status),
             self.stream))
 
-    def all_forces(self):
+    def all_forces(self, initial=False):
         """Pair forces, then (if configured) bond and angle forces and the
-        thermostat."""
+        thermostat (which the next half kick adds instead, except for the
+        initial forces, when the split calls are used)."""
         self.forces()
         if self.bonds is not None:
             self.fene()
         if self.angles is not None:
             self.angle()
-        if self.langevin_cfg is not None:
+        if self.langevin_cfg is not None and (initial or not self.vv_thermo):
             self.langevin()
 
     # ------------------------------------------------------------ the step
@@ -447,7 +454,7 @@ class MDSystem:
         self.sort(gated=False)
         self.build(gated=False)
         self.ensure_list()
-        self.all_forces()
+        self.all_forces(initial=True)
 
     def ensure_list(self):
         """Synchronise; on list overflow grow max_nbr and rebuild every replica."""

@@ -141,7 +141,8 @@ def test_calls_reject_bad_arguments_without_a_gpu():
     assert lib.md_cell_sort(P(bad), P(atoms), P(atoms), None, None, 0, None, None, None) == abi.MD_EINVAL
     assert lib.md_verlet_build(P(bad), P(atoms), None, 2.5, 0.3, P(nl), None, None, None, None) == abi.MD_EINVAL
     assert lib.md_lj_forces(P(bad), P(atoms), P(nl), P(lj), 0, 0, None, None, None, 0, None, None) == abi.MD_EINVAL
-    assert lib.md_vv_step(P(bad), P(atoms), 1, 0.005, None, 1, 0.3, None, None, None, 0, None, None) == abi.MD_EINVAL
+    assert lib.md_vv_step(P(bad), P(atoms), 1, 0.005, None, 1, 0.3, None, None, None, None, 0,
+                          None, None) == abi.MD_EINVAL
     assert lib.md_lj_forces_vjp(P(bad), P(atoms), P(nl), P(lj), 0, None, None, None, None, None,
                                 None, None, None, 0, None, None) == abi.MD_EINVAL
     assert lib.md_workspace_bytes(P(bad)) == 0
@@ -160,7 +161,16 @@ def test_calls_reject_bad_arguments_without_a_gpu():
     assert lib.md_lj_forces(P(ok), P(full), P(nl), P(lj1), 0, 0, None, None, 8, 16, None, None) == abi.MD_ENOWS
     assert lib.md_lj_forces_vjp(P(ok), P(full), P(nl), P(lj1), 0, 8, 8, 8, None, 8, None, None,
                                 8, 1 << 30, None, None) == abi.MD_EUNSUPPORTED
-    assert lib.md_vv_step(P(ok), P(full), 4, 0.005, 8, 1, 0.3, 8, None, 8, 1 << 30, None, None) == abi.MD_EINVAL
+    assert lib.md_vv_step(P(ok), P(full), 4, 0.005, 8, 1, 0.3, 8, None, None, 8, 1 << 30, None,
+                          None) == abi.MD_EINVAL
+    # a thermostat only with the phases that kick with the force, and complete
+    th = abi.MdThermostat(0.5, 1.0, 7, 8, 8)
+    assert lib.md_vv_step(P(ok), P(full), 1, 0.005, 8, 1, 0.3, 8, None, P(th), 8, 1 << 30, None,
+                          None) == abi.MD_EINVAL
+    for bad_th in (abi.MdThermostat(0.5, 1.0, 7, None, 8), abi.MdThermostat(0.5, 1.0, 7, 8, None),
+                   abi.MdThermostat(-1.0, 1.0, 7, 8, 8), abi.MdThermostat(0.5, -1.0, 7, 8, 8)):
+        assert lib.md_vv_step(P(ok), P(full), 3, 0.005, 8, 1, 0.3, 8, None, P(bad_th), 8,
+                              1 << 30, None, None) == abi.MD_EINVAL
 
 
 def test_angle_forces_reject_bad_arguments_without_a_gpu():
