@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 7
+#define MD_ABI_VERSION 8
 
 /* ------------------------------------------------------------ return codes */
 #define MD_OK            0
@@ -438,6 +438,17 @@ int md_fene_forces(const md_batch *b, const md_atoms *atoms, const md_bonds *bon
 int md_angle_forces(const md_batch *b, const md_atoms *atoms, const md_angles *angles,
                     double K, double *energy, double *virial, void *ws, size_t ws_bytes,
                     uint32_t *status, void *stream);
+
+/* md_fene_forces and md_angle_forces in one pass over the atoms, for tables
+ * keyed by index (md_bonded_reindex; MD_EINVAL otherwise): each atom sums its
+ * bonds (K, R0) and its angle triples (Ka) and updates its force once.  The
+ * results equal the two calls in sequence bit for bit (forces, flags, and
+ * the energy/virial outputs of each term, all optional). */
+int md_bonded_forces(const md_batch *b, const md_atoms *atoms, const md_bonds *bonds,
+                     double K, double R0, const md_angles *angles, double Ka,
+                     double *energy_bond, double *virial_bond, double *energy_angle,
+                     double *virial_angle, void *ws, size_t ws_bytes, uint32_t *status,
+                     void *stream);
 
 /* Bonded tables in the atoms' current (cell-sorted) order: for every atom
  * at index i of a replica whose gate is set (every replica when gate is

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmd.so")
 
 # Constants mirrored from md.h.
-MD_ABI_VERSION = 7
+MD_ABI_VERSION = 8
 MD_OK = 0
 MD_EINVAL = -1
 MD_EBOX = -2
@@ -56,7 +56,7 @@ EXPORTS = (
     "md_tile_plan",
     "md_workspace_bytes", "md_cell_sort", "md_verlet_build", "md_lj_forces",
     "md_vv_step", "md_lj_forces_vv", "md_lj_forces_vjp", "md_fene_forces", "md_angle_forces",
-    "md_bonded_reindex", "md_langevin",
+    "md_bonded_forces", "md_bonded_reindex", "md_langevin",
 )
 
 _vp = ctypes.c_void_p
@@ -173,6 +173,9 @@ def load():
     lib.md_angle_forces.restype = ctypes.c_int
     lib.md_angle_forces.argtypes = [P(MdBatch), P(MdAtoms), P(MdAngles), _dbl, _vp, _vp, _vp,
                                     ctypes.c_size_t, _vp, _vp]
+    lib.md_bonded_forces.restype = ctypes.c_int
+    lib.md_bonded_forces.argtypes = [P(MdBatch), P(MdAtoms), P(MdBonds), _dbl, _dbl, P(MdAngles),
+                                     _dbl, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
     lib.md_bonded_reindex.restype = ctypes.c_int
     lib.md_bonded_reindex.argtypes = [P(MdBatch), P(MdAtoms), P(MdBonds), _vp, _vp, P(MdAngles),
                                       _vp, _vp, _vp, _vp]

@@ -18,7 +18,7 @@
 // still sit in nearby cells.
 #include <cmath>
 
-#include "md_common.hpp"
+#include "md_bonded.hpp"
 
 namespace md {
 namespace {
@@ -45,68 +45,17 @@ __global__ __launch_bounds__(kUnit) void k_angle(AngleArgs a)
     // column of the table: an atom id (ids of a replica span its range) or
     // the current index
     const int me = w.begin + threadIdx.x;
-    double e = 0.0, vir = 0.0;
+    BondedSum sum{0.0, 0.0, 0.0, 0.0, 0.0};
     if (me < w.end) {
-        const double Lx = a.box[3 * w.rep], Ly = a.box[3 * w.rep + 1], Lz = a.box[3 * w.rep + 2];
-        // d/L through the reciprocal rounds to the same image as the
-        // division except within rounding of |d| = L/2, where the image is
-        // ambiguous anyway
-        const double ix = 1.0 / Lx, iy = 1.0 / Ly, iz = 1.0 / Lz;
         const int i = ORDER == MD_BY_ID ? a.where[me] : me;
-        const int nt = min(a.acount[me], a.max_angles);
-        double fx = 0.0, fy = 0.0, fz = 0.0;
-        bool bad = false;
-        for (int k = 0; k < nt; ++k) {
-            const size_t row = size_t(3 * k) * a.N + me;
-            const int ia = a.tri[row], ib = a.tri[row + a.N], ic = a.tri[row + 2 * size_t(a.N)];
-            const int pa = ORDER == MD_BY_ID ? a.where[ia] : ia;
-            const int pb = ORDER == MD_BY_ID ? a.where[ib] : ib;
-            const int pc = ORDER == MD_BY_ID ? a.where[ic] : ic;
-            double d1x = a.x[pa] - a.x[pb], d1y = a.y[pa] - a.y[pb], d1z = a.z[pa] - a.z[pb];
-            double d2x = a.x[pc] - a.x[pb], d2y = a.y[pc] - a.y[pb], d2z = a.z[pc] - a.z[pb];
-            d1x -= Lx * rint(d1x * ix);
-            d1y -= Ly * rint(d1y * iy);
-            d1z -= Lz * rint(d1z * iz);
-            d2x -= Lx * rint(d2x * ix);
-            d2y -= Ly * rint(d2y * iy);
-            d2z -= Lz * rint(d2z * iz);
-            const double r11 = d1x * d1x + d1y * d1y + d1z * d1z;
-            const double r22 = d2x * d2x + d2y * d2y + d2z * d2z;
-            if (!(r11 > 0.0) || !(r22 > 0.0)) {
-                bad = true;
-                continue;
-            }
-            const double inv12 = 1.0 / sqrt(r11 * r22);
-            const double c = (d1x * d2x + d1y * d2y + d1z * d2z) * inv12;
-            // F_a = -K (d2 inv12 - c d1 / r11), F_c = -K (d1 inv12 - c d2 / r22)
-            const double qa = c / r11, qc = c / r22;
-            const double fax = -a.K * (d2x * inv12 - qa * d1x);
-            const double fay = -a.K * (d2y * inv12 - qa * d1y);
-            const double faz = -a.K * (d2z * inv12 - qa * d1z);
-            const double fcx = -a.K * (d1x * inv12 - qc * d2x);
-            const double fcy = -a.K * (d1y * inv12 - qc * d2y);
-            const double fcz = -a.K * (d1z * inv12 - qc * d2z);
-            if (me == ia) {
-                fx += fax;
-                fy += fay;
-                fz += faz;
-            } else if (me == ic) {
-                fx += fcx;
-                fy += fcy;
-                fz += fcz;
-            } else {
-                fx -= fax + fcx;
-                fy -= fay + fcy;
-                fz -= faz + fcz;
-                e += a.K * (1.0 + c);
-                vir += d1x * fax + d1y * fay + d1z * faz + d2x * fcx + d2y * fcy + d2z * fcz;
-            }
-        }
-        a.fx[i] += fx;
-        a.fy[i] += fy;
-        a.fz[i] += fz;
-        if (bad && a.status) atomicOr(a.status, MD_F_NONFINITE);
+        const bool ok = angle_atom<ORDER>(me, a.x, a.y, a.z, a.where, a.acount, a.tri,
+                                          a.max_angles, a.N, a.K, bond_box(a.box, w.rep), sum);
+        a.fx[i] += sum.fx;
+        a.fy[i] += sum.fy;
+        a.fz[i] += sum.fz;
+        if (!ok && a.status) atomicOr(a.status, MD_F_NONFINITE);
     }
+    const double e = sum.e, vir = sum.w;
     const double es = block_sum(e, red);
     const double ws = block_sum(vir, red);
     if (threadIdx.x == 0) {

@@ -9,7 +9,7 @@
 // id is reached through id[i] and names partners by id (found through
 // where[]); a table keyed by index (md_bonded_reindex) is read coalesced and
 // names the partners' indices directly.
-#include "md_common.hpp"
+#include "md_bonded.hpp"
 
 namespace md {
 namespace {
@@ -34,43 +34,18 @@ __global__ __launch_bounds__(kUnit) void k_fene(FeneArgs a)
     const int u = blockIdx.x;
     const Unit w = unit_of(u, a.unit_rep, a.unit_off, a.atom_off);
     const int i = w.begin + threadIdx.x;
-    double e = 0.0, vir = 0.0;
+    BondedSum sum{0.0, 0.0, 0.0, 0.0, 0.0};
     if (i < w.end) {
-        const double Lx = a.box[3 * w.rep], Ly = a.box[3 * w.rep + 1], Lz = a.box[3 * w.rep + 2];
-        // d/L through the reciprocal rounds to the same image as the
-        // division except within rounding of |d| = L/2, where the image is
-        // ambiguous anyway
-        const double ix = 1.0 / Lx, iy = 1.0 / Ly, iz = 1.0 / Lz;
-        const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
         const int me = ORDER == MD_BY_ID ? a.id[i] : i;   // column of the table
-        const int nb = min(a.bcount[me], a.max_bonds);
-        double fx = 0.0, fy = 0.0, fz = 0.0;
-        bool broken = false;
-        for (int k = 0; k < nb; ++k) {
-            const int p = a.bpartner[size_t(k) * a.N + me];
-            const int j = ORDER == MD_BY_ID ? a.where[p] : p;
-            double dx = xi - a.x[j], dy = yi - a.y[j], dz = zi - a.z[j];
-            dx -= Lx * rint(dx * ix);
-            dy -= Ly * rint(dy * iy);
-            dz -= Lz * rint(dz * iz);
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double q = 1.0 - r2 / a.R02;
-            if (!(q > 0.0)) {
-                broken = true;
-                continue;
-            }
-            const double fr = -a.K / q;
-            fx = fma(fr, dx, fx);
-            fy = fma(fr, dy, fy);
-            fz = fma(fr, dz, fz);
-            e += -0.25 * a.K * a.R02 * log(q);
-            vir += 0.5 * fr * r2;
-        }
-        a.fx[i] += fx;
-        a.fy[i] += fy;
-        a.fz[i] += fz;
-        if (broken && a.status) atomicOr(a.status, MD_F_BOND_BROKEN);
+        const bool ok = fene_atom<ORDER>(i, me, a.x, a.y, a.z, a.where, a.bcount, a.bpartner,
+                                         a.max_bonds, a.N, a.K, a.R02, bond_box(a.box, w.rep),
+                                         sum);
+        a.fx[i] += sum.fx;
+        a.fy[i] += sum.fy;
+        a.fz[i] += sum.fz;
+        if (!ok && a.status) atomicOr(a.status, MD_F_BOND_BROKEN);
     }
+    const double e = sum.e, vir = sum.w;
     const double es = block_sum(e, red);
     const double ws = block_sum(vir, red);
     if (threadIdx.x == 0) {

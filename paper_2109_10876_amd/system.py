@@ -423,6 +423,15 @@ class MDSystem:
             self.fene_K, self.fene_R0, _ptr(self.energy_bond), _ptr(self.virial_bond),
             _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
 
+    def bonded(self):
+        """FENE bonds and angle triples in one call (tables keyed by index)."""
+        check("md_bonded_forces", self.lib.md_bonded_forces(
+            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self._bonds_k),
+            self.fene_K, self.fene_R0, ctypes.byref(self._angles_k), self.angle_K,
+            _ptr(self.energy_bond), _ptr(self.virial_bond), _ptr(self.energy_angle),
+            _ptr(self.virial_angle), _ptr(self.ws), self.ws_bytes, _ptr(self.status),
+            self.stream))
+
     def angle(self):
         check("md_angle_forces", self.lib.md_angle_forces(
             ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self._angles_k),
@@ -441,10 +450,13 @@ class MDSystem:
         thermostat (which the next half kick adds instead, except for the
         initial forces, when the split calls are used)."""
         self.forces()
-        if self.bonds is not None:
-            self.fene()
-        if self.angles is not None:
-            self.angle()
+        if self.bonds is not None and self.angles is not None and self.bonded_by_index:
+            self.bonded()
+        else:
+            if self.bonds is not None:
+                self.fene()
+            if self.angles is not None:
+                self.angle()
         if self.langevin_cfg is not None and (initial or not self.vv_thermo):
             self.langevin()
 

@@ -309,3 +309,19 @@ def test_bonded_tables_check_their_order_without_a_gpu():
                                  None) == abi.MD_EINVAL
     assert lib.md_bonded_reindex(P(abi.MdBatch()), P(full), P(bid), 8, 8, None, None, None, None,
                                  None) == abi.MD_EINVAL
+    # the one-pass bonded call: both tables keyed by index
+    bix = abi.MdBonds(2, abi.MD_BY_INDEX, 8, 8)
+    aix = abi.MdAngles(3, abi.MD_BY_INDEX, 8, 8)
+
+    def bonded(bb, aa, K=30.0, R0=1.5, Ka=1.5, ws_bytes=big):
+        return lib.md_bonded_forces(P(ok), P(full), P(bb) if bb else None, K, R0,
+                                    P(aa) if aa else None, Ka, None, None, None, None, 8,
+                                    ws_bytes, None, None)
+
+    assert bonded(bid, aix) == abi.MD_EINVAL
+    assert bonded(bix, aid) == abi.MD_EINVAL
+    assert bonded(None, aix) == abi.MD_EINVAL and bonded(bix, None) == abi.MD_EINVAL
+    assert bonded(bix, aix, Ka=-1.0) == abi.MD_EINVAL
+    assert bonded(bix, aix, Ka=float("inf")) == abi.MD_EINVAL
+    assert bonded(bix, aix, R0=0.0) == abi.MD_EINVAL
+    assert bonded(bix, aix, ws_bytes=16) == abi.MD_ENOWS

@@ -444,3 +444,28 @@ def test_replica_batch_full_size_after_graphed_steps():
         assert err < 1e-5
     finally:
         lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, 0)
+
+
+def test_bonded_forces_equal_the_separate_calls():
+    # md_bonded_forces (FENE and angles in one pass) against md_fene_forces
+    # then md_angle_forces on the same state: forces and energies bit for bit
+    import torch
+    print("case: combined bonded call", flush=True)
+    cfg = _rings((8, 8, 8), 41, jit=0.05)
+    s = _system(cfg)
+    s.setup()
+    s.run(20, check_every=0)
+    assert s.ensure_list() == 0
+    out = []
+    for combined in (True, False):
+        s.forces()
+        if combined:
+            s.bonded()
+        else:
+            s.fene()
+            s.angle()
+        torch.cuda.synchronize()
+        out.append((s.forces_np(), float(s.energy_bond[0]), float(s.virial_bond[0]),
+                    float(s.energy_angle[0]), float(s.virial_angle[0])))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1:] == out[1][1:]
