@@ -319,6 +319,10 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy five times (the "
                          "calibration kernel for HBM byte counters) and exit")
+    ap.add_argument("--workload", default=None,
+                    choices=["kg_melt", "ring_melt", "lj_slab", "lj_sphere", "replicas"],
+                    help="only time this secondary workload (autotuned, graphed, "
+                         "--steps steps) and print its JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -328,6 +332,10 @@ def main():
     import torch
     import md_inputs
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload:
+        out = time_workload(args.workload, args.steps, warmup=args.warmup)
+        print(json.dumps({"workload": args.workload, **out}), flush=True)
+        return
     if args.copy_probe:
         src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")   # 512 MiB
         dst = torch.empty_like(src)
