@@ -1,7 +1,10 @@
-"""GPU parity of the polymer-melt and slab pieces: purely repulsive LJ (the
-LJ kernel with rc = 2^(1/6), energy shifted), FENE bonds, the cosine angle
-term of the ring melt and the Langevin thermostat, against the FP64 oracle
-(same Philox noise stream)."""
+"""GPU parity of the polymer melts and the systems in vacuum: purely
+repulsive LJ (the LJ kernel with rc = 2^(1/6), energy shifted), FENE bonds,
+the cosine angle term of the ring melt (tables keyed by id or by index, the
+one-pass bonded call), the Langevin thermostat in each of its placements
+(own call, half kick, fused force call), the occupied-tile launch and the
+two-stage tile sums, against the FP64 oracle (same Philox noise stream),
+including the full-size sphere, slab, ring melt and replica batch."""
 import numpy as np
 import pytest
 
