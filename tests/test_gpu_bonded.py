@@ -472,3 +472,35 @@ def test_bonded_forces_equal_the_separate_calls():
                     float(s.energy_angle[0]), float(s.virial_angle[0])))
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][1:] == out[1][1:]
+
+
+def test_half_kick_with_thermostat_equals_langevin_then_half_kick():
+    # md_vv_step with the thermostat against md_langevin followed by the plain
+    # md_vv_step, from the same state and noise counter (phases 3 and 2)
+    import torch
+    print("case: half kick with thermostat", flush=True)
+    cfg = md_inputs.lattice_chains((8, 8, 10), 40, seed=6, temperature=1.0)
+    for phase in (3, 2):
+        out = []
+        for inside in (True, False):
+            s = _system(cfg, langevin=(0.5, 1.2, 77, 3))
+            assert s.vv_thermo
+            s.setup()
+            s.run(5, check_every=0)
+            s.forces()
+            s.fene()
+            if inside:
+                s.vv(phase)
+            else:
+                s.langevin()
+                s.vv_thermo = False
+                s.vv(phase)
+            torch.cuda.synchronize()
+            out.append((s.positions(), s.velocities(), s.forces_np(), float(s.ke[0]),
+                        int(s.noise_step.item())))
+        a, b = out
+        assert a[4] == b[4]
+        np.testing.assert_allclose(a[2], b[2], rtol=1e-14, atol=1e-12)
+        np.testing.assert_allclose(a[1], b[1], rtol=1e-14, atol=1e-14)
+        np.testing.assert_allclose(a[0], b[0], rtol=1e-15, atol=1e-14)
+        assert a[3] == pytest.approx(b[3], rel=1e-14)
