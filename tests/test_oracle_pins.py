@@ -303,6 +303,17 @@ def test_vjp_energy_only_is_minus_force():
     np.testing.assert_allclose(gx, -gE * f, rtol=1e-12, atol=1e-12)
 
 
+def test_vjp_force_jacobian_is_symmetric():
+    # F = -grad E, so dF/dx is minus the Hessian and symmetric: with the
+    # position VJP gx(u) = u^T dF/dx, u . gx(v) = v . gx(u) for any u, v
+    pos, box, types, eps, sig, u = _vjp_case(6)
+    v = np.random.default_rng(7).normal(size=pos.shape)
+    gu, _, _ = oracle.lj_vjp(pos, box, RC, u, 0.0, eps, sig, types, 1)
+    gv, _, _ = oracle.lj_vjp(pos, box, RC, v, 0.0, eps, sig, types, 1)
+    a, b = float(np.sum(v * gu)), float(np.sum(u * gv))
+    assert a == pytest.approx(b, rel=1e-11)
+
+
 def test_vjp_eps_homogeneity_and_sigma_euler():
     pos, box, types, eps, sig, G = _vjp_case(5)
     gE = 0.9
