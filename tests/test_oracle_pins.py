@@ -198,6 +198,22 @@ def _small_md(m=4, T=0.72, seed=11):
     return pos, vel, box
 
 
+def test_skin_rule_keeps_the_list_valid_and_a_skipped_rebuild_is_caught():
+    # the rebuild rule (rebuild once an atom moved more than skin/2): while it
+    # has not fired, every pair within rc is in the list built with rc + skin;
+    # a list kept past the point where it fires misses pairs, which the
+    # containment check the GPU tests use then reports
+    pos, vel, box = _small_md(T=1.5, seed=3)
+    lst = set(map(tuple, oracle.pairs_cells(pos, box, RC + SKIN)))
+    r = oracle.md_run(pos, vel, box, RC, SKIN, 0.005, 60)
+    first = int(np.argmax(r["rebuild"])) if r["rebuild"].any() else None
+    assert first is not None and first > 0
+    ok = oracle.md_run(pos, vel, box, RC, SKIN, 0.005, first)
+    assert set(map(tuple, oracle.pairs_cells(ok["pos"], box, RC))) <= lst
+    late = oracle.md_run(pos, vel, box, RC, SKIN, 0.005, 60)
+    assert not set(map(tuple, oracle.pairs_cells(late["pos"], box, RC))) <= lst
+
+
 def test_vv_time_reversible():
     pos, vel, box = _small_md()
     a = oracle.md_run(pos, vel, box, RC, SKIN, 0.005, 40)
