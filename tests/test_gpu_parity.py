@@ -708,3 +708,24 @@ def test_tile_vjp_equals_global_vjp_one_type(prec):
     assert out["tile"][2] == pytest.approx(out["full"][2], rel=tol * 10)
     gx_r, ge_r, gs_r = oracle.lj_vjp(cfg.pos, cfg.box[0], RC, G, 0.7, shift=1)
     assert _err(out["tile"][0], gx_r) < (1e-11 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("mode,prec", [("full", "fp64"), ("tile", "mixed"), ("half", "fp64")])
+def test_coincident_atoms_raise_the_nonfinite_flag(mode, prec):
+    # two atoms at one position: the pair term is not finite, the force call
+    # says so in the status word (nothing is clamped silently)
+    import torch
+    from paper_2109_10876_amd import _abi as abi
+    cfg = md_inputs.lj_fluid(6, temperature=1.0, seed=8)
+    cfg.pos = cfg.pos.copy()
+    say(f"case: coincident atoms {mode} {prec}")
+    clean = _system(cfg, mode=mode, prec=prec)
+    clean.setup()
+    assert not (clean.ensure_list() & abi.MD_F_NONFINITE)
+    cfg.pos[1] = cfg.pos[0]
+    s = _system(cfg, mode=mode, prec=prec)
+    s.sort(gated=False)
+    s.build(gated=False)
+    s.forces()
+    torch.cuda.synchronize()
+    assert int(s.status.item()) & abi.MD_F_NONFINITE
