@@ -98,31 +98,34 @@ __device__ __forceinline__ PolyConst poly_const(double eps, double sig, double r
     return p;
 }
 
-// Pair terms of one displacement evaluated unconditionally and masked with
-// selects (no branch: in a wavefront most entries fall inside the cutoff
-// anyway).  The cutoff test is in double.  A masked entry adds exact zeros;
-// its own arithmetic may overflow but is never selected.
+// Pair terms of one displacement inside the cutoff (the test is in double);
+// entries beyond it (up to rc + skin, or the far pad slot) add nothing.  In a
+// wavefront almost every entry has some lane inside the cutoff, so this is
+// one exec-masked pass over the pair arithmetic per entry.  Written as a
+// branch around every accumulation rather than as selects of the results:
+// the compiler then needs no zeros for the lanes outside (10-12% fewer
+// vector instructions per entry) and the sums are the same bit for bit.
 template <int PREC>
 __device__ __forceinline__ void lj_pair_masked(const PolyConst &pc, double dx, double dy,
                                                double dz, double rc2, Acc &c)
 {
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const bool in = r2 < rc2;
+    if (!(r2 < rc2)) return;
     double fr;
     if (PREC == MD_FP64) {
         const double q = rcp_f64(r2);
         const double q3 = q * q * q;
         const double w = q3 * (pc.A * q3 - pc.B);
-        fr = in ? w * q : 0.0;
-        c.ed += in ? q3 * (pc.C * q3 - pc.D) - pc.ush : 0.0;
+        fr = w * q;
+        c.ed += q3 * (pc.C * q3 - pc.D) - pc.ush;
         c.wd = fma(fr, r2, c.wd);
     } else {
         const float r2f = static_cast<float>(r2);
         const float q = __builtin_amdgcn_rcpf(r2f);
         const float q3 = q * q * q;
         const float w = q3 * fmaf(pc.Af, q3, -pc.Bf);
-        const float frf = in ? w * q : 0.0f;
-        c.ef += in ? fmaf(q3, fmaf(pc.Cf, q3, -pc.Df), -pc.ushf) : 0.0f;
+        const float frf = w * q;
+        c.ef += fmaf(q3, fmaf(pc.Cf, q3, -pc.Df), -pc.ushf);
         c.wf = fmaf(frf, r2f, c.wf);
         fr = static_cast<double>(frf);
     }
@@ -161,6 +164,8 @@ __device__ __forceinline__ void lj_pair_ab(const PairAB<PREC> &k, double dx, dou
                                            double dz, double rc2, Acc &c)
 {
     const double r2 = dx * dx + dy * dy + dz * dz;
+    // selects here, not the branch of lj_pair_masked: with per-lane constants
+    // the branch form made the two-type kernel 5% slower
     const bool in = r2 < rc2;
     double fr;
     if constexpr (PREC == MD_FP64) {
