@@ -50,10 +50,10 @@ FLOPS_PER_ATOM_VV = 36
 # in); each entry: source hash of the kernel's files and calibrated bytes per
 # launch for the FP32-mixed and FP64 paths.
 COUNTED_TRAFFIC = {
-    "tile_fused": {"src_sha256_16": "28ac7748aacb6ac4",
-                   "bytes_per_launch": {"mixed": 422628123, "fp64": 423287547}},
-    "tile": {"src_sha256_16": "28ac7748aacb6ac4",
-             "bytes_per_launch": {"mixed": 319549517, "fp64": 320374309}},
+    "tile_fused": {"src_sha256_16": "083378e90d437c89",
+                   "bytes_per_launch": {"mixed": 420817368, "fp64": 422103553}},
+    "tile": {"src_sha256_16": "083378e90d437c89",
+             "bytes_per_launch": {"mixed": 317950414, "fp64": 319368176}},
 }
 
 FORCE_KERNEL_SOURCES = {
