@@ -155,6 +155,34 @@ def test_forces_cells_equal_brute_definition():
     assert w1 == pytest.approx(w2, rel=1e-13)
 
 
+@pytest.mark.parametrize("shift", [0, 1])
+@pytest.mark.parametrize("typed", [False, True])
+def test_force_one_equals_brute_rows_and_shares_sum_to_totals(shift, typed):
+    # The single-atom loop (the reference of every sampled full-size check)
+    # against the plainest definition, Eq. lj summed over all j != i: row i
+    # bit for bit, and the half shares of E and W summed over i give E and W.
+    pos, box = _snapshot(m=4, seed=11)
+    n = pos.shape[0]
+    kw = {}
+    if typed:
+        rng = np.random.default_rng(4)
+        kw = dict(types=rng.integers(0, 2, n).astype(np.int32),
+                  eps=np.array([[1.0, 0.87], [0.87, 1.15]]),
+                  sig=np.array([[1.0, 1.08], [1.08, 0.93]]))
+    f, e, w = oracle.lj_forces_brute(pos, box, RC, shift=shift, **kw)
+    planes = tuple(np.ascontiguousarray(pos[:, k]) for k in range(3))
+    es = ws = 0.0
+    for i in range(n):
+        fi, ei, wi = oracle.lj_force_one(i, pos, box, RC, shift=shift, planes=planes, **kw)
+        assert np.array_equal(fi, f[i]), i
+        es += ei
+        ws += wi
+    assert es == pytest.approx(e, rel=1e-13)
+    assert ws == pytest.approx(w, rel=1e-13)
+    # the forces are not trivially zero on this snapshot
+    assert np.abs(f).max() > 1.0
+
+
 def test_newton_third_law_and_translation_invariance():
     pos, box = _snapshot(m=4, seed=3)
     f, e, w = oracle.lj_forces(pos, box, RC)
