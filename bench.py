@@ -31,12 +31,22 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
 # lane (the 157.3 TFLOP/s FP32 figure needs packed two-wide FP32, which this
 # code does not use).
 VALU_PEAK_TFLOPS = 78.6
-# Algorithmic flops of the pair loop: every list entry pays the displacement
-# (3), r^2 (5) and the cutoff test (1); every pair inside rc the LJ terms:
-# 1/r^2 (1), q^3 (2), w = q^3 (A q^3 - B) (3), fr = w q (1), force
-# accumulation (6), energy (5) and virial (2).
+# Algorithmic flops of the method's pair work, each unordered pair once (a
+# half list with Newton's third law, Sec. 2.1.2): every half-list entry pays
+# the displacement (3), r^2 (5) and the cutoff test (1); every pair inside rc
+# the LJ terms: 1/r^2 (1), q^3 (2), w = q^3 (A q^3 - B) (3), fr = w q (1),
+# force accumulation (6), energy (5) and virial (2).
 FLOPS_PER_ENTRY = 9
 FLOPS_PER_PAIR_IN_RC = 20
+# Algorithmic HBM bytes of one force evaluation per atom (the half-list
+# minimum): 4 B per half-list entry (int32 index), the count (4), own FP64
+# position (24) and FP64 force write (24), neighbour positions being cache-
+# or LDS-resident after the spatial sort.  Fused with the integrator: also
+# the velocity read and write, the build-time position read and the next
+# position write (4 x 24 B).
+BYTES_PER_HALF_ENTRY = 4
+BYTES_PER_ATOM_FORCE = 52
+BYTES_PER_ATOM_VV_FUSED = 96
 # Velocity-Verlet work per atom when fused into the force kernel: two half
 # kicks (2 x 6), kinetic energy (8), drift (6), displacement from the build
 # positions and its running maximum (9), and the step factor (1).
@@ -99,46 +109,54 @@ def pairs_within_rc(s):
     return n
 
 
-def sampled_force_error(pos, f, box, rc, nsample=32, seed=0):
-    """Normwise relative force error of GPU forces ``f`` (by atom id) against
-    the FP64 oracle's O(N) loop on sampled atoms (CPU-baseline leg)."""
-    import oracle
-    rng = np.random.default_rng(seed)
-    planes = tuple(np.ascontiguousarray(pos[:, k]) for k in range(3))
-    smp = rng.choice(pos.shape[0], nsample, replace=False)
-    ref = np.array([oracle.lj_force_one(i, None, box, rc, planes=planes)[0] for i in smp])
-    return float(np.linalg.norm(f[smp] - ref) / np.linalg.norm(ref))
+def graph_length(steps, cap=50):
+    """Steps per captured graph for a run of ``steps`` steps: the first step's
+    head runs eagerly, so up to steps - 1 repeated steps are replayed; an even
+    number (the fused call alternates two position buffers), at most cap."""
+    return max(2, min(cap, (steps - 1) // 2 * 2))
 
 
-def time_path(cfg, prec, steps, warmup, tuned, graph_k=50):
+def time_path(cfg, prec, steps, warmup, tuned):
     import torch
     from paper_2109_10876_amd import MDSystem, autotune
     autotune.apply(tuned)
+    graph_k = graph_length(steps)
     s = MDSystem(cfg.natoms, cfg.box, cfg.pos, cfg.vel, rc=cfg.rc, skin=cfg.skin, dt=cfg.dt,
                  shift=cfg.shift, mode=tuned["mode"], prec=prec,
                  tile_cells=tuned.get("tile_cells"),
                  tile_rows=tuple(tuned.get("tile_rows", (1, 1))))
     s.setup()
-    s.ensure_list()
+    s.capture(graph_k)
     if warmup:
-        s.run_graphed(warmup, k=graph_k)
-    s.ensure_list()
+        s.run_checked(warmup, k=graph_k)
     stream = torch.cuda.current_stream()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for attempt in range(3):
+    for attempt in range(4):
+        # a timed run whose list overflowed is discarded: back to its start
+        # (the list grows) and timed again
+        cp = s.checkpoint()
+        e_start = float(s.energy[0]) + float(s.ke[0])
         torch.cuda.synchronize()
         t0.record(stream)
         s.run_graphed(steps, k=graph_k)
         t1.record(stream)
         torch.cuda.synchronize()
         ms = t0.elapsed_time(t1)
-        st = int(s.status.item())
-        if st == 0:
+        if not s.overflowed():
             break
-        log(f"[{prec}] list overflow during the timed run (status {st}); regrow and repeat")
-        s.ensure_list()
+        log(f"[{prec}] list overflow during the timed run; regrow and repeat")
+        s.restore(cp)
+        s.capture(graph_k)
     else:
         raise RuntimeError("list overflow persisted")
+    s.ensure_list()
+    e_end = float(s.energy[0]) + float(s.ke[0])
+    drift = {"steps": steps, "e_total_start": e_start, "e_total_end": e_end,
+             "per_atom": (e_end - e_start) / s.N,
+             "rel": (e_end - e_start) / abs(e_start)}
+    replays = (steps - 1) // graph_k
+    graphed = {"graph_steps": graph_k, "replays": replays,
+               "eager_steps": steps - replays * graph_k}
     # dominant kernel: the pair-force kernel of the step (fused with the
     # integrator on pure-LJ tile runs), timed by libmd itself with HIP events
     # around each of its launches on their stream, over nrep eager steps of
@@ -149,18 +167,17 @@ def time_path(cfg, prec, steps, warmup, tuned, graph_k=50):
     nrep = 50
     torch.cuda.synchronize()
     assert lib.md_kernel_timing_start(nrep) == 0
-    s.run(nrep + 1, check_every=0)
+    s.run(nrep + 1, check_every=nrep + 1)
     f_ms, n_timed = ctypes.c_double(), ctypes.c_int32()
     assert lib.md_kernel_timing_read(ctypes.byref(f_ms), ctypes.byref(n_timed)) == 0
     assert n_timed.value == nrep, n_timed.value
     f_ms = f_ms.value
     s.ensure_list()
     sections = time_sections(s, ms / steps, f_ms)
-    s.forces()   # forces at the final positions for the snapshot
     mean_k = float(s.count.double().mean().item())
     npairs = pairs_within_rc(s)
-    snap = (s.positions(), s.forces_np())
-    return s, ms, f_ms, mean_k, npairs, snap, bool(s.fuse), sections
+    snap = (s.positions(), s.velocities())
+    return s, ms, f_ms, mean_k, npairs, snap, bool(s.fuse), sections, drift, graphed
 
 
 def time_sections(s, step_ms, pair_ms, nsteps=200, nrep=10):
@@ -172,11 +189,14 @@ def time_sections(s, step_ms, pair_ms, nsteps=200, nrep=10):
     it), Other the remainder (finalisers, gated no-op launches, launch gaps)."""
     import torch
     rebuilds = 0
+    cp = s.checkpoint()
     s._head()
     for _ in range(nsteps):
         s._body()
         rebuilds += int(s.gate.max().item() > 0)
     s._tail()
+    if s.overflowed():
+        s.restore(cp)   # the count stands; the state goes back to a valid list
     s.ensure_list()
     interval = nsteps / max(rebuilds, 1)
 
@@ -236,16 +256,22 @@ def time_workload(name, steps, warmup=10):
     s = make(tuned["mode"], tuned.get("tile_cells"), tuple(tuned.get("tile_rows", (1, 1))),
              tuned.get("fuse", True))
     s.setup()
-    s.ensure_list()
-    s.run_graphed(warmup, k=25)
-    s.ensure_list()
+    gk = graph_length(steps, cap=25)
+    s.capture(gk)
+    s.run_checked(warmup, k=gk)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    s.run_graphed(steps, k=25)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+    for _ in range(4):
+        # a timed run whose list overflowed is discarded and timed again
+        cp = s.checkpoint()
+        ev0.record()
+        s.run_graphed(steps, k=gk)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        if not s.overflowed():
+            break
+        s.restore(cp)
+        s.capture(gk)
     st = s.ensure_list()
     out = {"N": s.N, "R": s.R, "steps": steps, "ms_per_step": ms / steps, "launch": tuned,
            "atom_steps_per_s": s.N * steps / (ms * 1e-3), "status": st,
@@ -289,22 +315,143 @@ def time_workload(name, steps, warmup=10):
     return out
 
 
-def cpu_baseline(cfg):
-    """The FP64 oracle as it stands, single-threaded on a host core: one NVE
-    step of the same 1,048,576-atom system, taken as the difference of a
-    2-step and a 1-step run (each run starts with one force evaluation)."""
+def host_cpu():
+    """CPU model and logical CPU count of this host (for the baseline's record)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def oracle_leg(pos, vel, box, rc, skin, dt, samples=3):
+    """The FP64 oracle as it stands, timed on this host's cores on the given
+    state: single-threaded (liborc.so) and on all usable threads (the
+    timing-only liborc_omp.so, same per-pair arithmetic).  One sample is the
+    time of a 1-step run minus that of a 0-step run (each starts with one
+    force evaluation), i.e. one step: Integrate1, skin test, pair search and
+    forces within rc, Integrate2.  Also returns the 1-step result, the
+    reference of the per-result errors."""
     import oracle
     oracle.build()
-    t = time.perf_counter()
-    oracle.md_run(cfg.pos, cfg.vel, cfg.box[0], cfg.rc, cfg.skin, cfg.dt, 1)
-    t1 = time.perf_counter() - t
-    t = time.perf_counter()
-    oracle.md_run(cfg.pos, cfg.vel, cfg.box[0], cfg.rc, cfg.skin, cfg.dt, 2)
-    t2 = time.perf_counter() - t
-    per_step = max(t2 - t1, 1e-9)
-    return {"value": cfg.n / per_step, "unit": "atom-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 NVE step of the full {cfg.n}-atom system (2-step minus 1-step run), "
-                      f"{per_step:.2f} s/step"}
+    cpu = host_cpu()
+    threads = max(1, min(int(os.environ.get("OMP_NUM_THREADS", cpu["usable_cpus"])),
+                         cpu["usable_cpus"]))
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    legs, ref1 = {}, None
+    for name, omp in (("single", False), ("all_cores", True)):
+        per = []
+        for _ in range(samples):
+            t = time.perf_counter()
+            oracle.md_run(pos, vel, box, rc, skin, dt, 0, omp=omp)
+            t0 = time.perf_counter() - t
+            t = time.perf_counter()
+            r1 = oracle.md_run(pos, vel, box, rc, skin, dt, 1, omp=omp)
+            per.append(max(time.perf_counter() - t - t0, 1e-9))
+            if not omp:
+                ref1 = r1
+        med = float(np.median(per))
+        legs[name] = {"value": pos.shape[0] / med, "unit": "atom-steps/s",
+                      "cores": 1 if not omp else threads, "s_per_step": per,
+                      "s_per_step_median": med}
+    return legs, cpu, ref1
+
+
+def per_result_errors(cfg, tuned, pos, vel, ref1, steps_window):
+    """Error of each result of the FP32-mixed path on one thermalised state
+    (the mixed run's final positions and velocities): potential energy E,
+    virial W and forces against the FP64 GPU path and the FP64 oracle, and
+    kinetic energy and positions after one step against both.  E and W of the
+    oracle come from its cell-list force evaluation of all atoms; its forces
+    are sampled with the O(N) single-atom loop."""
+    import torch
+    import oracle
+    from paper_2109_10876_amd import MDSystem, autotune
+    autotune.apply(tuned)
+    box = cfg.box[0]
+    res = {}
+    for prec in ("mixed", "fp64"):
+        s = MDSystem(cfg.natoms, cfg.box, pos, vel, rc=cfg.rc, skin=cfg.skin, dt=cfg.dt,
+                     shift=cfg.shift, mode=tuned["mode"], prec=prec,
+                     tile_cells=tuned.get("tile_cells"),
+                     tile_rows=tuple(tuned.get("tile_rows", (1, 1))))
+        s.setup()
+        s.ensure_list()
+        r = {"E": float(s.energy[0]), "W": float(s.virial[0]), "F": s.forces_np()}
+        s.run(1, check_every=1)
+        s.ensure_list()
+        r["KE1"] = float(s.ke[0])
+        r["pos1"] = s.positions()
+        res[prec] = r
+        del s
+        torch.cuda.empty_cache()
+    f_o, e_o, w_o = oracle.lj_forces(pos, cfg.box[0], cfg.rc, shift=cfg.shift)
+    m, d = res["mixed"], res["fp64"]
+    rel = lambda a, b: abs(a - b) / abs(b)
+    nrm = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    out = {
+        "state": f"the mixed run's state after its {steps_window} timed steps and the "
+                 f"measurement steps that follow them (thermalised)",
+        "vs_oracle": {
+            "E_rel": rel(m["E"], e_o), "W_rel": rel(m["W"], w_o), "F_rel": nrm(m["F"], f_o),
+            "KE_1step_rel": rel(m["KE1"], ref1["ekin"][-1]),
+            "pos_1step_max_abs": float(np.abs(m["pos1"] - ref1["pos"]).max()),
+        },
+        "vs_fp64_gpu": {
+            "E_rel": rel(m["E"], d["E"]), "W_rel": rel(m["W"], d["W"]),
+            "F_rel": nrm(m["F"], d["F"]), "KE_1step_rel": rel(m["KE1"], d["KE1"]),
+            "pos_1step_max_abs": float(np.abs(m["pos1"] - d["pos1"]).max()),
+        },
+        "fp64_gpu_vs_oracle": {
+            "E_rel": rel(d["E"], e_o), "W_rel": rel(d["W"], w_o), "F_rel": nrm(d["F"], f_o),
+            "KE_1step_rel": rel(d["KE1"], ref1["ekin"][-1]),
+            "pos_1step_max_abs": float(np.abs(d["pos1"] - ref1["pos"]).max()),
+        },
+        "bounds": {"F_rel": 1e-5, "E_rel": 1e-6, "W_rel": 1e-6},
+    }
+    return out
+
+
+def copy_probe_gbs(nbytes=512 << 20, reps=5):
+    """HBM bandwidth a plain streaming kernel reaches on this GPU: libmd's
+    copy probe over nbytes, bytes read + written per launch over the mean
+    launch time (HIP events on the launch stream)."""
+    import ctypes
+    import torch
+    from paper_2109_10876_amd import _abi
+    lib = _abi.load()
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    for _ in range(2):
+        assert lib.md_copy_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                 nbytes, sp) == 0
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        assert lib.md_copy_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                 nbytes, sp) == 0
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    assert torch.equal(src, dst)
+    mean = float(np.mean(ms))
+    out = {"bytes_each_way": nbytes, "launches": reps, "ms_mean": mean,
+           "gbs": 2 * nbytes / (mean * 1e-3) / 1e9}
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -323,12 +470,13 @@ def main():
                     help="tile lists: staged capacity of the 256-thread shape")
     ap.add_argument("--batch", type=int, default=4, choices=[1, 2, 4, 8],
                     help="neighbour gathers issued together")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle leg (CPU baseline and per-result errors)")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the melt / slab / replica-batch throughput lines")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="only run a plain 512 MiB device-to-device copy five times (the "
-                         "calibration kernel for HBM byte counters) and exit")
+                    help="only run libmd's 512 MiB streaming copy probe (the calibration "
+                         "kernel for HBM byte counters), print its bandwidth and exit")
     ap.add_argument("--workload", default=None,
                     choices=["kg_melt", "ring_melt", "lj_slab", "lj_sphere", "replicas"],
                     help="only time this secondary workload (autotuned, graphed, "
@@ -347,13 +495,10 @@ def main():
         print(json.dumps({"workload": args.workload, **out}), flush=True)
         return
     if args.copy_probe:
-        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")   # 512 MiB
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 8, "launches": 5}))
+        print(json.dumps(copy_probe_gbs()), flush=True)
         return
+    copy = copy_probe_gbs()
+    log(f"copy probe: {json.dumps(copy)}")
     cfg = md_inputs.CONFIGS["lj1m"]()
     from paper_2109_10876_amd import MDSystem, autotune
     if args.mode == "auto":
@@ -371,23 +516,21 @@ def main():
     out, snaps = {}, {}
     for prec in ("mixed", "fp64"):
         log(f"[{prec}] timing {args.steps} steps after {args.warmup} warm-up steps")
-        s, ms, f_ms, mean_k, npairs, snap, fused, sections = time_path(
+        s, ms, f_ms, mean_k, npairs, snap, fused, sections, drift, graphed = time_path(
             cfg, prec, args.steps, args.warmup, tuned)
         snaps[prec] = snap
-        # algorithmic bytes of one pair-kernel launch: per atom the list
-        # entries (4 B each, 2 B in tile-local lists), count (4 B), own
-        # position (24 B) and force write (24 B), neighbour positions being
-        # cache- or LDS-resident; fused with the integrator also velocity
-        # read and write, build-time position read and next position write
-        # (4 x 24 B)
+        n = s.N
+        k_half = mean_k / 2.0 if tuned["mode"] != "half" else mean_k
+        # algorithmic bytes of one launch (the half-list minimum, each
+        # unordered pair once) and the bytes of the list form this run uses
+        vv_b = BYTES_PER_ATOM_VV_FUSED if fused else 0
+        bytes_min = n * (BYTES_PER_HALF_ENTRY * k_half + BYTES_PER_ATOM_FORCE + vv_b)
         ebytes = 2.0 if tuned["mode"] == "tile" else 4.0
-        bytes_launch = s.N * (ebytes * mean_k + 4 + 24 + 24 + (96 if fused else 0))
-        gbs = bytes_launch / (f_ms * 1e-3) / 1e9
-        # algorithmic flops of one launch: full list, so every unordered pair
-        # inside rc is visited from both ends; fused, the integrator's flops
-        # per atom on top
-        flops_launch = (s.N * mean_k * FLOPS_PER_ENTRY + 2 * npairs * FLOPS_PER_PAIR_IN_RC
-                        + (s.N * FLOPS_PER_ATOM_VV if fused else 0))
+        bytes_own = n * (ebytes * mean_k + BYTES_PER_ATOM_FORCE + vv_b)
+        gbs = bytes_min / (f_ms * 1e-3) / 1e9
+        # the method's flops, each unordered pair once
+        flops_launch = (n * k_half * FLOPS_PER_ENTRY + npairs * FLOPS_PER_PAIR_IN_RC
+                        + (n * FLOPS_PER_ATOM_VV if fused else 0))
         tfs = flops_launch / (f_ms * 1e-3) / 1e12
         traffic = traffic_bytes = None
         counted = COUNTED_TRAFFIC.get(tuned["mode"] + ("_fused" if fused else ""))
@@ -398,37 +541,41 @@ def main():
             kernel = "md_lj_forces_vv (k_tile_lj fused with velocity-Verlet)"
         else:
             kernel = "md_lj_forces (%s)" % ("k_tile_lj" if tuned["mode"] == "tile" else "k_lj")
-        hbm_view = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
-                    "bytes_per_launch": bytes_launch, "kernel": kernel}
-        if tuned["mode"] == "tile":
-            # LDS-staged neighbours: the pair loop is bound by vector issue
-            roof = {"bound": "alu", "achieved": tfs, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": tfs / VALU_PEAK_TFLOPS, "traffic": traffic,
-                    "traffic_unit": "GB/s", "traffic_bytes_per_launch": traffic_bytes,
-                    "flops_per_launch": flops_launch, "kernel": kernel,
-                    "hbm_view": {k: hbm_view[k] for k in ("achieved", "frac", "bytes_per_launch")}}
-        else:
-            roof = hbm_view
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                "frac_of_copy_probe": gbs / copy["gbs"], "copy_probe_gbs": copy["gbs"],
+                "target_frac_of_copy_probe": 0.6,
+                "bytes_per_launch": bytes_min,
+                "bytes_per_atom": bytes_min / n,
+                "bytes_formula": "N x (4 K_half + 52 + 96 if fused), K_half = half-list "
+                                 "entries per atom = full-list mean / 2",
+                "own_list_bytes_per_launch": bytes_own,
+                "own_list_frac": bytes_own / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "traffic_unit": "GB/s", "traffic_bytes_per_launch": traffic_bytes,
+                "kernel": kernel, "kernel_ms": f_ms,
+                "alu_view": {"achieved": tfs, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": tfs / VALU_PEAK_TFLOPS, "flops_per_launch": flops_launch,
+                             "count": "the method's work: each unordered pair once"}}
         out[prec] = {
             "ms_per_step": ms / args.steps,
-            "atom_steps_per_s": s.N * args.steps / (ms * 1e-3),
+            "atom_steps_per_s": n * args.steps / (ms * 1e-3),
             "pair_evals_per_s": npairs * args.steps / (ms * 1e-3),
             "pairs_within_rc": npairs,
             "mean_list_entries": mean_k,
-            "force_err_rel": None,
             "forces_kernel_ms": f_ms,
             "roofline": roof,
+            "drift": drift,
+            "graph": graphed,
         }
         # Amdahl-style bound in the spirit of the paper's S_max (Sec. 4.1):
-        # the step if the pair kernel ran at the vector peak on its
-        # algorithmic flops, every other section unchanged
+        # the step if the pair kernel ran at the copy-probe bandwidth on its
+        # algorithmic bytes, every other section unchanged
         step_us = ms / args.steps * 1e3
-        pair_min_us = flops_launch / (VALU_PEAK_TFLOPS * 1e12) * 1e6
-        sections["s_max_pair_at_peak"] = s_max(
+        pair_min_us = bytes_min / (copy["gbs"] * 1e9) * 1e6
+        sections["s_max_pair_at_copy_bw"] = s_max(
             {"pair": sections["pair_us"], "rest": step_us - sections["pair_us"]}, ("pair",),
             sections["pair_us"] / pair_min_us)
-        sections["pair_at_peak_us"] = pair_min_us
+        sections["pair_at_copy_bw_us"] = pair_min_us
         out[prec]["sections"] = sections
         log(f"[{prec}] {json.dumps(out[prec])}")
         del s
@@ -447,12 +594,16 @@ def main():
                                "skin=0.3 dt=0.005 NVE", "N": cfg.n, "launch": tuned},
         "pair_evals_per_s": m["pair_evals_per_s"],
         "forces_kernel_ms": m["forces_kernel_ms"],
-        "force_err_rel": m["force_err_rel"],
+        "force_err_rel": None,
         "roofline": m["roofline"],
+        "copy_probe": copy,
         "sections": m["sections"],
+        "graph": m["graph"],
+        "drift": {"mixed": m["drift"], "fp64": out["fp64"]["drift"]},
+        "err": None,
         "fp64": {k: out["fp64"][k] for k in ("atom_steps_per_s", "pair_evals_per_s",
                                              "ms_per_step", "forces_kernel_ms",
-                                             "force_err_rel", "roofline", "sections")},
+                                             "roofline", "sections")},
         "cpu_baseline": None,
     }
     if not args.no_other:
@@ -468,15 +619,27 @@ def main():
             log(f"[{name}] {json.dumps(other[name])}")
         line["workloads"] = other
     if not args.no_cpu:
-        # the oracle leg: CPU timing, and the force error of both GPU paths
-        # on their final states against the oracle's O(N) loop
-        log("cpu baseline: oracle, one step of the full system")
-        line["cpu_baseline"] = cpu_baseline(cfg)
-        for prec in ("mixed", "fp64"):
-            pos, f = snaps[prec]
-            out[prec]["force_err_rel"] = sampled_force_error(pos, f, cfg.box[0], cfg.rc)
-        line["force_err_rel"] = out["mixed"]["force_err_rel"]
-        line["fp64"]["force_err_rel"] = out["fp64"]["force_err_rel"]
+        # the oracle leg on the mixed run's final (thermalised) state: CPU
+        # timing on one core and on all cores, then the error of every
+        # result of the mixed path against the oracle and the FP64 GPU path
+        pos, vel = snaps["mixed"]
+        log("oracle leg: CPU timing (1 core, all cores) on the final state")
+        legs, cpu, ref1 = oracle_leg(pos, vel, cfg.box[0], cfg.rc, cfg.skin, cfg.dt)
+        one = legs["single"]
+        line["cpu_baseline"] = {
+            "value": one["value"], "unit": "atom-steps/s", "cores": one["cores"],
+            "kind": "oracle",
+            "sample": (f"3 samples of one NVE step of the full {cfg.n}-atom system from the "
+                       f"mixed run's final state, each a 1-step minus a 0-step oracle run; "
+                       f"median {one['s_per_step_median']:.2f} s/step on 1 core, "
+                       f"{legs['all_cores']['s_per_step_median']:.2f} s/step on "
+                       f"{legs['all_cores']['cores']} threads"),
+            "legs": legs, "host": cpu}
+        log("per-result errors of the mixed path")
+        err = per_result_errors(cfg, tuned, pos, vel, ref1, args.steps)
+        line["err"] = err
+        line["force_err_rel"] = err["vs_oracle"]["F_rel"]
+        line["fp64"]["force_err_rel"] = err["fp64_gpu_vs_oracle"]["F_rel"]
     print(json.dumps(line), flush=True)
 
 

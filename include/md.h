@@ -271,6 +271,16 @@ int md_tune_get(int32_t knob);
  * an event cannot be read. */
 int md_kernel_timing_start(int32_t n);
 int md_kernel_timing_read(double *mean_ms, int32_t *count);
+/* Measurement aid: copies `bytes` bytes from device buffer src to device
+ * buffer dst (caller-owned, 16-byte aligned, not overlapping) with a plain
+ * streaming kernel on `stream` (a hipStream_t).  Timing it gives the HBM
+ * bandwidth a kernel can reach (bytes read + bytes written over the
+ * duration), the denominator of the roofline fraction, and it is the
+ * known-size kernel that calibrates the HBM byte counters.  MD_EINVAL for null
+ * or misaligned pointers or a size that is 0 or not a multiple of 16,
+ * MD_ERANGE for sizes beyond 2^31 blocks of 16 KiB, MD_EHIP on a launch
+ * failure. */
+int md_copy_probe(const void *src, void *dst, size_t bytes, void *stream);
 /* Staged-atom capacity per tile of MD_TILE_FULL lists for the current
  * MD_TUNE_TILE_THREADS and MD_TUNE_TILE_SLOTS (a tile whose staged sequence
  * is larger raises MD_F_TILE_OVERFLOW). */

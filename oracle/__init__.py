@@ -31,14 +31,23 @@ _CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
            "-fno-fast-math", "-Wall", "-Wextra"]
 
 
-def build(force=False):
-    """Compile orc.c into liborc.so with gcc (plain -O2, no fast-math)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    tmp = _LIB + ".tmp"
-    subprocess.run(["gcc", *_CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
-    os.replace(tmp, _LIB)
-    return _LIB
+_LIB_OMP = os.path.join(_HERE, "liborc_omp.so")
+
+
+def build(force=False, omp=False):
+    """Compile orc.c into liborc.so with gcc (plain -O2, no fast-math).
+
+    omp=True builds the timing-only liborc_omp.so instead (-fopenmp with
+    ORC_OMP: the pair search and the pair force sum on all threads, per-pair
+    arithmetic unchanged), used only for the all-core CPU baseline."""
+    lib = _LIB_OMP if omp else _LIB
+    if not force and os.path.exists(lib) and os.path.getmtime(lib) >= os.path.getmtime(_SRC):
+        return lib
+    tmp = lib + ".tmp"
+    extra = ["-fopenmp", "-DORC_OMP"] if omp else []
+    subprocess.run(["gcc", *_CFLAGS, *extra, _SRC, "-o", tmp, "-lm"], check=True)
+    os.replace(tmp, lib)
+    return lib
 
 
 _lib = None
@@ -49,13 +58,24 @@ _U8 = ctypes.POINTER(ctypes.c_uint8)
 _U32 = ctypes.POINTER(ctypes.c_uint32)
 
 
-def _load():
-    global _lib
+_lib_omp = None
+
+
+def _load(omp=False):
+    global _lib, _lib_omp
+    if omp:
+        if _lib_omp is None:
+            _lib_omp = _declare(ctypes.CDLL(build(omp=True)))
+        return _lib_omp
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         build()
-    lib = ctypes.CDLL(_LIB)
+    _lib = _declare(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def _declare(lib):
     i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.orc_min_image.restype = dbl
     lib.orc_min_image.argtypes = [dbl, dbl]
@@ -104,7 +124,6 @@ def _load():
                                    i32, dbl, dbl, i32, i64, _I, _I, dbl, dbl, i64, _I, _I, _I,
                                    dbl, dbl, dbl, ctypes.c_uint64, ctypes.c_uint64, _U8, _D,
                                    _D, _D, _D, _D]
-    _lib = lib
     return lib
 
 
@@ -281,11 +300,12 @@ def lj_vjp(pos, box, rc, G, gE, eps=1.0, sig=1.0, types=None, shift=1, pairs=Non
 
 
 def md_run(pos, vel, box, rc, skin, dt, steps, eps=1.0, sig=1.0, types=None,
-           mass=None, shift=1):
+           mass=None, shift=1, omp=False):
     """NVE velocity Verlet (Sec. 2.1, Fig. 1) with the skin rebuild test
     recorded per step.  Returns a dict with final unwrapped positions,
-    velocities and forces, per-step rebuild flags and energy series."""
-    lib = _load()
+    velocities and forces, per-step rebuild flags and energy series.
+    omp=True runs the timing-only all-thread build (CPU baseline only)."""
+    lib = _load(omp)
     x, y, z = (p.copy() for p in _planes(pos))
     vx, vy, vz = (p.copy() for p in _planes(vel))
     n = x.shape[0]

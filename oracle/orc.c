@@ -34,7 +34,28 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef ORC_OMP
+#include <omp.h>
+#endif
+
 #define EXPORT __attribute__((visibility("default")))
+
+#ifdef ORC_OMP
+#define ORC_PAR_FOR _Pragma("omp parallel for schedule(static)")
+#define ORC_PAR_FOR_SUM_K _Pragma("omp parallel for schedule(static) reduction(+ : k)")
+#define ORC_PAR_FOR_MAX_DMAX _Pragma("omp parallel for schedule(static) reduction(max : dmax)")
+#else
+#define ORC_PAR_FOR
+#define ORC_PAR_FOR_SUM_K
+#define ORC_PAR_FOR_MAX_DMAX
+#endif
+
+/* ORC_OMP (a timing-only build, liborc_omp.so, used for the all-core CPU
+ * baseline): the pair search runs over atoms i on all threads and the force
+ * sum over pairs splits into per-thread partial force arrays.  Every pair's
+ * arithmetic is the same; only the order in which per-atom forces and the
+ * energy and virial are summed differs.  The checked build (liborc.so) has
+ * ORC_OMP unset and runs every loop in the order written. */
 
 /* ---------------------------------------------------------------- geometry */
 
@@ -150,8 +171,30 @@ EXPORT int64_t orc_pairs_cells(int32_t n, const double *x, const double *y,
         head[c] = i;
     }
     int64_t cnt = 0;
+#ifdef ORC_OMP
+    /* each thread searches a contiguous block of i into its own buffer; the
+     * buffers are concatenated in thread order, i.e. in the serial order */
+    int nth = omp_get_max_threads();
+    int32_t **bufi = calloc((size_t)nth, sizeof(int32_t *));
+    int32_t **bufj = calloc((size_t)nth, sizeof(int32_t *));
+    int64_t *bufn = calloc((size_t)nth, sizeof(int64_t));
+    int bad = !bufi || !bufj || !bufn;
+#pragma omp parallel num_threads(nth) reduction(| : bad)
+    {
+        int th = omp_get_thread_num();
+        int32_t *js_t = malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+        int64_t tcap = (int64_t)n * 48 / nth + 1024, tn = 0;
+        int32_t *pi_t = malloc(sizeof(int32_t) * tcap), *pj_t = malloc(sizeof(int32_t) * tcap);
+        double dx, dy, dz;
+        if (!js_t || !pi_t || !pj_t) bad = 1;
+#pragma omp for schedule(static)
+        for (int32_t i = 0; i < n; ++i) {
+            if (bad) continue;
+            int32_t *js = js_t;
+#else
     double dx, dy, dz;
     for (int32_t i = 0; i < n; ++i) {
+#endif
         int32_t c = cid[i];
         int32_t cx = c % nc[0], cy = (c / nc[0]) % nc[1], cz = c / (nc[0] * nc[1]);
         int32_t seen[27], nseen = 0, nj = 0;
@@ -171,6 +214,30 @@ EXPORT int64_t orc_pairs_cells(int32_t n, const double *x, const double *y,
                             js[nj++] = j;
                 }
         qsort(js, (size_t)nj, sizeof(int32_t), cmp_i32);
+#ifdef ORC_OMP
+            if (tn + nj > tcap) {
+                tcap = 2 * (tn + nj);
+                int32_t *a = realloc(pi_t, sizeof(int32_t) * tcap);
+                int32_t *b = a ? realloc(pj_t, sizeof(int32_t) * tcap) : NULL;
+                if (a) pi_t = a;
+                if (b) pj_t = b;
+                if (!a || !b) { bad = 1; continue; }
+            }
+            for (int32_t k = 0; k < nj; ++k) { pi_t[tn] = i; pj_t[tn] = js[k]; ++tn; }
+        }
+        free(js_t);
+        if (bufi && bufj && bufn) { bufi[th] = pi_t; bufj[th] = pj_t; bufn[th] = tn; }
+        else { free(pi_t); free(pj_t); }
+    }
+    for (int t = 0; !bad && t < nth; ++t) {
+        for (int64_t k = 0; k < bufn[t]; ++k, ++cnt)
+            if (cnt < cap) { pi[cnt] = bufi[t][k]; pj[cnt] = bufj[t][k]; }
+    }
+    for (int t = 0; bufi && bufj && t < nth; ++t) { free(bufi[t]); free(bufj[t]); }
+    free(bufi); free(bufj); free(bufn);
+    free(head); free(next); free(cid); free(js);
+    return bad ? -2 : cnt;
+#else
         for (int32_t k = 0; k < nj; ++k) {
             if (cnt < cap) { pi[cnt] = i; pj[cnt] = js[k]; }
             ++cnt;
@@ -178,6 +245,7 @@ EXPORT int64_t orc_pairs_cells(int32_t n, const double *x, const double *y,
     }
     free(head); free(next); free(cid); free(js);
     return cnt;
+#endif
 }
 
 /* ----------------------------------------------------------------- forces */
@@ -194,6 +262,41 @@ EXPORT void orc_lj_forces_pairs(int32_t n, const double *x, const double *y,
                                 double *energy, double *virial)
 {
     for (int32_t i = 0; i < n; ++i) fx[i] = fy[i] = fz[i] = 0.0;
+#ifdef ORC_OMP
+    /* per-thread force arrays over contiguous blocks of pairs, summed in
+     * thread order */
+    int nth = omp_get_max_threads();
+    double *part = calloc((size_t)nth * 3 * (size_t)n, sizeof(double));
+    if (part) {
+        double e = 0.0, w = 0.0;
+#pragma omp parallel num_threads(nth) reduction(+ : e, w)
+        {
+            double *ax = part + (size_t)omp_get_thread_num() * 3 * (size_t)n;
+            double *ay = ax + n, *az = ay + n, dx, dy, dz, u, fr;
+#pragma omp for schedule(static)
+            for (int64_t p = 0; p < np; ++p) {
+                int32_t i = pi[p], j = pj[p];
+                int32_t t = type ? type[i] * nt + type[j] : 0;
+                double r2 = dist2(x, y, z, L, i, j, &dx, &dy, &dz);
+                if (!orc_lj_pair(r2, eps[t], sig[t], rc, shift, &u, &fr)) continue;
+                ax[i] += fr * dx; ay[i] += fr * dy; az[i] += fr * dz;
+                ax[j] -= fr * dx; ay[j] -= fr * dy; az[j] -= fr * dz;
+                e += u;
+                w += fr * r2;
+            }
+        }
+#pragma omp parallel for schedule(static)
+        for (int32_t i = 0; i < n; ++i)
+            for (int t = 0; t < nth; ++t) {
+                const double *a = part + (size_t)t * 3 * (size_t)n;
+                fx[i] += a[i]; fy[i] += a[n + i]; fz[i] += a[2 * (size_t)n + i];
+            }
+        free(part);
+        *energy = e;
+        *virial = w;
+        return;
+    }
+#endif
     double e = 0.0, w = 0.0, dx, dy, dz, u, fr;
     for (int64_t p = 0; p < np; ++p) {
         int32_t i = pi[p], j = pj[p];
@@ -381,6 +484,7 @@ EXPORT int32_t orc_md_run(int32_t n, double *x, double *y, double *z,
                                   fx, fy, fz, &e, &w);
     if (rcode < 0) { free(xb); free(yb); free(zb); return (int32_t)rcode; }
     double k = 0.0;
+    ORC_PAR_FOR_SUM_K
     for (int32_t i = 0; i < n; ++i) {
         double m = mass[type ? type[i] : 0];
         k += 0.5 * m * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]);
@@ -388,6 +492,7 @@ EXPORT int32_t orc_md_run(int32_t n, double *x, double *y, double *z,
     epot[0] = e; ekin[0] = k; vir[0] = w;
     const double lim2 = 0.25 * skin * skin;
     for (int32_t s = 0; s < steps; ++s) {
+        ORC_PAR_FOR
         for (int32_t i = 0; i < n; ++i) {
             double im = 1.0 / mass[type ? type[i] : 0];
             vx[i] += 0.5 * dt * fx[i] * im;
@@ -398,6 +503,7 @@ EXPORT int32_t orc_md_run(int32_t n, double *x, double *y, double *z,
             z[i] += dt * vz[i];
         }
         double dmax = 0.0;
+        ORC_PAR_FOR_MAX_DMAX
         for (int32_t i = 0; i < n; ++i) {
             double a = x[i] - xb[i], b = y[i] - yb[i], c = z[i] - zb[i];
             double d2 = a * a + b * b + c * c;
@@ -413,6 +519,7 @@ EXPORT int32_t orc_md_run(int32_t n, double *x, double *y, double *z,
                               fx, fy, fz, &e, &w);
         if (rcode < 0) { free(xb); free(yb); free(zb); return (int32_t)rcode; }
         k = 0.0;
+        ORC_PAR_FOR_SUM_K
         for (int32_t i = 0; i < n; ++i) {
             double m = mass[type ? type[i] : 0];
             double im = 1.0 / m;

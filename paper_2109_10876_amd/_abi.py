@@ -51,7 +51,8 @@ MD_TUNE_TILE_SLOTS = 3
 
 EXPORTS = (
     "md_abi_version", "md_strerror", "md_tune_set", "md_tune_get", "md_tile_capacity",
-    "md_tile_max_cells", "md_kernel_timing_start", "md_kernel_timing_read", "md_plan_sizes",
+    "md_tile_max_cells", "md_kernel_timing_start", "md_kernel_timing_read", "md_copy_probe",
+    "md_plan_sizes",
     "md_plan_fill",
     "md_tile_plan",
     "md_workspace_bytes", "md_cell_sort", "md_verlet_build", "md_lj_forces",
@@ -109,6 +110,11 @@ class MDError(RuntimeError):
         super().__init__(f"{fn}: {strerror(code)} (code {code})")
 
 
+class ListOverflowError(RuntimeError):
+    """Steps ran on a Verlet list that had overflowed (MD_F_NBR_OVERFLOW or
+    MD_F_TILE_OVERFLOW set after a run): their trajectory is not valid."""
+
+
 _lib = None
 
 
@@ -143,6 +149,8 @@ def load():
     lib.md_kernel_timing_start.argtypes = [_i32]
     lib.md_kernel_timing_read.restype = ctypes.c_int
     lib.md_kernel_timing_read.argtypes = [P(_dbl), P(_i32)]
+    lib.md_copy_probe.restype = ctypes.c_int
+    lib.md_copy_probe.argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
     lib.md_tile_plan.restype = ctypes.c_int
     lib.md_tile_plan.argtypes = [_i32, _vp, _i32, _i32, _i32, _vp, _vp]
     lib.md_workspace_bytes.restype = ctypes.c_size_t

@@ -2,6 +2,9 @@
 // around its pair-force kernel launches (global-index and tile-local, plain
 // and fused with the integrator), on the stream each launch uses, so a
 // caller can read the kernel's own duration without the launches around it.
+// Also a streaming copy that gives the achievable HBM bandwidth, the
+// denominator of the roofline fraction, and the known-size kernel that
+// calibrates the HBM byte counters.
 #include "md_common.hpp"
 
 namespace md {
@@ -42,9 +45,47 @@ void timing_end(int k, hipStream_t s)
     --g_left;
 }
 
+// dst = src over n 16-byte words; each thread moves kCopyPer words at a
+// stride of one block, so a wave's loads and stores are contiguous 1 KiB runs
+// and every thread has kCopyPer loads in flight before its first store.
+constexpr int kCopyBlock = 256, kCopyPer = 4;
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kCopyBlock) void k_copy_probe(const u32x4 *__restrict__ src,
+                                                           u32x4 *__restrict__ dst, size_t n)
+{
+    const size_t base = size_t(blockIdx.x) * (kCopyBlock * kCopyPer) + threadIdx.x;
+    u32x4 v[kCopyPer];
+#pragma unroll
+    for (int k = 0; k < kCopyPer; ++k) {
+        const size_t i = base + size_t(k) * kCopyBlock;
+        if (i < n) v[k] = __builtin_nontemporal_load(src + i);
+    }
+#pragma unroll
+    for (int k = 0; k < kCopyPer; ++k) {
+        const size_t i = base + size_t(k) * kCopyBlock;
+        if (i < n) __builtin_nontemporal_store(v[k], dst + i);
+    }
+}
+
 }  // namespace md
 
 extern "C" {
+
+int md_copy_probe(const void *src, void *dst, size_t bytes, void *stream)
+{
+    if (!src || !dst || bytes == 0 || bytes % 16 != 0) return MD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(src) % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0)
+        return MD_EINVAL;
+    const size_t n = bytes / 16;
+    const size_t per = size_t(md::kCopyBlock) * md::kCopyPer;
+    const size_t blocks = (n + per - 1) / per;
+    if (blocks > 0x7fffffffu) return MD_ERANGE;
+    hipLaunchKernelGGL(md::k_copy_probe, dim3(unsigned(blocks)), dim3(md::kCopyBlock), 0,
+                       static_cast<hipStream_t>(stream), static_cast<const md::u32x4 *>(src),
+                       static_cast<md::u32x4 *>(dst), n);
+    return hipGetLastError() == hipSuccess ? MD_OK : MD_EHIP;
+}
 
 int md_kernel_timing_start(int32_t n)
 {

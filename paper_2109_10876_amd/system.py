@@ -192,6 +192,8 @@ class MDSystem:
         self.virial = torch.zeros(self.R, dtype=torch.float64, device=d)
         self.ke = torch.zeros(self.R, dtype=torch.float64, device=d)
         self._graph = None
+        self._stepped = 0        # steps run since the status word was last read clean
+        self.recoveries = []     # overflow recoveries of run()/run_checked(): sticky record
 
         # ---- optional FENE bonds (id pairs [Nb,2]) and Langevin thermostat
         self.bonds = None
@@ -468,33 +470,105 @@ class MDSystem:
         self.ensure_list()
         self.all_forces(initial=True)
 
-    def ensure_list(self):
-        """Synchronise; on list overflow grow max_nbr and rebuild every replica."""
-        torch.cuda.synchronize(self.dev)
-        st = int(self.status.item())
-        while st & abi.MD_F_TILE_OVERFLOW:
+    _OVERFLOW = abi.MD_F_NBR_OVERFLOW | abi.MD_F_TILE_OVERFLOW
+
+    def _regrow(self, st):
+        """Grow the list storage for the overflow flags in ``st``: smaller
+        tiles for MD_F_TILE_OVERFLOW, a longer list for MD_F_NBR_OVERFLOW.
+        Captured graphs hold the old pointers, so they are dropped."""
+        if st & abi.MD_F_TILE_OVERFLOW:
             if self.tile_cells <= 1:
                 raise RuntimeError("a single-cell tile exceeds the LDS staging capacity")
             self._plan_tiles(max(1, self.tile_cells - max(1, self.tile_cells // 4)))
             self._set_nlist()
-            self._graph = None
-            self.status.zero_()
-            self.tile_need.zero_()
-            self.build(gated=False)
-            torch.cuda.synchronize(self.dev)
-            st = int(self.status.item())
         if st & abi.MD_F_NBR_OVERFLOW:
-            need = int(self.need.item())
-            self._alloc_list(int(need * 1.2) + 8)
-            self._graph = None   # captured launches hold the old list pointers
-            self.status.zero_()
-            self.need.zero_()
+            self._alloc_list(int(int(self.need.item()) * 1.2) + 8)
+        self._graph = None
+        self.status.zero_()
+        self.need.zero_()
+        self.tile_need.zero_()
+
+    def ensure_list(self):
+        """Synchronise and read the status word.
+
+        Right after an ungated re-sort and list build (set-up, recovery) an
+        overflow is repaired here: the list storage grows and the list is
+        rebuilt until it fits.  After steps have run on a list, an overflow
+        means some of those steps used a truncated list (forces, and in the
+        fused call whole tiles, were skipped), so the trajectory is invalid:
+        that raises ListOverflowError with the flag left set; run() with
+        check_every > 0 recovers by itself instead.  Any other flag raises."""
+        torch.cuda.synchronize(self.dev)
+        st = int(self.status.item())
+        if st & self._OVERFLOW and self._stepped:
+            raise abi.ListOverflowError(
+                f"the Verlet list overflowed during the last {self._stepped} steps "
+                f"(status 0x{st:x}): their trajectory used a truncated list")
+        while st & self._OVERFLOW:
+            self._regrow(st)
             self.build(gated=False)
             torch.cuda.synchronize(self.dev)
             st = int(self.status.item())
-        if st & ~abi.MD_F_NBR_OVERFLOW:
+        if st:
             raise RuntimeError(f"device status flags 0x{st:x}")
+        self._stepped = 0
         return st
+
+    # ------------------------------------------------- checkpoint / recovery
+    _STATE = ("vx", "vy", "vz", "fx", "fy", "fz", "xb", "yb", "zb", "type", "id", "img",
+              "where", "pos4", "noise_step", "energy", "virial", "ke")
+
+    def checkpoint(self):
+        """Device copy of the state a run evolves (positions, velocities,
+        forces, build positions, atom order and images, the thermostat's
+        noise counter); restore() brings it back."""
+        torch.cuda.synchronize(self.dev)
+        cp = {"par": self._par, "pos": tuple(t.clone() for t in self._pos[self._par])}
+        for k in self._STATE:
+            t = getattr(self, k, None)
+            cp[k] = t.clone() if t is not None else None
+        return cp
+
+    def restore(self, cp):
+        """Return to a checkpoint() and make the list valid for it: grow the
+        list storage for the overflow flags that are set, clear the status,
+        re-sort and rebuild (ungated, so the build positions are the current
+        ones), and carry the checkpoint's forces over to the new atom order
+        (the re-sort permutes every per-atom plane except the forces)."""
+        torch.cuda.synchronize(self.dev)
+        st = int(self.status.item())
+        self._par = cp["par"]
+        for dst, src in zip(self._pos[self._par], cp["pos"]):
+            dst.copy_(src)
+        for k in self._STATE:
+            if cp[k] is not None:
+                getattr(self, k).copy_(cp[k])
+        # forces by atom id, on the host (a permutation, no arithmetic)
+        ids = cp["id"].cpu().numpy()
+        f_id = np.empty((self.N, 3))
+        f_id[ids] = np.stack([cp["fx"].cpu().numpy(), cp["fy"].cpu().numpy(),
+                              cp["fz"].cpu().numpy()], 1)
+        if st & self._OVERFLOW:
+            self._regrow(st)
+        else:
+            self.status.zero_()
+        self.sort(gated=False)
+        self.build(gated=False)
+        self._stepped = 0
+        self.ensure_list()
+        f_new = f_id[self.id.cpu().numpy()]
+        for k, t in enumerate((self.fx, self.fy, self.fz)):
+            t.copy_(torch.from_numpy(np.ascontiguousarray(f_new[:, k])))
+        torch.cuda.synchronize(self.dev)
+        return st
+
+    def overflowed(self):
+        """Synchronise; True if a list overflow flag is set (other flags raise)."""
+        torch.cuda.synchronize(self.dev)
+        st = int(self.status.item())
+        if st & ~self._OVERFLOW:
+            raise RuntimeError(f"device status flags 0x{st:x}")
+        return bool(st & self._OVERFLOW)
 
     def step_body(self, first):
         """One velocity-Verlet step except its final half kick."""
@@ -512,6 +586,7 @@ class MDSystem:
         self.build()
 
     def _body(self):
+        self._stepped += 1
         if self.fuse:
             self.fused_body()
         else:
@@ -519,6 +594,7 @@ class MDSystem:
 
     def _head(self):
         # first step up to its forces (fused: up to its list build)
+        self._stepped += 1
         if self.fuse:
             self.vv(1)
             self.sort()
@@ -532,14 +608,48 @@ class MDSystem:
             self.all_forces()
         self.vv(2)
 
-    def run(self, steps, check_every=50):
-        """`steps` full steps (Integrate2 of step s fused with Integrate1 of s+1)."""
+    def run(self, steps, check_every=50, max_recoveries=8):
+        """`steps` full steps (Integrate2 of step s fused with Integrate1 of s+1).
+
+        With check_every > 0 the status word is read every check_every steps.
+        A list overflow seen there sends the run back to the state saved at
+        the previous check (restore(): the list grows and is rebuilt), and
+        the steps since are run again; each such recovery is recorded in
+        self.recoveries (step, flags).  With check_every = 0 nothing is read
+        and ensure_list() afterwards raises if the list overflowed."""
+        if not check_every:
+            self._head()
+            for _ in range(1, steps):
+                self._body()
+            self._tail()
+            return
+        cp, at = self.checkpoint(), -1      # -1: before the first step's head
         self._head()
-        for s in range(1, steps):
-            self._body()
-            if check_every and s % check_every == 0:
-                self.ensure_list()
+        done, tries = 0, 0
+        while True:
+            k = min(check_every, steps - 1 - done)
+            for _ in range(k):
+                self._body()
+            done += k
+            if self.overflowed():
+                tries += 1
+                if tries > max_recoveries:
+                    raise abi.ListOverflowError("the Verlet list kept overflowing")
+                flags = self.restore(cp)
+                self.recoveries.append({"step": done, "flags": flags,
+                                        "max_nbr": self.max_nbr,
+                                        "tile_cells": self.tile_cells})
+                if at < 0:
+                    done = 0
+                    self._head()
+                else:
+                    done = at
+                continue
+            if done >= steps - 1:
+                break
+            cp, at = self.checkpoint(), done
         self._tail()
+        self._stepped = 0
 
     def capture(self, k):
         """Capture k repeated steps (Integrate2+Integrate1, gated re-sort and
@@ -561,7 +671,9 @@ class MDSystem:
 
     def run_graphed(self, steps, k=50):
         """Same trajectory as run(steps) with the repeated steps replayed from a
-        captured graph of k steps.  Status flags are not inspected here."""
+        captured graph of k steps.  Status flags are not read here: call
+        ensure_list() afterwards (it raises if the list overflowed), or use
+        run_checked()."""
         if self._graph is None or self._graph[0] != k:
             self.capture(k)
         _, g, kk, par0 = self._graph
@@ -575,6 +687,20 @@ class MDSystem:
         for _ in range(rest % kk):
             self._body()
         self._tail()
+
+    def run_checked(self, steps, k=50, max_recoveries=8):
+        """run_graphed() from a checkpoint: if the list overflowed on the way,
+        return to the checkpoint (the list grows) and run the steps again."""
+        cp = self.checkpoint()
+        for _ in range(max_recoveries + 1):
+            self.run_graphed(steps, k=k)
+            if not self.overflowed():
+                self._stepped = 0
+                return
+            flags = self.restore(cp)
+            self.recoveries.append({"step": None, "flags": flags, "max_nbr": self.max_nbr,
+                                    "tile_cells": self.tile_cells})
+        raise abi.ListOverflowError("the Verlet list kept overflowing")
 
     # ------------------------------------------------------------ readback
     def order(self):

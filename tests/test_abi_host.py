@@ -209,6 +209,17 @@ def test_kernel_timing_arguments_and_empty_read():
     assert lib.md_kernel_timing_read(None, ctypes.byref(n)) == abi.MD_EINVAL
 
 
+def test_copy_probe_rejects_bad_arguments_without_a_gpu():
+    lib = abi.load()
+    buf = (ctypes.c_double * 8)()
+    p = ctypes.addressof(buf)
+    assert lib.md_copy_probe(None, p, 16, None) == abi.MD_EINVAL
+    assert lib.md_copy_probe(p, None, 16, None) == abi.MD_EINVAL
+    assert lib.md_copy_probe(p, p + 16, 0, None) == abi.MD_EINVAL
+    assert lib.md_copy_probe(p, p + 16, 24, None) == abi.MD_EINVAL
+    assert lib.md_copy_probe(p + 8, p + 32, 16, None) == abi.MD_EINVAL
+
+
 def test_tile_list_needs_a_staging_table_of_the_current_capacity():
     # rejected on the host before anything is launched (fake device pointers)
     lib = abi.load()

@@ -504,3 +504,69 @@ def test_half_kick_with_thermostat_equals_langevin_then_half_kick():
         np.testing.assert_allclose(a[1], b[1], rtol=1e-14, atol=1e-14)
         np.testing.assert_allclose(a[0], b[0], rtol=1e-15, atol=1e-14)
         assert a[3] == pytest.approx(b[3], rel=1e-14)
+
+
+# ---------------------------------------------------- the melts as benchmarked
+# The benchmark times both melts on global full lists with FP32 pair math and
+# the thermostat force added by the half kick, replayed from captured graphs.
+# Bounds: forces normwise 1e-5 (the mixed path's target); the WCA energy
+# relative 1e-6; the bonded terms run in FP64 on both sides (1e-11).
+
+MELT_LANGEVIN = {"kg_melt": (0.5, 1.0, 3), "ring_melt": (0.5, 1.0, 7)}
+
+
+@pytest.mark.parametrize("name", ["kg_melt", "ring_melt"])
+def test_melt_full_size_in_the_benchmarked_form(name):
+    import torch
+    from paper_2109_10876_amd import _abi as abi
+    cfg = md_inputs.CONFIGS[name]()
+    print(f"case: {name} N={cfg.n} full list, mixed, thermostat in the half kick, "
+          f"50 graphed steps", flush=True)
+    s = _system(cfg, langevin=MELT_LANGEVIN[name], mode="full", prec="mixed")
+    assert s.mode == abi.MD_FULL and not s.fuse and s.vv_thermo
+    s.setup()
+    s.run_checked(50, k=24)
+    assert s.ensure_list() == 0
+    # every force on the current positions (LJ, then the bonded terms added)
+    s.forces()
+    if cfg.angles is not None:
+        s.bonded()
+    else:
+        s.fene()
+    torch.cuda.synchronize()
+    pos = s.positions()
+    f_lj, e_lj, _ = oracle.lj_forces(pos, cfg.box[0], cfg.rc, shift=1)
+    f_b, e_b, w_b, broken = oracle.fene_forces(pos, cfg.box[0], cfg.bonds)
+    ref = f_lj + f_b
+    assert broken == 0
+    if cfg.angles is not None:
+        f_a, e_a, _, bad = oracle.angle_forces(pos, cfg.box[0], cfg.angles)
+        assert bad == 0
+        ref = ref + f_a
+        assert float(s.energy_angle[0]) == pytest.approx(e_a, rel=1e-11)
+    got = s.forces_np()
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-5
+    assert float(s.energy[0]) == pytest.approx(e_lj, rel=1e-6)
+    assert float(s.energy_bond[0]) == pytest.approx(e_b, rel=1e-11)
+    assert float(s.virial_bond[0]) == pytest.approx(w_b, rel=1e-11)
+
+
+@pytest.mark.parametrize("rings", [False, True])
+def test_melt_mixed_trajectory_short_horizon(rings):
+    # 20 thermostatted steps of a small melt in the benchmarked form against
+    # the oracle's run with the same noise stream: the FP32 pair terms move
+    # positions by ~1e-8 over this horizon, held to 1e-6
+    cfg = _rings((8, 8, 8), 23, jit=0.02) if rings else \
+        md_inputs.lattice_chains((8, 8, 10), 40, seed=6, temperature=1.0)
+    print(f"case: melt mixed 20 steps rings={rings}", flush=True)
+    s = _system(cfg, langevin=(0.5, 1.0, 41, 0), mode="full", prec="mixed")
+    s.setup()
+    s.run(20)
+    assert s.ensure_list() == 0
+    ref = oracle.md_run_ext(cfg.pos, cfg.vel, cfg.box[0], cfg.rc, cfg.skin, cfg.dt, 20,
+                            bonds=cfg.bonds, angles=cfg.angles, gamma=0.5, temperature=1.0,
+                            seed=41, step0=0)
+    assert ref["broken"] == 0
+    assert np.abs(s.positions() - ref["pos"]).max() < 1e-6
+    assert np.abs(s.velocities() - ref["vel"]).max() < 1e-5
+    assert float(s.ke[0]) == pytest.approx(ref["ekin"][-1], rel=1e-6)

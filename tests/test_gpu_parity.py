@@ -253,6 +253,53 @@ def test_neighbour_overflow_is_flagged_then_recovered(c1_snapshot):
     assert np.abs(s.forces_np() - ref).max() < 1e-10
 
 
+def _midrun_overflow_case(mode):
+    # the 4000-atom fluid from its perfect FCC sites: exactly 78 neighbours
+    # within rc + skin at t = 0, so max_nbr = 80 fits at set-up; the vibrating
+    # lattice needs more, so the list first overflows at a rebuild during
+    # the run
+    cfg = md_inputs.lj_fluid(10, temperature=0.72, seed=1)
+    s = _system(cfg, mode=mode, prec="fp64", max_nbr=80)
+    s.setup()
+    assert s.max_nbr == 80 and s.recoveries == []
+    return cfg, s
+
+
+@pytest.mark.parametrize("mode,graphed", [("full", False), ("tile", False), ("tile", True)])
+def test_overflow_first_seen_mid_run_is_recovered(mode, graphed):
+    # run() goes back to the state saved at the last check, grows the list
+    # and runs those steps again (run_checked: from the start of the run);
+    # the trajectory then equals the oracle's, which never uses a list
+    cfg, s = _midrun_overflow_case(mode)
+    say(f"case: mid-run overflow {mode} graphed={graphed}")
+    if graphed:
+        s.run_checked(cfg.steps, k=10)
+    else:
+        s.run(cfg.steps, check_every=10)
+    assert s.ensure_list() == 0
+    assert s.recoveries and s.max_nbr > 80
+    if not graphed:
+        assert s.recoveries[0]["step"] > 0
+    ref = oracle.md_run(cfg.pos, cfg.vel, cfg.box[0], RC, SKIN, cfg.dt, cfg.steps)
+    assert np.abs(s.positions() - ref["pos"]).max() < 1e-9
+    assert np.abs(s.velocities() - ref["vel"]).max() < 1e-9
+    assert float(s.energy[0]) == pytest.approx(ref["epot"][-1], rel=1e-10)
+    assert float(s.ke[0]) == pytest.approx(ref["ekin"][-1], rel=1e-10)
+
+
+@pytest.mark.parametrize("mode", ["full", "tile"])
+def test_overflow_after_an_unchecked_run_raises(mode):
+    # without checks the steps after the overflow used a truncated list:
+    # reading the status afterwards raises and leaves the flag set
+    from paper_2109_10876_amd import _abi as abi
+    cfg, s = _midrun_overflow_case(mode)
+    say(f"case: unchecked overflow raises {mode}")
+    s.run(cfg.steps, check_every=0)
+    with pytest.raises(abi.ListOverflowError):
+        s.ensure_list()
+    assert int(s.status.item()) & abi.MD_F_NBR_OVERFLOW
+
+
 def test_small_boxes_with_two_cells_per_dimension():
     # replicas of 500 atoms: box 8.398 gives 2 cells of edge >= 2.8 per dimension
     cfg = md_inputs.replica_batch(nrep=5, nmin=500, nmax=700, seed=11)

@@ -589,3 +589,19 @@ def test_langevin_thermostat_reaches_target_temperature():
     n = pos.shape[0]
     tkin = 2.0 * r["ekin"][800:] / (3 * n)
     assert abs(tkin.mean() - target) < 0.08 * target
+
+
+# ------------------------------------------------ all-thread timing build
+
+def test_timing_build_runs_the_same_trajectory():
+    # liborc_omp.so (the all-core CPU baseline) splits the pair search and
+    # the force sum over threads: same pairs, same per-pair arithmetic, only
+    # the summation order of forces, energy and virial differs
+    cfg = md_inputs.lj_fluid(8, temperature=1.0, seed=17)
+    a = oracle.md_run(cfg.pos, cfg.vel, cfg.box[0], RC, SKIN, cfg.dt, 30)
+    b = oracle.md_run(cfg.pos, cfg.vel, cfg.box[0], RC, SKIN, cfg.dt, 30, omp=True)
+    assert np.array_equal(a["rebuild"], b["rebuild"]) and a["rebuild"].any()
+    assert np.abs(a["pos"] - b["pos"]).max() < 1e-11
+    np.testing.assert_allclose(b["epot"], a["epot"], rtol=1e-12)
+    np.testing.assert_allclose(b["virial"], a["virial"], rtol=1e-12)
+    np.testing.assert_allclose(b["ekin"], a["ekin"], rtol=1e-12)
