@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 8
+#define MD_ABI_VERSION 9
 
 /* ------------------------------------------------------------ return codes */
 #define MD_OK            0
@@ -47,6 +47,7 @@ extern "C" {
 #define MD_EUNSUPPORTED -4  /* valid request this build does not implement             */
 #define MD_EHIP         -5  /* a HIP launch failed                                     */
 #define MD_ERANGE       -6  /* sizes beyond the encoding limits below                  */
+#define MD_ESCRATCH     -7  /* batch needs more than MD_NOALLOC_SCRATCH_BYTES          */
 
 /* ------------------------------------------------ device status bits (sticky) */
 #define MD_F_NBR_OVERFLOW 0x1u  /* some atom has more list entries than max_nbr     */
@@ -357,6 +358,24 @@ int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
                  const md_lj *p, int32_t prec, int32_t accumulate,
                  double *energy, double *virial, void *ws, size_t ws_bytes,
                  uint32_t *status, void *stream);
+
+/* md_lj_forces without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Arguments, results, errors and
+ * determinism are those of md_lj_forces (the same kernels, bit for bit).  The
+ * scratch the call needs -- per-work-unit partial sums (n_units rows of 32
+ * bytes) and, for MD_TILE_FULL lists, per-tile partial sums (n_tiles rows of
+ * 32 bytes) -- lives in a fixed array of MD_NOALLOC_SCRATCH_BYTES inside the
+ * library, one per GPU, held from the first call on that GPU until the
+ * process ends.  That first call looks the array up on the current device
+ * (the stream must belong to it); no call allocates.  A batch needing more
+ * returns MD_ESCRATCH before anything is enqueued.  Every call on one GPU
+ * shares its array: calls that may overlap on one GPU (different streams,
+ * or threads) race and must be serialised by the caller. */
+#define MD_NOALLOC_SCRATCH_BYTES (8u << 20)
+int md_lj_forces_noalloc(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
+                         const md_lj *p, int32_t prec, int32_t accumulate, double *energy,
+                         double *virial, uint32_t *status, void *stream);
 
 /* md_lj_forces followed, in the same kernel, by md_vv_step phase 3 for each
  * atom as soon as its force is known (the forces of a step feed its

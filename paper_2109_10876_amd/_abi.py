@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmd.so")
 
 # Constants mirrored from md.h.
-MD_ABI_VERSION = 8
+MD_ABI_VERSION = 9
 MD_OK = 0
 MD_EINVAL = -1
 MD_EBOX = -2
@@ -22,6 +22,8 @@ MD_ENOWS = -3
 MD_EUNSUPPORTED = -4
 MD_EHIP = -5
 MD_ERANGE = -6
+MD_ESCRATCH = -7
+MD_NOALLOC_SCRATCH_BYTES = 8 << 20
 MD_F_NBR_OVERFLOW = 0x1
 MD_F_NONFINITE = 0x2
 MD_F_BOND_BROKEN = 0x4
@@ -56,6 +58,7 @@ EXPORTS = (
     "md_plan_fill",
     "md_tile_plan",
     "md_workspace_bytes", "md_cell_sort", "md_verlet_build", "md_lj_forces",
+    "md_lj_forces_noalloc",
     "md_vv_step", "md_lj_forces_vv", "md_lj_forces_vjp", "md_fene_forces", "md_angle_forces",
     "md_bonded_forces", "md_bonded_reindex", "md_langevin",
 )
@@ -164,6 +167,9 @@ def load():
     lib.md_lj_forces.restype = ctypes.c_int
     lib.md_lj_forces.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32, _i32,
                                  _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]
+    lib.md_lj_forces_noalloc.restype = ctypes.c_int
+    lib.md_lj_forces_noalloc.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32, _i32,
+                                         _vp, _vp, _vp, _vp]
     lib.md_vv_step.restype = ctypes.c_int
     lib.md_vv_step.argtypes = [P(MdBatch), P(MdAtoms), _i32, _dbl, _vp, _i32, _dbl, _vp, _vp,
                                P(MdThermostat), _vp, ctypes.c_size_t, _vp, _vp]

@@ -293,6 +293,17 @@ int tile_vjp(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const
 int timing_begin(hipStream_t s);
 void timing_end(int slot, hipStream_t s);
 
+// md_lj_forces split in two (md_forces.hip): the checks of every argument
+// but the workspace, and the launches given the two scratch regions the
+// call needs -- partial (n_units rows of kPartials doubles) and, for tile
+// lists, tpart (n_tiles rows of kTilePartials doubles).  Every row is written
+// before it is read, so neither region needs clearing.
+int lj_forces_check(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
+                    const md_lj *p, int32_t prec);
+int lj_forces_run(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const md_lj *p,
+                  int32_t prec, int32_t accumulate, double *energy, double *virial,
+                  double *partial, double *tpart, uint32_t *status, hipStream_t s);
+
 // Per-replica fixed-order sums of partial slots k0 and k0+1 (md_forces.hip).
 void launch_finalize_sum2(int R, const int32_t *unit_off, const double *partial, int k0,
                           double *out0, double *out1, hipStream_t s);

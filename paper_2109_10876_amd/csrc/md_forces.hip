@@ -261,40 +261,43 @@ void launch_finalize_sum2(int R, const int32_t *unit_off, const double *partial,
 
 }  // namespace md
 
-extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
-                            const md_lj *p, int32_t prec, int32_t accumulate, double *energy,
-                            double *virial, void *ws, size_t ws_bytes, uint32_t *status,
-                            void *stream)
+namespace md {
+
+int lj_forces_check(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
+                    const md_lj *p, int32_t prec)
 {
-    using namespace md;
     int e = check_batch(b);
     if (e != MD_OK) return e;
     if (!atoms || !atoms->x || !atoms->y || !atoms->z || !atoms->fx || !atoms->fy ||
-        !atoms->fz || !nl || !nl->count || !nl->idx || !p || !p->eps || !p->sig || !ws)
+        !atoms->fz || !nl || !nl->count || !nl->idx || !p || !p->eps || !p->sig)
         return MD_EINVAL;
     if (nl->mode != MD_HALF && nl->mode != MD_FULL && nl->mode != MD_TILE_FULL) return MD_EINVAL;
     if (nl->max_nbr < 1 || nl->ld < b->N || nl->ld % 64 != 0) return MD_EINVAL;
     if (p->ntypes < 1 || p->ntypes > MD_MAX_TYPES || !(p->rc > 0.0)) return MD_EINVAL;
     if (p->ntypes > 1 && !atoms->type) return MD_EINVAL;
     if (prec != MD_FP64 && prec != MD_FP32_MIXED) return MD_EINVAL;
-    const WsLayout l = ws_layout(b);
-    if (ws_bytes < l.total) return MD_ENOWS;
     if (nl->mode == MD_TILE_FULL) {
         if (!tile_list_ok(b, nl) || !nl->cell_start) return MD_EINVAL;
         if (p->ntypes > MD_TILE_MAX_TYPES) return MD_EUNSUPPORTED;
         // a typed list is needed for several types, and only then
         if (p->ntypes > 1 ? (nl->tile_types != p->ntypes || !atoms->type) : nl->tile_types > 1)
             return MD_EINVAL;
-        return tile_forces(b, atoms, nl, p, prec, accumulate, nl->cell_start, energy, virial,
-                           ws_at<double>(ws, l.tile_partial), ws_at<double>(ws, l.partial),
-                           b->n_units, md_tune_get(MD_TUNE_PAIR_BATCH), nullptr, status,
-                           as_stream(stream));
     }
+    return MD_OK;
+}
+
+int lj_forces_run(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, const md_lj *p,
+                  int32_t prec, int32_t accumulate, double *energy, double *virial,
+                  double *partial, double *tpart, uint32_t *status, hipStream_t s)
+{
+    if (nl->mode == MD_TILE_FULL)
+        return tile_forces(b, atoms, nl, p, prec, accumulate, nl->cell_start, energy, virial,
+                           tpart, partial, b->n_units, md_tune_get(MD_TUNE_PAIR_BATCH), nullptr,
+                           status, s);
     ForceArgs a{b->atom_off, b->unit_rep, b->unit_off, b->box, atoms->x, atoms->y, atoms->z,
                 atoms->pos4, atoms->type, nl->count, nl->idx, nl->ld, nl->max_nbr, p->eps,
                 p->sig, p->ntypes, p->shift, p->rc, atoms->fx, atoms->fy, atoms->fz, accumulate,
-                ws_at<double>(ws, l.partial), status};
-    hipStream_t s = as_stream(stream);
+                partial, status};
     const bool half = nl->mode == MD_HALF;
     if (half && !accumulate)
         hipLaunchKernelGGL(k_zero3, dim3((b->N + kUnit - 1) / kUnit), dim3(kUnit), 0, s, b->N,
@@ -304,9 +307,26 @@ extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_n
               atoms->pos4 != nullptr, s);
     timing_end(timed, s);
     if (energy || virial)
-        launch_finalize_sum2(b->R, b->unit_off, ws_at<const double>(ws, l.partial), 0, energy,
-                             virial, s);
+        launch_finalize_sum2(b->R, b->unit_off, partial, 0, energy, virial, s);
     return launch_status();
+}
+
+}  // namespace md
+
+extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
+                            const md_lj *p, int32_t prec, int32_t accumulate, double *energy,
+                            double *virial, void *ws, size_t ws_bytes, uint32_t *status,
+                            void *stream)
+{
+    using namespace md;
+    int e = lj_forces_check(b, atoms, nl, p, prec);
+    if (e != MD_OK) return e;
+    if (!ws) return MD_EINVAL;
+    const WsLayout l = ws_layout(b);
+    if (ws_bytes < l.total) return MD_ENOWS;
+    return lj_forces_run(b, atoms, nl, p, prec, accumulate, energy, virial,
+                         ws_at<double>(ws, l.partial), ws_at<double>(ws, l.tile_partial), status,
+                         as_stream(stream));
 }
 
 extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlist *nl,

@@ -45,6 +45,9 @@ const char *md_strerror(int code)
     case MD_EUNSUPPORTED: return "request not supported by this build";
     case MD_EHIP: return "HIP launch failed";
     case MD_ERANGE: return "size beyond the library's encoding limits";
+    case MD_ESCRATCH:
+        return "batch needs more scratch than the no-allocation call holds "
+               "(MD_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown md error code";
     }
 }

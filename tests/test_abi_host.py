@@ -38,7 +38,7 @@ def test_header_constants_match_binding():
                  "MD_TILE_SLOTS", "MD_TILE_MAX_CELLS", "MD_TILE_MAX_ROWS", "MD_TILE_MAX_TYPES",
                  "MD_TUNE_PAIR_BATCH", "MD_TUNE_TILE_THREADS", "MD_TUNE_TILE_STAGE_PACKED",
                  "MD_TUNE_TILE_SLOTS", "MD_MAX_BONDS", "MD_MAX_ANGLES", "MD_BY_ID",
-                 "MD_BY_INDEX"):
+                 "MD_BY_INDEX", "MD_ESCRATCH"):
         m = re.search(rf"#define\s+{name}\s+(-?\w+)", src)
         assert m, name
         assert int(m.group(1), 0) == getattr(abi, name), name
@@ -194,6 +194,39 @@ def test_angle_forces_reject_bad_arguments_without_a_gpu():
                                    None, None) == abi.MD_EINVAL
     assert lib.md_angle_forces(P(ok), P(full), P(ang), 1.5, None, None, 8, 16,
                                None, None) == abi.MD_ENOWS
+
+
+def test_noalloc_forces_check_arguments_and_scratch_size_without_a_gpu():
+    # everything md_lj_forces checks, then the fixed scratch size, all on the
+    # host before the scratch array is looked up on a device
+    lib = abi.load()
+    P = ctypes.byref
+    full = abi.MdAtoms(*([8] * 17))
+    lj1 = abi.MdLj(1, 1, 2.5, 8, 8)
+    nl = abi.MdNlist(abi.MD_FULL, 64, 1024, 0, 8, 8, 0, 1, 1, 0, None, None, None, None)
+    assert lib.md_lj_forces_noalloc(P(abi.MdBatch()), P(full), P(nl), P(lj1), 0, 0, None, None,
+                                    None, None) == abi.MD_EINVAL
+    ok = abi.MdBatch(1, 1000, 27, 4, 8, 8, 8, 8, 8, 8)
+    assert lib.md_lj_forces_noalloc(P(ok), P(full), P(nl), P(lj1), 5, 0, None, None, None,
+                                    None) == abi.MD_EINVAL
+    assert lib.md_lj_forces_noalloc(P(ok), None, P(nl), P(lj1), 0, 0, None, None, None,
+                                    None) == abi.MD_EINVAL
+    # 32 bytes per work unit (and per tile): 2^18 rows fit, one more does not
+    rows = abi.MD_NOALLOC_SCRATCH_BYTES // 32
+    n = abi.MD_MAX_ATOMS // 64 * 64   # ld a multiple of 64; two replicas give rows + 1 units
+    nlb = abi.MdNlist(abi.MD_FULL, 64, n, 0, 8, 8, 0, 1, 1, 0, None, None, None, None)
+    big = abi.MdBatch(2, n, 54, rows + 1, 8, 8, 8, 8, 8, 8)
+    assert lib.md_lj_forces_noalloc(P(big), P(full), P(nlb), P(lj1), 0, 0, None, None, None,
+                                    None) == abi.MD_ESCRATCH
+    # tile lists add one row per tile
+    cap = lib.md_tile_capacity()
+    nt, nu = rows - 32767, 32768   # tile lists: ld <= 2^23 atoms
+    tl = abi.MdNlist(abi.MD_TILE_FULL, 64, 1 << 23, 1, 16, 16, nt, 1, 1, 0, 16, 16, None, 16,
+                     cap, 0, 16)
+    tb = abi.MdBatch(1, 1 << 23, nt, nu, 8, 8, 8, 8, 8, 8)
+    assert lib.md_lj_forces_noalloc(P(tb), P(full), P(tl), P(lj1), 0, 0, None, None, None,
+                                    None) == abi.MD_ESCRATCH
+    assert "scratch" in abi.strerror(abi.MD_ESCRATCH)
 
 
 def test_kernel_timing_arguments_and_empty_read():
