@@ -257,7 +257,8 @@ const char *md_strerror(int code);
 #define MD_TUNE_TILE_SLOTS 3   /* staged capacity of the 256-thread tile shape:
                                   0 (default) or 3072 (up to 64 cells per tile),
                                   2048 (16 cells) or 1536 (8 cells).  Less LDS
-                                  per workgroup lets more of them share a CU.
+                                  per workgroup lets more of them share a CU
+                                  (force kernels: two, three and four).
                                   Change it only before a rebuild of
                                   MD_TILE_FULL lists.                           */
 #define MD_TUNE_NKNOBS     4

@@ -27,7 +27,7 @@ template <class SH, int PREC, int U, bool P4, int TY, int FUSE>
 __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
 {
     constexpr int TB = SH::TB, CAP = SH::CAP;
-    __shared__ TileStage<CAP, SH::MAXC> st;
+    __shared__ TilePlanes<CAP> st;
     __shared__ double red[4][TB / kWave];
     __shared__ PolyConst ptab[TY ? kTileMaxTypes * kTileMaxTypes : 1];
     // launch slot -> tile; with the occupied-tile list, slot k takes its

@@ -23,8 +23,9 @@ constexpr int kMaxStagedRows = (MD_TILE_MAX_ROWS + 2) * (MD_TILE_MAX_ROWS + 2);
 // Workgroup shapes of the tile kernels: TB threads (at most TB home atoms per
 // pass), CAP staged slots (3 x 8 CAP bytes of LDS), MAXC cells per tile
 // along x.  LDS per workgroup bounds how many workgroups share a CU (160 KiB
-// each): the 3072-slot shape fits two, the 2048-slot shape three and the
-// 1536-slot shape four.
+// each; measured on MI355X: three workgroups of up to 53,760 bytes, four of
+// up to 40,960): the force kernel of the 3072-slot shape fits two, of the
+// 2048-slot shape three and of the 1536-slot shape four.
 template <int TB_, int CAP_, int MAXC_>
 struct TileShape {
     static constexpr int TB = TB_, CAP = CAP_, MAXC = MAXC_;
@@ -103,6 +104,15 @@ struct TileStage {
     int rowc[kChunks];                 // staged row holding slot 64 c (first row if several)
 };
 
+// The position planes of TileStage alone (same layout and pad slot): all
+// that the force kernel keeps in LDS, so that its workgroups use less of it.
+template <int CAP>
+struct TilePlanes {
+    static constexpr int kCap = CAP;
+    static constexpr int kStride = (CAP + 1 + 63) / 64 * 64 + 1;
+    double x[kStride], y[kStride], z[kStride];
+};
+
 // Coordinate of the pad slot: every distance to it is far beyond any cutoff
 // and its pair terms stay finite in single precision.
 constexpr double kPadCoord = 1.0e15;
@@ -115,7 +125,9 @@ __device__ __forceinline__ int staged_row(const TileSpec &s, int dy, int dz)
 
 // Staging record of a tile, written by the list build for the force kernel:
 // word sl (< staged count) holds slot sl's source atom in its low 26 bits
-// and the image shift of x, y, z in two bits each (0: none, 1: +L, 2: -L);
+// and the image shift of x, y, z in two bits each, a signed two-bit number
+// (0: none, 1: +L, 3: -L), so that a sign-extending field extract gives the
+// multiple of L to add;
 // word kTabTotal holds the staged count; words kTabAdj .. +63 hold the
 // adjoint's per-tile (eps, sigma) sums (32 doubles).  tab_stride words per
 // tile.
@@ -129,13 +141,24 @@ constexpr int tab_stride(int cap) { return cap + 128; }
 
 __device__ __forceinline__ uint32_t shift_code(double d)
 {
-    return d > 0.0 ? 1u : (d < 0.0 ? 2u : 0u);
+    return d > 0.0 ? 1u : (d < 0.0 ? 3u : 0u);
 }
 
-__device__ __forceinline__ double shift_of(uint32_t c, double L)
+// p + s L for the signed two-bit field of `code` at bit `at` (s in -1, 0, 1):
+// s L is exact, so this equals p + L, p - L or p bit for bit.
+__device__ __forceinline__ double apply_shift(double p, uint32_t code, int at, double L)
 {
-    c &= 3u;
-    return c == 1u ? L : (c == 2u ? -L : 0.0);
+    const int sh = __builtin_amdgcn_sbfe(int(code), at, 2);
+    return fma(static_cast<double>(sh), L, p);
+}
+
+// Element `i` of a device array whose byte size is below 4 GiB, addressed by
+// a 32-bit byte offset (one shift and a scalar base per load).
+template <class T>
+__device__ __forceinline__ T load_at(const T *__restrict__ base, uint32_t i)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                        (i * uint32_t(sizeof(T))));
 }
 
 // Fills the staging tables and stages positions (x, y, z planes or the
@@ -349,31 +372,32 @@ __device__ int stage_from_table(const TileSpec &s, const uint32_t *__restrict__ 
     if (!mid()) return -1;
     if (total > cap) return total;
     double px[kPer], py[kPer], pz[kPer];
+    const uint32_t last = uint32_t(n_atoms - 1);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-        const int src = min(int(code[k] & kTabSrcMask), n_atoms - 1);
+        const uint32_t src = min(code[k] & kTabSrcMask, last);
         if (lsrc) {
             const int sl = tid + k * TB;
-            if (sl < total) lsrc[sl] = src;
+            if (sl < total) lsrc[sl] = int(src);
         }
         if (P4) {
-            const double4 v = reinterpret_cast<const double4 *>(pos4)[src];
+            const double4 v = load_at(reinterpret_cast<const double4 *>(pos4), src);
             px[k] = v.x;
             py[k] = v.y;
             pz[k] = v.z;
         } else {
-            px[k] = x[src];
-            py[k] = y[src];
-            pz[k] = z[src];
+            px[k] = load_at(x, src);
+            py[k] = load_at(y, src);
+            pz[k] = load_at(z, src);
         }
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int sl = tid + k * TB;
         if (sl < total) {
-            st.x[sl] = px[k] + shift_of(code[k] >> kTabShiftX, s.L[0]);
-            st.y[sl] = py[k] + shift_of(code[k] >> kTabShiftY, s.L[1]);
-            st.z[sl] = pz[k] + shift_of(code[k] >> kTabShiftZ, s.L[2]);
+            st.x[sl] = apply_shift(px[k], code[k], kTabShiftX, s.L[0]);
+            st.y[sl] = apply_shift(py[k], code[k], kTabShiftY, s.L[1]);
+            st.z[sl] = apply_shift(pz[k], code[k], kTabShiftZ, s.L[2]);
         }
     }
     __syncthreads();
