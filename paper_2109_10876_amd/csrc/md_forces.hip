@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kUnit) void k_lj(ForceArgs a)
         const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
         const int ti = TYPED ? a.type[i] : 0;
         const int n = min(a.count[i], a.max_nbr);
-        Acc c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
+        Acc c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f, 0u};
         const uint32_t *col = a.idx + i;
         int k = 0;
         for (; k + U <= n; k += U) {

@@ -33,6 +33,7 @@ __device__ __forceinline__ PairConst pair_const(double eps, double sig, double r
 struct Acc {
     double fx, fy, fz, ed, wd;
     float ef, wf;
+    uint32_t n;   // pairs inside the cutoff (lj_pair_sums)
 };
 
 // Cutoff test (always in double) and pair terms of one displacement; adds
@@ -132,6 +133,49 @@ __device__ __forceinline__ void lj_pair_masked(const PolyConst &pc, double dx, d
     c.fx = fma(fr, dx, c.fx);
     c.fy = fma(fr, dy, c.fy);
     c.fz = fma(fr, dz, c.fz);
+}
+
+// One atom type, energy and virial as sums: with w = q3 (A q3 - B) the
+// virial term fr r^2, and A = 12 C, B = 6 D, a pair's energy is
+// U = w / 12 - (D / 2) q3 - U(rc).  Each atom therefore sums w (its virial),
+// q3 and its count of pairs inside the cutoff, from which its energy follows
+// once (pair_sums_energy): three accumulations per pair instead of the four
+// of the polynomial form.  Acc holds sum w in wd / wf, sum q3 in ed / ef and
+// the count in n.
+template <int PREC>
+__device__ __forceinline__ void lj_pair_sums(const PolyConst &pc, double dx, double dy,
+                                             double dz, double rc2, Acc &c)
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < rc2)) return;
+    double fr;
+    if (PREC == MD_FP64) {
+        const double q = rcp_f64(r2);
+        const double q3 = q * q * q;
+        const double w = q3 * (pc.A * q3 - pc.B);
+        fr = w * q;
+        c.wd += w;
+        c.ed += q3;
+    } else {
+        const float q = __builtin_amdgcn_rcpf(static_cast<float>(r2));
+        const float q3 = q * q * q;
+        const float w = q3 * fmaf(pc.Af, q3, -pc.Bf);
+        const float frf = w * q;
+        c.wf += w;
+        c.ef += q3;
+        fr = static_cast<double>(frf);
+    }
+    c.n += 1u;
+    c.fx = fma(fr, dx, c.fx);
+    c.fy = fma(fr, dy, c.fy);
+    c.fz = fma(fr, dz, c.fz);
+}
+
+// The atom's energy from the sums of lj_pair_sums (sum w, sum q3, count).
+__device__ __forceinline__ double pair_sums_energy(const PolyConst &pc, double sw, double sq3,
+                                                   uint32_t n)
+{
+    return sw * (1.0 / 12.0) - 0.5 * pc.D * sq3 - pc.ush * double(n);
 }
 
 // The same pair terms from the force constants of one type pair alone:

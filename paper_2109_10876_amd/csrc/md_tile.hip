@@ -102,7 +102,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
         const char *stb = reinterpret_cast<const char *>(st.x);
         constexpr int kY = int(sizeof(double)) * decltype(st)::kStride;
         while (hk < nh) {
-            Acc c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
+            Acc c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f, 0u};
             PairAB<PREC> k0{}, k1{};
             if (TY == 2) {
                 k0 = pair_ab<PREC>(ptab[ti4]);
@@ -137,9 +137,11 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
                     if (TY == 2)
                         lj_pair_ab<PREC>(select_ab<PREC>(ent[q] & 1u, k0, k1), xi - px[q],
                                          yi - py[q], zi - pz[q], rc2, c);
+                    else if (TY)
+                        lj_pair_masked<PREC>(ptab[ti4 + (ent[q] & 7)], xi - px[q], yi - py[q],
+                                             zi - pz[q], rc2, c);
                     else
-                        lj_pair_masked<PREC>(TY ? ptab[ti4 + (ent[q] & 7)] : pc, xi - px[q],
-                                             yi - py[q], zi - pz[q], rc2, c);
+                        lj_pair_sums<PREC>(pc, xi - px[q], yi - py[q], zi - pz[q], rc2, c);
                 }
 #pragma unroll
                 for (int b = 0; b < NB; ++b) cur[b] = nxt[b];
@@ -149,6 +151,8 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
                 ed = static_cast<double>(c.ef);
                 wd = static_cast<double>(c.wf);
             }
+            // one type: the energy follows from the sums of lj_pair_sums
+            if (!TY) ed = pair_sums_energy(pc, wd, ed, c.n);
             e_acc += 0.5 * ed;
             w_acc += 0.5 * wd;
             double gx = c.fx, gy = c.fy, gz = c.fz;   // the atom's force
