@@ -88,7 +88,7 @@ __device__ __forceinline__ TileSpec tile_spec(int t, const int32_t *__restrict__
 template <int CAP, int MAXC>
 struct TileStage {
     static constexpr int kCap = CAP;
-    static constexpr int kStride = (CAP + 1 + 63) / 64 * 64 + 1;
+    static constexpr int kStride = CAP + 2;   // pad slot included, planes 16-byte aligned
     static constexpr int kRowStage = MAXC + 3;   // cell starts a-1 .. b+2 of one staged row
     double x[kStride], y[kStride], z[kStride];
     int row_slot[kMaxStagedRows + 1];  // first slot of staged row q; [nrows] = total

@@ -22,6 +22,38 @@ __device__ __forceinline__ void put_entry(const TileArgs &a, int k, int i, uint1
         e;
 }
 
+// Register path: a wave gathers one home atom's entries in its LDS buffer
+// (entry kb + e at wb[e], kb a multiple of 8) and stores them a block of 8
+// entries (16 bytes) per lane, lane b taking block kb / 8 + b: one store
+// instruction per home atom instead of a scattered 2-byte store per hit.
+// 288 entries per wave keep the build's LDS within three workgroups per CU.
+constexpr int kWaveBuf = 288;
+
+__device__ __forceinline__ void store_block(const TileArgs &a, const uint16_t *wb, int i, int kb,
+                                            int b)
+{
+    const uint4 v = *reinterpret_cast<const uint4 *>(wb + 8 * b);
+    *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(a.idx) + tile_entry_byte(kb + 8 * b, i, a.ld)) =
+        v;
+}
+
+// Store the buffer's whole blocks (those below max_nbr) and move the partial
+// block to the front; returns the new kb.  Every lane of the wave calls it.
+// Taken only when a group of chunks could overrun the buffer (about 100
+// entries in hand already), so rarely on a liquid.
+__device__ __forceinline__ int flush_blocks(const TileArgs &a, uint16_t *wb, int i, int kb, int cnt,
+                                            int lane)
+{
+    const int nfb = (cnt - kb) >> 3, rest = (cnt - kb) & 7;
+    __builtin_amdgcn_wave_barrier();
+    if (lane < nfb && kb + 8 * lane < a.max_nbr) store_block(a, wb, i, kb, lane);
+    const uint16_t t = lane < rest ? wb[8 * nfb + lane] : uint16_t(0);
+    __builtin_amdgcn_wave_barrier();
+    if (lane < rest) wb[lane] = t;
+    __builtin_amdgcn_wave_barrier();
+    return kb + 8 * nfb;
+}
+
 // Lanes 0 .. nb-1 of a wavefront hold the entry counts of home atoms
 // hb .. hb+nb-1: store them and flag overflow.
 __device__ __forceinline__ void store_counts(const TileArgs &a, int hb, int nb, int lane, int vcnt)
@@ -50,8 +82,9 @@ __device__ __forceinline__ void store_counts(const TileArgs &a, int hb, int nb, 
 // atom (all within two cell diagonals of it), with rl^2 raised by 2^-40
 // relative: more than the rounding of either side, so every pair within rl
 // is kept and a pair kept beyond it lies within rounding of rl.  The own atom
-// is lane j of chunk 0.  The hits of one chunk are consecutive entries of
-// the home atom, so their stores fall into one or two 8-entry blocks.
+// is lane j of chunk 0.  A chunk's hits go to the wave's LDS buffer (one
+// 2-byte LDS store per hitting lane, at the count of hits before it), and
+// the home atom's finished list leaves it as 16-byte blocks.
 template <class SH, bool P4>
 __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) void k_tile_build(
     TileArgs a)
@@ -60,9 +93,11 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
     constexpr int kWaves = TB / kWave;
     constexpr int C = kFlatChunks;
     __shared__ TileStage<CAP, SH::MAXC> st;
+    __shared__ __attribute__((aligned(16))) uint16_t wbuf[kWaves][kWaveBuf];
     if (sole_replica_gated_off(a.gate, a.R)) return;
     const int lane = __lane_id();
     const int wid = uniform(threadIdx.x / kWave);
+    uint16_t *const wb = wbuf[wid];
     const uint16_t pad = uint16_t(CAP * 8);
     const double rl2x = a.rl2 * (1.0 + 0x1p-40);
     for (int lt = blockIdx.x; lt < a.n_tiles; lt += gridDim.x) {
@@ -159,28 +194,35 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
                     const double tx = 2.0 * hx, ty = 2.0 * hy, tz = 2.0 * hz;
                     const double rhs = fma(hx, hx, fma(hy, hy, hz * hz)) - rl2x;
                     int cnt = 0;
+                    int kb = 0;
 #pragma unroll
                     for (int g = 0; g < C; g += kChunkGroup) {
                         if (g >= nch) break;
+                        // room for the group's hits (at most its candidates) and the pad
+                        if (cnt - kb + min(kChunkGroup * kWave, T - g * kWave) + 16 > kWaveBuf)
+                            kb = flush_blocks(a, wb, i, kb, cnt, lane);
 #pragma unroll
                         for (int c = g; c < g + kChunkGroup; ++c) {
                             const double lhs = fma(tx, px[c], fma(ty, py[c], fma(tz, pz[c], -pp[c])));
                             bool take = lhs > rhs;
                             if (c == 0) take = take && lane != j;
                             const uint64_t m = __builtin_amdgcn_ballot_w64(take);
-                            const int k = int(__builtin_amdgcn_mbcnt_hi(
-                                uint32_t(m >> 32),
-                                __builtin_amdgcn_mbcnt_lo(uint32_t(m), uint32_t(cnt))));
-                            if (take && k < a.max_nbr) put_entry(a, k, i, uint16_t(ent[c]));
+                            if (take) {
+                                const int r = int(__builtin_amdgcn_mbcnt_hi(
+                                    uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
+                                wb[cnt - kb + r] = uint16_t(ent[c]);
+                            }
                             cnt += int(__popcll(m));
                         }
                     }
-                    // pad to a multiple of 16 (past max_nbr nothing is stored;
-                    // the count flags the overflow)
-                    if (cnt <= a.max_nbr) {
-                        const int kk = cnt + lane;
-                        if (kk < ((cnt + 15) & ~15)) put_entry(a, kk, i, pad);
-                    }
+                    // pad to a multiple of 16, then store the buffered blocks
+                    // (past max_nbr nothing is stored; the count flags the overflow)
+                    const int n16 = (cnt + 15) & ~15;
+                    if (cnt + lane < n16) wb[cnt - kb + lane] = pad;
+                    __builtin_amdgcn_wave_barrier();
+                    const int kend = min(n16, a.max_nbr);
+                    if (kb + 8 * lane < kend) store_block(a, wb, i, kb, lane);
+                    __builtin_amdgcn_wave_barrier();
                     vcnt = lane == j ? cnt : vcnt;
                 }
                 store_counts(a, g0, nown, lane, vcnt);
