@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 9
+#define MD_ABI_VERSION 10
 
 /* ------------------------------------------------------------ return codes */
 #define MD_OK            0
@@ -186,6 +186,20 @@ typedef struct md_nlist {
                                  and md_lj_forces_vv then give workgroups to
                                  listed tiles only, so the vacuum of a sparse
                                  system costs no staging.  NULL: every tile. */
+    const int32_t *tile_m;    /* MD_TILE_FULL, optional: [R] device, replica r's
+                                 cells per tile along x (1 .. tile_cells), the
+                                 h_tile_m the tiles were planned with, so that
+                                 each replica takes the largest tiles its own
+                                 cell occupancy fits.  NULL: tile_cells for
+                                 every replica.                                */
+    int32_t *tile_todo;       /* MD_TILE_FULL, optional: [n_tiles + 1] device
+                                 scratch of md_verlet_build on a batch (R > 1)
+                                 called with a gate: it first lists the tiles
+                                 of the replicas to rebuild there (their count,
+                                 then the tiles), so that a workgroup per
+                                 listed tile builds and every other one returns
+                                 after one load.  NULL: each tile reads its
+                                 replica's gate.                               */
 } md_nlist;
 
 /* Lennard-Jones parameters (Eq. lj: U = 4 eps [(sig/r)^12 - (sig/r)^6] for
@@ -306,11 +320,14 @@ int md_plan_fill(int32_t R, const int32_t *h_natoms, const double *h_box,
                  int32_t *h_unit_rep, int32_t *h_unit_off);
 
 /* Tiles of MD_TILE_FULL lists: with h_tile_rep/h_tile_off NULL returns the
- * number of tiles of tile_cells x tile_py x tile_pz cells (h_ncell as from
- * md_plan_fill); otherwise also fills h_tile_rep[n_tiles] and
- * h_tile_off[R+1].  Negative MD_E* on bad arguments. */
-int md_tile_plan(int32_t R, const int32_t *h_ncell, int32_t tile_cells, int32_t tile_py,
-                 int32_t tile_pz, int32_t *h_tile_rep, int32_t *h_tile_off);
+ * number of tiles of m_r x tile_py x tile_pz cells (h_ncell as from
+ * md_plan_fill), m_r = h_tile_m[r] (optional [R] host array, each in
+ * 1 .. tile_cells) or tile_cells for every replica when h_tile_m is NULL;
+ * otherwise also fills h_tile_rep[n_tiles] and h_tile_off[R+1].  Negative
+ * MD_E* on bad arguments. */
+int md_tile_plan(int32_t R, const int32_t *h_ncell, int32_t tile_cells,
+                 const int32_t *h_tile_m, int32_t tile_py, int32_t tile_pz,
+                 int32_t *h_tile_rep, int32_t *h_tile_off);
 
 /* Bytes of the device workspace used by the calls below for this batch.
  * The workspace must be zero-filled once after allocation; every call

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmd.so")
 
 # Constants mirrored from md.h.
-MD_ABI_VERSION = 9
+MD_ABI_VERSION = 10
 MD_OK = 0
 MD_EINVAL = -1
 MD_EBOX = -2
@@ -85,7 +85,7 @@ class MdNlist(ctypes.Structure):
                 ("tile_pz", _i32), ("tile_types", _i32),
                 ("tile_rep", _vp), ("tile_off", _vp), ("tile_need", _vp), ("cell_start", _vp),
                 ("tile_src_cap", _i32), ("_pad", _i32), ("tile_src", _vp),
-                ("tile_active", _vp)]
+                ("tile_active", _vp), ("tile_m", _vp), ("tile_todo", _vp)]
 
 
 class MdLj(ctypes.Structure):
@@ -155,7 +155,7 @@ def load():
     lib.md_copy_probe.restype = ctypes.c_int
     lib.md_copy_probe.argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
     lib.md_tile_plan.restype = ctypes.c_int
-    lib.md_tile_plan.argtypes = [_i32, _vp, _i32, _i32, _i32, _vp, _vp]
+    lib.md_tile_plan.argtypes = [_i32, _vp, _i32, _vp, _i32, _i32, _vp, _vp]
     lib.md_workspace_bytes.restype = ctypes.c_size_t
     lib.md_workspace_bytes.argtypes = [P(MdBatch)]
     lib.md_cell_sort.restype = ctypes.c_int

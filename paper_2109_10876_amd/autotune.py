@@ -9,8 +9,9 @@ timing a short graphed run of the real step for each candidate:
   * tile-local lists: workgroup size (MD_TUNE_TILE_THREADS), staged
     capacity (MD_TUNE_TILE_SLOTS: less LDS, more workgroups per CU), rows per tile
     (1 x 1, 2 x 1 or 2 x 2 in y x z) and cells per tile along x, the last
-    swept the paper's way -- from the fewest (largest) tiles that fit, make
-    tiles smaller (more of them) while the time keeps dropping;
+    swept the paper's way -- from the fewest (largest) tiles that fit (chosen
+    per replica in a batch: tile_cells None), make tiles smaller (more of
+    them, the same width for every replica) while the time keeps dropping;
   * neighbour-gather batch (MD_TUNE_PAIR_BATCH);
   * on tile lists, the fused force + integrator call or the split calls
     (when the factory takes ``fuse``).
@@ -114,7 +115,10 @@ def tune(make, key, steps=40, warmup=10, cache=DEFAULT_CACHE, retune=False, log=
             if log:
                 log(f"autotune {json.dumps(c)} -> not usable ({exc})")
             return math.inf
-        c = dict(c, tile_cells=tc) if c["mode"] == "tile" else c
+        if c["mode"] == "tile":
+            # the automatic width stays automatic (per replica in a batch);
+            # its largest value starts the sweep below
+            c = dict(c, tile_cells_max=tc) if c.get("tile_cells") is None else c
         trials.append((c, ms))
         if log:
             log(f"autotune {json.dumps(c)} -> {ms:.4f} ms/step ({time.perf_counter() - t0:.1f} s)")
@@ -131,7 +135,7 @@ def tune(make, key, steps=40, warmup=10, cache=DEFAULT_CACHE, retune=False, log=
         best_ms = run(dict(base, tile_cells=None))
         if math.isinf(best_ms):
             continue
-        m = trials[-1][0]["tile_cells"]
+        m = trials[-1][0]["tile_cells_max"]
         while m and m > 2:
             m = max(2, m - max(1, m // 4))
             ms = run(dict(base, tile_cells=m))

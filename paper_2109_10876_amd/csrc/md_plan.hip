@@ -115,8 +115,9 @@ int md_plan_fill(int32_t R, const int32_t *h_natoms, const double *h_box, double
     return MD_OK;
 }
 
-int md_tile_plan(int32_t R, const int32_t *h_ncell, int32_t tile_cells, int32_t tile_py,
-                 int32_t tile_pz, int32_t *h_tile_rep, int32_t *h_tile_off)
+int md_tile_plan(int32_t R, const int32_t *h_ncell, int32_t tile_cells,
+                 const int32_t *h_tile_m, int32_t tile_py, int32_t tile_pz,
+                 int32_t *h_tile_rep, int32_t *h_tile_off)
 {
     if (R < 1 || !h_ncell || tile_cells < 1 || tile_cells > MD_TILE_MAX_CELLS) return MD_EINVAL;
     if (tile_py < 1 || tile_py > MD_TILE_MAX_ROWS || tile_pz < 1 || tile_pz > MD_TILE_MAX_ROWS)
@@ -125,8 +126,10 @@ int md_tile_plan(int32_t R, const int32_t *h_ncell, int32_t tile_cells, int32_t 
     for (int32_t r = 0; r < R; ++r) {
         const int32_t nx = h_ncell[3 * r], ny = h_ncell[3 * r + 1], nz = h_ncell[3 * r + 2];
         if (nx < 1 || ny < 1 || nz < 1) return MD_EINVAL;
+        const int32_t m = h_tile_m ? h_tile_m[r] : tile_cells;
+        if (m < 1 || m > tile_cells) return MD_EINVAL;
         const int64_t nt = int64_t((ny + tile_py - 1) / tile_py) * ((nz + tile_pz - 1) / tile_pz) *
-                           ((nx + tile_cells - 1) / tile_cells);
+                           ((nx + m - 1) / m);
         if (h_tile_off) h_tile_off[r] = static_cast<int32_t>(t);
         if (h_tile_rep)
             for (int64_t k = 0; k < nt; ++k) h_tile_rep[t + k] = r;

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
         t = min(max(a.active[1 + lt], 0), a.n_tiles - 1);
     }
     const int row = lt;   // partial row: the tile itself, or its place in the list
-    const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
+    const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g, a.tile_m);
     const PolyConst pc = poly_const(a.eps[0], a.sig[0], a.rc, a.shift);
     const double rc2 = a.rc * a.rc;
     if (TY) {

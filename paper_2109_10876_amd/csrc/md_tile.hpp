@@ -54,7 +54,8 @@ __device__ __forceinline__ TileSpec tile_spec(int t, const int32_t *__restrict__
                                               const int32_t *__restrict__ tile_off,
                                               const int32_t *__restrict__ ncell,
                                               const int32_t *__restrict__ cell_off,
-                                              const double *__restrict__ box, TileGrid g)
+                                              const double *__restrict__ box, TileGrid g,
+                                              const int32_t *__restrict__ tile_m)
 {
     TileSpec s;
     s.rep = tile_rep[t];
@@ -62,12 +63,15 @@ __device__ __forceinline__ TileSpec tile_spec(int t, const int32_t *__restrict__
     s.ny = ncell[3 * s.rep + 1];
     s.nz = ncell[3 * s.rep + 2];
     s.coff = cell_off[s.rep];
+    // the replica's cells per tile along x (never above g.m, which sizes the
+    // LDS tables)
+    const int m = tile_m ? min(max(tile_m[s.rep], 1), g.m) : g.m;
     const int local = t - tile_off[s.rep];
-    const int tx = (s.nx + g.m - 1) / g.m, ty = (s.ny + g.py - 1) / g.py;
+    const int tx = (s.nx + m - 1) / m, ty = (s.ny + g.py - 1) / g.py;
     const int bx = local % tx, rest = local / tx;
     const int by = rest % ty, bz = rest / ty;
-    s.a = bx * g.m;
-    s.b = min(s.a + g.m, s.nx) - 1;
+    s.a = bx * m;
+    s.b = min(s.a + m, s.nx) - 1;
     s.y0 = by * g.py;
     s.hy = min(s.y0 + g.py, s.ny) - s.y0;
     s.z0 = bz * g.pz;
@@ -472,6 +476,7 @@ __device__ __forceinline__ int home_index(const HomeRows &hr, int k)
 // Arguments of the tile kernels (list build and forces).
 struct TileArgs {
     const int32_t *tile_rep, *tile_off, *ncell, *cell_off;
+    const int32_t *tile_m;   // per-replica cells per tile along x, or null
     const double *box;
     const uint32_t *gate;
     const double *x, *y, *z, *pos4;
@@ -501,6 +506,7 @@ struct TileArgs {
     uint32_t *status;
     int32_t R;
     int32_t *active;  // occupied-tile list (md_nlist.tile_active) or null
+    const int32_t *todo;   // list build: tiles to rebuild (count, tiles) or null
 };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -530,6 +536,7 @@ inline TileArgs tile_args(const md_batch *b, const md_atoms *atoms, const md_nli
     TileArgs a{};
     a.tile_rep = nl->tile_rep;
     a.tile_off = nl->tile_off;
+    a.tile_m = nl->tile_m;
     a.ncell = b->ncell;
     a.cell_off = b->cell_off;
     a.box = b->box;

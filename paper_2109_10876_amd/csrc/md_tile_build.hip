@@ -100,9 +100,12 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
     uint16_t *const wb = wbuf[wid];
     const uint16_t pad = uint16_t(CAP * 8);
     const double rl2x = a.rl2 * (1.0 + 0x1p-40);
-    for (int lt = blockIdx.x; lt < a.n_tiles; lt += gridDim.x) {
-        const int t = xcd_chunked(lt, a.n_tiles, kTileXcdChunk);
-        const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
+    // with a to-do list, workgroups past its count return after one load
+    const int n_work = a.todo ? a.todo[0] : a.n_tiles;
+    for (int lt = blockIdx.x; lt < n_work; lt += gridDim.x) {
+        const int t = a.todo ? a.todo[1 + xcd_chunked(lt, n_work, kTileXcdChunk)]
+                             : xcd_chunked(lt, a.n_tiles, kTileXcdChunk);
+        const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g, a.tile_m);
         if (a.gate != nullptr && a.gate[s.rep] == 0u) continue;
         const int home = tile_home_atoms(s, a.cell_start);
         // occupancy for the occupied-tile list (listed by k_tile_compact)
@@ -273,6 +276,49 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
 }
 
+// The to-do list of a batch's list build: the tiles of every replica whose
+// gate is set, replica by replica, after their count.  One workgroup scans
+// the replicas kFin at a time (per-replica tile counts, a block prefix sum),
+// then each wave writes the tile ranges of its replicas.
+__global__ __launch_bounds__(kFin) void k_tile_todo(int R, const uint32_t *__restrict__ gate,
+                                                    const int32_t *__restrict__ tile_off,
+                                                    int32_t *__restrict__ todo)
+{
+    constexpr int kW = kFin / kWave;
+    __shared__ int start[kFin];
+    __shared__ int wsum[kW];
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    int carry = 0;
+    for (int base = 0; base < R; base += kFin) {
+        const int r = base + tid;
+        const int n = r < R && gate[r] != 0u ? tile_off[r + 1] - tile_off[r] : 0;
+        int inc = n;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int up = __shfl_up(inc, o, kWave);
+            if (lane >= o) inc += up;
+        }
+        if (lane == kWave - 1) wsum[wid] = inc;
+        __syncthreads();
+        int before = carry, total = carry;
+        for (int w = 0; w < kW; ++w) {
+            before += w < wid ? wsum[w] : 0;
+            total += wsum[w];
+        }
+        start[tid] = before + inc - n;
+        __syncthreads();
+        for (int q = wid; q < kFin && base + q < R; q += kW) {
+            const int rr = base + q;
+            if (gate[rr] == 0u) continue;
+            const int t0 = tile_off[rr], nt = tile_off[rr + 1] - t0, s0 = start[q];
+            for (int k = lane; k < nt; k += kWave) todo[1 + s0 + k] = t0 + k;
+        }
+        carry = total;
+        __syncthreads();
+    }
+    if (tid == 0) todo[0] = carry;
+}
+
 // The occupied-tile list of one replica: the tiles whose flag the build set,
 // in ascending order, after the count.  One workgroup scans the flags in
 // passes of kFin tiles (each wave's prefix from a ballot, the waves' totals
@@ -319,6 +365,11 @@ int tile_build(const md_batch *b, const md_atoms *atoms, const int32_t *cell_sta
     a.need = need;
     a.status = status;
     a.active = nl->tile_active;   // one replica only (checked by the caller)
+    if (gate && b->R > 1 && nl->tile_todo) {
+        hipLaunchKernelGGL(k_tile_todo, dim3(1), dim3(kFin), 0, s, b->R, gate, nl->tile_off,
+                           nl->tile_todo);
+        a.todo = nl->tile_todo;
+    }
     // one workgroup per tile, gated or not: the hardware hands tiles to
     // whichever workgroup slot frees first, so uneven tiles (vacuum, surface)
     // balance themselves; a gated-off tile costs a launch slot only

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_vjp(TileArgs a)
     __shared__ VjpConst tab[kAdjSlots];
     __shared__ double red[2 * NS][kW];
     const int t = xcd_chunked(blockIdx.x, gridDim.x, kTileXcdChunk);
-    const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g);
+    const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g, a.tile_m);
     uint32_t *rec = a.tile_src + size_t(t) * tab_stride(CAP);
     double *adj = reinterpret_cast<double *>(rec + kTabAdj<TileStage<CAP, SH::MAXC>>);
     if (threadIdx.x < NS) {

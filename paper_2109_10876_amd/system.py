@@ -37,16 +37,27 @@ def _empty_cell_fraction(pos, box, ncell):
 
 def _occupied_cell_density(pos, natoms, box, ncell):
     """Host-side launch planning: mean atoms per non-empty cell of the cell
-    grid, for the replica where it is largest."""
-    nu, off = 1.0, 0
+    grid, per replica."""
+    nu, off = [], 0
     for r, n in enumerate(np.asarray(natoms).ravel()):
         n = int(n)
         L, nc = box[r], ncell[r].astype(np.int64)
         c = np.minimum((np.mod(pos[off:off + n], L) * nc / L).astype(np.int64), nc - 1)
         cnt = np.bincount((c[:, 2] * nc[1] + c[:, 1]) * nc[0] + c[:, 0])
-        nu = max(nu, float(cnt[cnt > 0].mean()))
+        nu.append(max(1.0, float(cnt[cnt > 0].mean())))
         off += n
-    return nu
+    return np.array(nu)
+
+
+def _tile_cells_for(nu, nx, cap, tb, py, pz, max_cells):
+    """Cells per tile along x for mean occupancy nu and nx cells per row: the
+    staged neighbourhood (m + 2)(py + 2)(pz + 2) nu within 92% of the
+    staging capacity and about one home atom per thread, then balanced along
+    the row (the paper grows its subnodes until the work per core stops
+    paying, Sec. 3.3; here the LDS staging bounds the tile)."""
+    m = int(min(0.92 * cap / ((py + 2) * (pz + 2) * nu) - 2, 1.02 * tb / (py * pz * nu)))
+    m = max(1, min(m, max_cells, nx))
+    return -(-nx // -(-nx // m))
 
 
 class MDSystem:
@@ -150,6 +161,7 @@ class MDSystem:
         self.ld = (self.N + 63) // 64 * 64
         self.tile_need = torch.zeros(1, dtype=torch.int32, device=d)
         self.tile_cells, self.n_tiles = 0, 0
+        self.h_tile_m, self.tile_m, self.tile_todo = None, None, None
         self.tile_py, self.tile_pz = (int(tile_rows[0]), int(tile_rows[1]))
         # occupied-tile list (one replica): on by default when most cells start
         # empty (a droplet or slab in vacuum), so empty tiles get no workgroup
@@ -162,21 +174,17 @@ class MDSystem:
         self.tile_active = None
         if self.mode == abi.MD_TILE_FULL:
             if tile_cells is None:
-                # cells per tile: staged neighbourhood 9 (m + 2) nu within 92% of
-                # the staging capacity and about one home atom per thread,
-                # nu = mean atoms per occupied cell of the densest replica (so
-                # vacuum does not dilute it); then balanced along each row
+                # cells per tile from nu = mean atoms per occupied cell (so
+                # vacuum does not dilute it), for each replica on its own: a
+                # batch whose replicas have different cell sizes then gives
+                # each the largest tiles it fits
                 nu = _occupied_cell_density(pos, natoms, box, self.h_ncell)
-                cap = self.lib.md_tile_capacity()
-                tb = self.lib.md_tune_get(abi.MD_TUNE_TILE_THREADS)
-                py, pz = self.tile_py, self.tile_pz
-                m = int(min(0.92 * cap / ((py + 2) * (pz + 2) * nu) - 2,
-                            1.02 * tb / (py * pz * nu)))
-                m = max(1, min(m, self.lib.md_tile_max_cells(), int(self.h_ncell[:, 0].max())))
-                nx = int(self.h_ncell[:, 0].max())
-                m = -(-nx // -(-nx // m))
-                tile_cells = m
-            self._plan_tiles(int(tile_cells))
+                args = (self.lib.md_tile_capacity(), self.lib.md_tune_get(abi.MD_TUNE_TILE_THREADS),
+                        self.tile_py, self.tile_pz, self.lib.md_tile_max_cells())
+                per = np.array([_tile_cells_for(nu[r], int(self.h_ncell[r, 0]), *args)
+                                for r in range(self.R)], dtype=np.int32)
+                tile_cells = per if self.R > 1 and np.any(per != per[0]) else int(per[0])
+            self._plan_tiles(tile_cells)
         if max_nbr is None:
             # ideal-gas estimate of neighbours within rc + skin, with margin
             rho = float(np.max(natoms / np.prod(box, axis=1)))
@@ -318,16 +326,31 @@ class MDSystem:
                            s.pos4.data_ptr() if s.pos4 is not None else None)
 
     def _plan_tiles(self, m):
+        """Tiles of m cells along x: one int for every replica, or an array
+        of one per replica (kept as ``h_tile_m``; ``tile_cells`` is then its
+        largest value)."""
         ncell = np.ascontiguousarray(self.h_ncell.ravel(), dtype=np.int32)
         py, pz = self.tile_py, self.tile_pz
-        n = self.lib.md_tile_plan(self.R, ncell.ctypes.data, m, py, pz, None, None)
+        if np.ndim(m) == 0:
+            hm, mx = None, int(m)
+        else:
+            hm = np.ascontiguousarray(m, dtype=np.int32)
+            mx = int(hm.max())
+        hp = hm.ctypes.data if hm is not None else None
+        n = self.lib.md_tile_plan(self.R, ncell.ctypes.data, mx, hp, py, pz, None, None)
         if n < 1:
             raise abi.MDError("md_tile_plan", n)
         rep = np.zeros(n, np.int32)
         off = np.zeros(self.R + 1, np.int32)
-        check("md_tile_plan", min(0, self.lib.md_tile_plan(self.R, ncell.ctypes.data, m, py, pz,
-                                                           rep.ctypes.data, off.ctypes.data)))
-        self.tile_cells, self.n_tiles = m, n
+        check("md_tile_plan", min(0, self.lib.md_tile_plan(self.R, ncell.ctypes.data, mx, hp,
+                                                           py, pz, rep.ctypes.data,
+                                                           off.ctypes.data)))
+        self.tile_cells, self.n_tiles = mx, n
+        self.h_tile_m = hm
+        self.tile_m = torch.as_tensor(hm).to(self.dev) if hm is not None else None
+        # a batch's list build lists the tiles of the replicas it rebuilds here
+        self.tile_todo = (torch.zeros(n + 1, dtype=torch.int32, device=self.dev)
+                          if self.R > 1 else None)
         self.tile_rep = torch.as_tensor(rep).to(self.dev)
         self.tile_off = torch.as_tensor(off).to(self.dev)
         # per-tile staging records (capacity + 128 words each), written by the build
@@ -354,7 +377,9 @@ class MDSystem:
             self.tile_off.data_ptr() if tiled else None,
             self.tile_need.data_ptr(), self.cell_start.data_ptr() if tiled else None,
             self.tile_src_cap if tiled else 0, 0, self.tile_src.data_ptr() if tiled else None,
-            self.tile_active.data_ptr() if tiled and self.tile_active is not None else None)
+            self.tile_active.data_ptr() if tiled and self.tile_active is not None else None,
+            self.tile_m.data_ptr() if tiled and self.tile_m is not None else None,
+            self.tile_todo.data_ptr() if tiled and self.tile_todo is not None else None)
 
     @property
     def stream(self):
@@ -479,7 +504,11 @@ class MDSystem:
         if st & abi.MD_F_TILE_OVERFLOW:
             if self.tile_cells <= 1:
                 raise RuntimeError("a single-cell tile exceeds the LDS staging capacity")
-            self._plan_tiles(max(1, self.tile_cells - max(1, self.tile_cells // 4)))
+            if self.h_tile_m is not None:
+                m = self.h_tile_m
+                self._plan_tiles(np.maximum(1, m - np.maximum(1, m // 4)))
+            else:
+                self._plan_tiles(max(1, self.tile_cells - max(1, self.tile_cells // 4)))
             self._set_nlist()
         if st & abi.MD_F_NBR_OVERFLOW:
             self._alloc_list(int(int(self.need.item()) * 1.2) + 8)
@@ -737,10 +766,11 @@ class MDSystem:
         rep = self.tile_rep.cpu().numpy()
         toff = self.tile_off.cpu().numpy()
         coff = np.concatenate([[0], np.cumsum(np.prod(self.h_ncell, axis=1))])
-        m, py, pz = self.tile_cells, self.tile_py, self.tile_pz
+        py, pz = self.tile_py, self.tile_pz
         tables = []
         for t in range(self.n_tiles):
             r = rep[t]
+            m = int(self.h_tile_m[r]) if self.h_tile_m is not None else self.tile_cells
             nx, ny, nz = self.h_ncell[r]
             tx, ty = -(-nx // m), -(-ny // py)
             local = t - toff[r]

@@ -47,17 +47,37 @@ def test_header_constants_match_binding():
 def test_tile_plan():
     lib = abi.load()
     ncell = np.array([38, 38, 38, 2, 3, 5], np.int32)
-    n = lib.md_tile_plan(2, ncell.ctypes.data, 10, 1, 1, None, None)
+    n = lib.md_tile_plan(2, ncell.ctypes.data, 10, None, 1, 1, None, None)
     assert n == 38 * 38 * 4 + 3 * 5 * 1
     rep = np.zeros(n, np.int32)
     off = np.zeros(3, np.int32)
-    assert lib.md_tile_plan(2, ncell.ctypes.data, 10, 1, 1, rep.ctypes.data, off.ctypes.data) == n
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 10, None, 1, 1, rep.ctypes.data,
+                            off.ctypes.data) == n
     assert list(off) == [0, 5776, 5791] and rep[5775] == 0 and rep[5776] == 1
     # 2 x 2 rows per tile: 19 x 19 row blocks; odd counts leave a short block
-    assert lib.md_tile_plan(2, ncell.ctypes.data, 3, 2, 2, None, None) == 13 * 19 * 19 + 1 * 2 * 3
-    assert lib.md_tile_plan(2, ncell.ctypes.data, 0, 1, 1, None, None) == abi.MD_EINVAL
-    assert lib.md_tile_plan(2, ncell.ctypes.data, 65, 1, 1, None, None) == abi.MD_EINVAL
-    assert lib.md_tile_plan(2, ncell.ctypes.data, 4, 3, 1, None, None) == abi.MD_EINVAL
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 3, None, 2, 2, None, None) == \
+        13 * 19 * 19 + 1 * 2 * 3
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 0, None, 1, 1, None, None) == abi.MD_EINVAL
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 65, None, 1, 1, None, None) == abi.MD_EINVAL
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 4, None, 3, 1, None, None) == abi.MD_EINVAL
+
+
+def test_tile_plan_per_replica_widths():
+    # replica r cut into tiles of m_r cells along x; each m_r in 1 .. tile_cells
+    lib = abi.load()
+    ncell = np.array([38, 38, 38, 2, 3, 5], np.int32)
+    m = np.array([3, 1], np.int32)
+    n = lib.md_tile_plan(2, ncell.ctypes.data, 3, m.ctypes.data, 2, 2, None, None)
+    assert n == 13 * 19 * 19 + 2 * 2 * 3
+    rep = np.zeros(n, np.int32)
+    off = np.zeros(3, np.int32)
+    assert lib.md_tile_plan(2, ncell.ctypes.data, 3, m.ctypes.data, 2, 2, rep.ctypes.data,
+                            off.ctypes.data) == n
+    assert list(off) == [0, 13 * 19 * 19, n] and np.all(rep[off[1]:] == 1)
+    for bad in ([4, 1], [3, 0]):
+        mb = np.array(bad, np.int32)
+        assert lib.md_tile_plan(2, ncell.ctypes.data, 3, mb.ctypes.data, 2, 2, None,
+                                None) == abi.MD_EINVAL
 
 
 def test_tuning_knobs():

@@ -591,6 +591,39 @@ def test_tile_batch_equals_each_replica_alone():
         assert float(t.ke[0]) == float(s.ke[r])
 
 
+def test_tile_widths_per_replica_equal_each_replica_alone():
+    # replicas of 500 .. 20000 atoms have cells of different occupancy, so the
+    # automatic tiling gives each its own width (cells per tile along x); a
+    # replica's trajectory and forces in the batch equal, bit for bit, those
+    # of the replica alone tiled with that width, and its forces match the
+    # oracle
+    cfg = _one_type(md_inputs.replica_batch(nrep=6, nmin=500, nmax=20000, seed=23))
+    say("case: per-replica tile widths")
+    s = _system(cfg, mode="tile", tile_rows=(2, 2))
+    assert s.h_tile_m is not None and len(set(s.h_tile_m.tolist())) > 1
+    assert s.tile_cells == int(s.h_tile_m.max())
+    s.setup()
+    s.run(12)
+    s.ensure_list()
+    pos_b, f_b = s.positions(), s.forces_np()
+    off = cfg.atom_off()
+    for r in range(6):
+        a, b = off[r], off[r + 1]
+        one = md_inputs.Config("one", cfg.pos[a:b], cfg.vel[a:b], cfg.box[r:r + 1],
+                               cfg.natoms[r:r + 1], cfg.types[a:b], 1, cfg.eps, cfg.sig,
+                               cfg.mass, RC, SKIN, cfg.dt, 1.0, 12)
+        t = _system(one, mode="tile", tile_cells=int(s.h_tile_m[r]), tile_rows=(2, 2))
+        t.setup()
+        t.run(12)
+        t.ensure_list()
+        assert np.array_equal(t.positions(), pos_b[a:b]), r
+        assert np.array_equal(t.forces_np(), f_b[a:b]), r
+    r = int(np.argmax(s.h_tile_m))
+    a, b = off[r], off[r + 1]
+    ref, _, _ = oracle.lj_forces(pos_b[a:b], cfg.box[r], RC, shift=1)
+    assert _err(f_b[a:b], ref) < 1e-5
+
+
 @pytest.mark.parametrize("prec,ntypes", [("fp64", 2), ("mixed", 2), ("fp64", 3),
                                           ("mixed", 4)])
 def test_typed_tile_lists_on_the_replica_batch(prec, ntypes):
