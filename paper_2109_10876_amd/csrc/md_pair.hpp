@@ -243,6 +243,7 @@ __device__ __forceinline__ void lj_pair_ab(const PairAB<PREC> &k, double dx, dou
 //   dus1 = 48 s12 - 24 s6 - shift part  (dU/dsig = (eps/sig) dus1)
 struct VjpConst {
     double eps, eos, s2, ush1, dus1;   // eps, eps/sig, sig^2, shift parts at rc
+    float epsf, eosf, s2f, ush1f, dus1f;   // the same rounded to FP32
 };
 
 __device__ __forceinline__ VjpConst vjp_const(double eps, double sig, double rc, int shift)
@@ -254,6 +255,11 @@ __device__ __forceinline__ VjpConst vjp_const(double eps, double sig, double rc,
     const double c2 = c.s2 / (rc * rc), c6 = c2 * c2 * c2, c12 = c6 * c6;
     c.ush1 = shift ? 4.0 * (c12 - c6) : 0.0;
     c.dus1 = shift ? (48.0 * c12 - 24.0 * c6) : 0.0;
+    c.epsf = static_cast<float>(c.eps);
+    c.eosf = static_cast<float>(c.eos);
+    c.s2f = static_cast<float>(c.s2);
+    c.ush1f = static_cast<float>(c.ush1);
+    c.dus1f = static_cast<float>(c.dus1);
     return c;
 }
 
@@ -282,6 +288,24 @@ __device__ __forceinline__ VjpTerms vjp_terms(const VjpConst &c, double r2)
         v.dfs1 = static_cast<double>((576.0f * s12 - 144.0f * s6) * invf);
         v.dus1 = static_cast<double>(48.0f * s12 - 24.0f * s6) - c.dus1;
     }
+    return v;
+}
+
+// The adjoint pair terms in FP32 throughout (FP32-mixed tile adjoint).
+struct VjpTermsF {
+    float fr1, dfr1, u1, dfs1, dus1;
+};
+
+__device__ __forceinline__ VjpTermsF vjp_terms_f32(const VjpConst &c, float r2)
+{
+    VjpTermsF v;
+    const float inv = __builtin_amdgcn_rcpf(r2);
+    const float s2 = c.s2f * inv, s6 = s2 * s2 * s2, s12 = s6 * s6;
+    v.fr1 = 24.0f * s6 * (2.0f * s6 - 1.0f) * inv;
+    v.dfr1 = (-672.0f * s12 + 192.0f * s6) * inv * inv;
+    v.u1 = 4.0f * (s12 - s6) - c.ush1f;
+    v.dfs1 = (576.0f * s12 - 144.0f * s6) * inv;
+    v.dus1 = (48.0f * s12 - 24.0f * s6) - c.dus1f;
     return v;
 }
 

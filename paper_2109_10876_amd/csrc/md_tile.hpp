@@ -351,12 +351,20 @@ __device__ int stage_tile(const TileSpec &s, const int32_t *__restrict__ cs,
 // table loads are in flight (returning false abandons the staging: -1).
 // Source indices are clamped below n_atoms, so a table that no build has
 // written gathers garbage but stays in bounds.  lsrc (optional, LDS, cap
-// entries) receives every staged slot's source atom.
-template <int TB, bool P4, class Stage, class Mid>
+// entries) receives every staged slot's source atom.  extra gathers more
+// per-slot data with the positions: extra.load(k, src) is called with the
+// position loads of a thread's k-th slot, extra.store(k, sl) with its LDS
+// stores (slots below the staged count only).
+struct NoSlotExtra {
+    __device__ void load(int, uint32_t) {}
+    __device__ void store(int, int) {}
+};
+
+template <int TB, bool P4, class Stage, class Mid, class Extra = NoSlotExtra>
 __device__ int stage_from_table(const TileSpec &s, const uint32_t *__restrict__ tab, int n_atoms,
                                 const double *__restrict__ x, const double *__restrict__ y,
                                 const double *__restrict__ z, const double *__restrict__ pos4,
-                                Stage &st, int cap, int *lsrc, Mid &&mid)
+                                Stage &st, int cap, int *lsrc, Mid &&mid, Extra &&extra = Extra{})
 {
     constexpr int kPer = (Stage::kCap + TB - 1) / TB;
     const int tid = threadIdx.x;
@@ -394,6 +402,7 @@ __device__ int stage_from_table(const TileSpec &s, const uint32_t *__restrict__ 
             py[k] = load_at(y, src);
             pz[k] = load_at(z, src);
         }
+        extra.load(k, src);
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -402,6 +411,7 @@ __device__ int stage_from_table(const TileSpec &s, const uint32_t *__restrict__ 
             st.x[sl] = apply_shift(px[k], code[k], kTabShiftX, s.L[0]);
             st.y[sl] = apply_shift(py[k], code[k], kTabShiftY, s.L[1]);
             st.z[sl] = apply_shift(pz[k], code[k], kTabShiftZ, s.L[2]);
+            extra.store(k, sl);
         }
     }
     __syncthreads();

@@ -9,9 +9,10 @@
 // supplies -w), and the parameter terms, seen from both atoms, are halved.
 //
 // One workgroup per tile: the neighbourhood is staged in LDS from the tile's
-// staging record (md_tile.hpp) together with every slot's source atom, so
-// the neighbour's G is gathered through it.  Per-tile (eps, sigma) sums go to
-// the record's adjoint words; a fixed-order finalize adds them over tiles.
+// staging record (md_tile.hpp), with, per slot, the neighbour's G (FP32-mixed)
+// or its source atom (FP64, G then gathered from memory through it).
+// Per-tile (eps, sigma) sums go to the record's adjoint words; a fixed-order
+// finalize adds them over tiles.
 #include "md_pair.hpp"
 #include "md_tile.hpp"
 
@@ -24,18 +25,57 @@ static_assert(2 * kAdjSlots * 2 <= 64, "adjoint sums fit the record's spare word
 
 typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
 
+// LDS of one tile.  FP32-mixed: the upstream G of every staged slot sits
+// beside its position, rounded to FP32 (a pair term, like the pair
+// arithmetic), gathered once per slot with the positions instead of once per
+// pair from memory.  FP64: G stays in memory, gathered per pair through the
+// slot's source atom.
+template <int CAP, bool STAGED_G>
+struct VjpLds;
+template <int CAP>
+struct VjpLds<CAP, true> {
+    TilePlanes<CAP> st;
+    float gx[CAP + 1], gy[CAP + 1], gz[CAP + 1];
+};
+template <int CAP>
+struct VjpLds<CAP, false> {
+    TilePlanes<CAP> st;
+    int lsrc[CAP];
+};
+
+// Stages G[src] of a thread's k-th slot (with its position) as FP32.
+template <int KPER>
+struct GradGather {
+    const double *gx, *gy, *gz;
+    float *lx, *ly, *lz;
+    double vx[KPER], vy[KPER], vz[KPER];
+    __device__ void load(int k, uint32_t src)
+    {
+        vx[k] = load_at(gx, src);
+        vy[k] = load_at(gy, src);
+        vz[k] = load_at(gz, src);
+    }
+    __device__ void store(int k, int sl)
+    {
+        lx[sl] = static_cast<float>(vx[k]);
+        ly[sl] = static_cast<float>(vy[k]);
+        lz[sl] = static_cast<float>(vz[k]);
+    }
+};
+
 template <class SH, int PREC, int NT>
 __global__ __launch_bounds__(SH::TB) void k_tile_vjp(TileArgs a)
 {
     constexpr int TB = SH::TB, CAP = SH::CAP, kW = TB / kWave, NS = NT * NT;
-    __shared__ TileStage<CAP, SH::MAXC> st;
-    __shared__ int lsrc[CAP];
+    constexpr bool SG = PREC == MD_FP32_MIXED;
+    __shared__ VjpLds<CAP, SG> L;
     __shared__ VjpConst tab[kAdjSlots];
     __shared__ double red[2 * NS][kW];
+    auto &st = L.st;
     const int t = xcd_chunked(blockIdx.x, gridDim.x, kTileXcdChunk);
     const TileSpec s = tile_spec(t, a.tile_rep, a.tile_off, a.ncell, a.cell_off, a.box, a.g, a.tile_m);
     uint32_t *rec = a.tile_src + size_t(t) * tab_stride(CAP);
-    double *adj = reinterpret_cast<double *>(rec + kTabAdj<TileStage<CAP, SH::MAXC>>);
+    double *adj = reinterpret_cast<double *>(rec + kTabAdj<TilePlanes<CAP>>);
     if (threadIdx.x < NS) {
         // the LJ table is [NT * NT] here (tile lists carry at most kTT types)
         const int ti = threadIdx.x / NT, tj = threadIdx.x % NT;
@@ -43,12 +83,21 @@ __global__ __launch_bounds__(SH::TB) void k_tile_vjp(TileArgs a)
     }
     HomeRows hr;
     int nh = 0;
-    const int total = stage_from_table<TB, false>(
-        s, rec, a.n_atoms, a.x, a.y, a.z, nullptr, st, CAP, lsrc, [&] {
-            hr = home_rows(s, a.cell_start);
-            nh = hr.total;
-            return nh > 0;
-        });
+    auto mid = [&] {
+        hr = home_rows(s, a.cell_start);
+        nh = hr.total;
+        return nh > 0;
+    };
+    int total;
+    if constexpr (SG) {
+        if (threadIdx.x == 0) L.gx[CAP] = L.gy[CAP] = L.gz[CAP] = 0.0f;
+        total = stage_from_table<TB, false>(
+            s, rec, a.n_atoms, a.x, a.y, a.z, nullptr, st, CAP, nullptr, mid,
+            GradGather<(CAP + TB - 1) / TB>{a.gfx, a.gfy, a.gfz, L.gx, L.gy, L.gz, {}, {}, {}});
+    } else {
+        total = stage_from_table<TB, false>(s, rec, a.n_atoms, a.x, a.y, a.z, nullptr, st, CAP,
+                                            L.lsrc, mid);
+    }
     // per-thread (type_i, type_j) sums of the parameter terms
     double ae[NS], as[NS];
 #pragma unroll
@@ -67,6 +116,12 @@ __global__ __launch_bounds__(SH::TB) void k_tile_vjp(TileArgs a)
             const int n = min(a.count[i], a.max_nbr);
             const u32x4v *lb = reinterpret_cast<const u32x4v *>(a.idx) + i;
             double ax = 0.0, ay = 0.0, az = 0.0;
+            // FP32-mixed: this atom's parameter terms by the neighbour's type
+            double pe_t[NT], ps_t[NT];
+#pragma unroll
+            for (int q = 0; q < NT; ++q) pe_t[q] = ps_t[q] = 0.0;
+            const float Gxf = static_cast<float>(Gx), Gyf = static_cast<float>(Gy),
+                        Gzf = static_cast<float>(Gz), gErf = static_cast<float>(gEr);
             for (int k = 0; k < n; k += kEntryBlock) {
                 const u32x4v blk = lb[size_t(min(k / kEntryBlock, bmax)) * a.ld];
 #pragma unroll
@@ -79,26 +134,58 @@ __global__ __launch_bounds__(SH::TB) void k_tile_vjp(TileArgs a)
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     if (!(r2 < rc2)) continue;   // pad entries never pass
                     const int tj = NT > 1 ? int(e & 7u) : 0;
-                    const int j = lsrc[max(min(slot, total - 1), 0)];
                     const VjpConst c = tab[ti * kTT + tj];
-                    const VjpTerms v = vjp_terms<PREC>(c, r2);
-                    const double fr = c.eps * v.fr1, dfr = c.eps * v.dfr1;
-                    const double ux = Gx - a.gfx[j], uy = Gy - a.gfy[j], uz = Gz - a.gfz[j];
-                    const double du = dx * ux + dy * uy + dz * uz;
-                    const double t1 = dfr * du - gEr * fr;
-                    ax += fr * ux + t1 * dx;
-                    ay += fr * uy + t1 * dy;
-                    az += fr * uz + t1 * dz;
-                    const double pe = du * v.fr1 + gEr * v.u1;
-                    const double ps = c.eos * (du * v.dfs1 + gEr * v.dus1);
-                    const int sl = ti * NT + tj;
+                    if constexpr (SG) {
+                        // the pair term in FP32, its sums in FP64
+                        const VjpTermsF v = vjp_terms_f32(c, static_cast<float>(r2));
+                        const float dxf = static_cast<float>(dx), dyf = static_cast<float>(dy),
+                                    dzf = static_cast<float>(dz);
+                        const float fr = c.epsf * v.fr1, dfr = c.epsf * v.dfr1;
+                        const float ux = Gxf - L.gx[slot], uy = Gyf - L.gy[slot],
+                                    uz = Gzf - L.gz[slot];
+                        const float du = fmaf(dxf, ux, fmaf(dyf, uy, dzf * uz));
+                        const float t1 = fmaf(dfr, du, -gErf * fr);
+                        ax += static_cast<double>(fmaf(fr, ux, t1 * dxf));
+                        ay += static_cast<double>(fmaf(fr, uy, t1 * dyf));
+                        az += static_cast<double>(fmaf(fr, uz, t1 * dzf));
+                        const float pe = fmaf(du, v.fr1, gErf * v.u1);
+                        const float ps = c.eosf * fmaf(du, v.dfs1, gErf * v.dus1);
 #pragma unroll
-                    for (int p = 0; p < NS; ++p)
-                        if (p == sl) {
-                            ae[p] += pe;
-                            as[p] += ps;
-                        }
+                        for (int q = 0; q < NT; ++q)
+                            if (q == tj) {
+                                pe_t[q] += static_cast<double>(pe);
+                                ps_t[q] += static_cast<double>(ps);
+                            }
+                    } else {
+                        const int j = L.lsrc[max(min(slot, total - 1), 0)];
+                        const double gjx = a.gfx[j], gjy = a.gfy[j], gjz = a.gfz[j];
+                        const VjpTerms v = vjp_terms<PREC>(c, r2);
+                        const double fr = c.eps * v.fr1, dfr = c.eps * v.dfr1;
+                        const double ux = Gx - gjx, uy = Gy - gjy, uz = Gz - gjz;
+                        const double du = dx * ux + dy * uy + dz * uz;
+                        const double t1 = dfr * du - gEr * fr;
+                        ax += fr * ux + t1 * dx;
+                        ay += fr * uy + t1 * dy;
+                        az += fr * uz + t1 * dz;
+                        const double pe = du * v.fr1 + gEr * v.u1;
+                        const double ps = c.eos * (du * v.dfs1 + gEr * v.dus1);
+                        const int sl = ti * NT + tj;
+#pragma unroll
+                        for (int p = 0; p < NS; ++p)
+                            if (p == sl) {
+                                ae[p] += pe;
+                                as[p] += ps;
+                            }
+                    }
                 }
+            }
+            if constexpr (SG) {
+#pragma unroll
+                for (int p = 0; p < NS; ++p)
+                    if (p / NT == ti) {
+                        ae[p] += pe_t[p % NT];
+                        as[p] += ps_t[p % NT];
+                    }
             }
             a.gx[i] = ax;
             a.gx[a.n_atoms + i] = ay;
@@ -135,7 +222,7 @@ __global__ __launch_bounds__(kUnit) void k_tile_vjp_finalize(const uint32_t *til
                                                              int nt, double *geps, double *gsig)
 {
     __shared__ double red[kWavesPerUnit];
-    constexpr int kAdj = kTabAdj<TileStage<SH::CAP, SH::MAXC>>;
+    constexpr int kAdj = kTabAdj<TilePlanes<SH::CAP>>;
     const int kind = blockIdx.x / (nt * nt), ab = blockIdx.x % (nt * nt);
     const int ta = ab / nt, tb = ab % nt;
     double sum = 0.0;

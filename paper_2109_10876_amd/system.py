@@ -505,8 +505,16 @@ class MDSystem:
             if self.tile_cells <= 1:
                 raise RuntimeError("a single-cell tile exceeds the LDS staging capacity")
             if self.h_tile_m is not None:
-                m = self.h_tile_m
-                self._plan_tiles(np.maximum(1, m - np.maximum(1, m // 4)))
+                # only the replicas with a tile past the capacity get smaller
+                # tiles: the build leaves every staged count in its record
+                stride = self.tile_src_cap + 128
+                tot = self.tile_src.view(self.n_tiles, stride)[:, self.tile_src_cap].cpu().numpy()
+                bad = np.unique(self.tile_rep.cpu().numpy()[tot > self.tile_src_cap])
+                m = self.h_tile_m.copy()
+                if bad.size == 0 or np.all(m[bad] <= 1):
+                    raise RuntimeError("a single-cell tile exceeds the LDS staging capacity")
+                m[bad] = np.maximum(1, m[bad] - np.maximum(1, m[bad] // 4))
+                self._plan_tiles(m)
             else:
                 self._plan_tiles(max(1, self.tile_cells - max(1, self.tile_cells // 4)))
             self._set_nlist()

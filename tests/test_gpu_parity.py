@@ -624,6 +624,33 @@ def test_tile_widths_per_replica_equal_each_replica_alone():
     assert _err(f_b[a:b], ref) < 1e-5
 
 
+def test_tile_overflow_shrinks_only_the_overflowing_replicas_tiles():
+    # one replica planned with a whole cell row per tile overflows the staging
+    # capacity: the recovery shrinks that replica's tiles only, and the lists
+    # then give the oracle's forces
+    cfg = _one_type(md_inputs.replica_batch(nrep=4, nmin=3000, nmax=12000, seed=24))
+    say("case: per-replica tile overflow")
+    s = _system(cfg, mode="tile", tile_rows=(2, 2))
+    m = (s.h_tile_m.copy() if s.h_tile_m is not None
+         else np.full(s.R, s.tile_cells, dtype=np.int32))
+    r = int(np.argmax(cfg.natoms))
+    big = m.copy()
+    big[r] = int(s.h_ncell[r, 0])
+    assert big[r] > m[r]
+    s._plan_tiles(big)
+    s._set_nlist()
+    s.setup()
+    assert s.ensure_list() == 0
+    assert s.h_tile_m[r] < big[r]
+    assert all(s.h_tile_m[k] == big[k] for k in range(s.R) if k != r)
+    f = s.forces_np()
+    off = cfg.atom_off()
+    for k in (r, (r + 1) % s.R):
+        a, b = off[k], off[k + 1]
+        ref, _, _ = oracle.lj_forces(cfg.pos[a:b], cfg.box[k], RC, shift=1)
+        assert np.abs(f[a:b] - ref).max() < 1e-10
+
+
 @pytest.mark.parametrize("prec,ntypes", [("fp64", 2), ("mixed", 2), ("fp64", 3),
                                           ("mixed", 4)])
 def test_typed_tile_lists_on_the_replica_batch(prec, ntypes):
