@@ -83,16 +83,17 @@ __device__ __forceinline__ TileSpec tile_spec(int t, const int32_t *__restrict__
     return s;
 }
 
-// LDS tables of one staged tile.  Positions of staged slot s sit at
-// x[s], y[s], z[s]; slot CAP is the pad slot (a position far outside any
-// box) that padded list entries name.  The planes are kStride apart, one
-// double more than a multiple of 64, so x, y and z of a slot sit in
-// different LDS banks (with a multiple of 64 all three share a bank, and the
-// step was 1.6% slower mixed, 0.8% FP64).
+// LDS tables of one staged tile, as the list build stages it.  Positions of
+// staged slot s sit at x[s], y[s], z[s]; slot CAP is the pad slot (a position
+// far outside any box) that padded list entries name.  The build reads 64
+// consecutive slots of one plane at a time, so the planes' distance does not
+// matter for banks there: they sit one slot apart (kStride = CAP + 2, 16-byte
+// aligned), which leaves room for the build's per-wave entry buffers at three
+// workgroups per CU.
 template <int CAP, int MAXC>
 struct TileStage {
     static constexpr int kCap = CAP;
-    static constexpr int kStride = CAP + 2;   // pad slot included, planes 16-byte aligned
+    static constexpr int kStride = CAP + 2;
     static constexpr int kRowStage = MAXC + 3;   // cell starts a-1 .. b+2 of one staged row
     double x[kStride], y[kStride], z[kStride];
     int row_slot[kMaxStagedRows + 1];  // first slot of staged row q; [nrows] = total
@@ -108,8 +109,11 @@ struct TileStage {
     int rowc[kChunks];                 // staged row holding slot 64 c (first row if several)
 };
 
-// The position planes of TileStage alone (same layout and pad slot): all
-// that the force kernel keeps in LDS, so that its workgroups use less of it.
+// The position planes alone (same pad slot): all that the force kernel keeps
+// in LDS, so that its workgroups use less of it.  The planes are kStride
+// apart, one double more than a multiple of 64, so x, y and z of a slot sit in
+// different LDS banks for the force loop's random slot reads (with a multiple
+// of 64 all three share a bank, and the step was 1.6% slower mixed, 0.8% FP64).
 template <int CAP>
 struct TilePlanes {
     static constexpr int kCap = CAP;
