@@ -429,22 +429,70 @@ def test_inhomogeneous_full_size_after_graphed_steps(name):
 
 def test_replica_batch_full_size_after_graphed_steps():
     # the 256 uneven two-type replicas (2.62 M atoms) in the benchmark's form:
-    # typed tile lists of 1 x 2 x 2 cells with 2048 slots, FP32-mixed, graphed;
-    # sampled atoms of every replica against the oracle
+    # typed tile lists of 2 x 2 rows with 2048 slots and each replica's own
+    # width along x, FP32-mixed, graphed; sampled atoms of every replica
+    # against the oracle
     print("case: replicas full size", flush=True)
     from paper_2109_10876_amd import _abi as abi
     lib = abi.load()
     lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, 2048)
     try:
         cfg = md_inputs.CONFIGS["replicas"]()
-        s = _system(cfg, mode="tile", prec="mixed", tile_rows=(2, 2), tile_cells=1)
+        s = _system(cfg, mode="tile", prec="mixed", tile_rows=(2, 2))
         assert s.nlist.tile_types == 2 and not s.sparse_tiles
+        assert s.h_tile_m is not None and len(set(s.h_tile_m.tolist())) > 1
         s.setup()
         s.run_graphed(30, k=10)
         assert s.ensure_list() == 0
         err = _sampled_force_error(s, cfg, 2, seed=6, types=cfg.types)
         print(f"  sampled e_F = {err:.3e}", flush=True)
         assert err < 1e-5
+    finally:
+        lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, 0)
+
+
+def test_replica_batch_adjoint_full_size_in_the_benchmarked_form():
+    # the force-matching adjoint of the 256-replica batch as the benchmark
+    # times it: typed tile lists with per-replica widths, FP32-mixed (the
+    # upstream G staged in FP32, the pair term in FP32, FP64 sums), after
+    # graphed steps; dL/dx of eight replicas of every tile width against the
+    # oracle's adjoint of each replica alone, within the mixed bound 1e-5
+    import torch
+    print("case: replicas adjoint full size", flush=True)
+    from paper_2109_10876_amd import _abi as abi
+    lib = abi.load()
+    lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, 2048)
+    try:
+        cfg = md_inputs.CONFIGS["replicas"]()
+        s = _system(cfg, mode="tile", prec="mixed", tile_rows=(2, 2))
+        s.setup()
+        s.run_graphed(20, k=10)
+        assert s.ensure_list() == 0
+        rng = np.random.default_rng(8)
+        G = rng.normal(size=(cfg.n, 3))
+        gE = rng.normal(size=s.R)
+        ids = s.id.cpu().numpy()
+        d = s.dev
+        gfx, gfy, gfz = (torch.tensor(G[ids, k].copy(), device=d) for k in range(3))
+        gx = torch.zeros(3 * cfg.n, dtype=torch.float64, device=d)
+        ge = torch.zeros(cfg.ntypes ** 2, dtype=torch.float64, device=d)
+        gs = torch.zeros(cfg.ntypes ** 2, dtype=torch.float64, device=d)
+        s.vjp(gfx, gfy, gfz, torch.tensor(gE, device=d), gx, ge, gs)
+        torch.cuda.synchronize()
+        got = np.empty((cfg.n, 3))
+        got[ids] = gx.cpu().numpy().reshape(3, cfg.n).T
+        pos = s.positions()
+        off = cfg.atom_off()
+        picks = []
+        for m in sorted(set(s.h_tile_m.tolist())):
+            picks += [int(r) for r in np.nonzero(s.h_tile_m == m)[0][:3]]
+        for r in picks[:8]:
+            a, b = off[r], off[r + 1]
+            ref, _, _ = oracle.lj_vjp(pos[a:b], cfg.box[r], cfg.rc, G[a:b], float(gE[r]),
+                                      cfg.eps, cfg.sig, cfg.types[a:b], shift=cfg.shift)
+            err = np.linalg.norm(got[a:b] - ref) / np.linalg.norm(ref)
+            print(f"  replica {r} width {s.h_tile_m[r]} N={b - a}: e = {err:.3e}", flush=True)
+            assert err < 1e-5
     finally:
         lib.md_tune_set(abi.MD_TUNE_TILE_SLOTS, 0)
 
