@@ -440,14 +440,17 @@ int md_vv_step(const md_batch *b, md_atoms *atoms, int32_t phase, double dt,
                uint32_t *gate, double *ke, const md_thermostat *thermo, void *ws,
                size_t ws_bytes, uint32_t *status, void *stream);
 
-/* Vector-Jacobian product of md_lj_forces: given G = dL/dF (planes gfx,
- * gfy, gfz, [N] each, same atom order) and gE ([R], dL/dE_r, optional),
- * writes gx = dL/dx (planes [3N]) and, optionally, geps and gsig ([ntypes^2],
- * derivatives with respect to the shared parameter of each unordered type
- * pair; both mirrored entries hold it, summed over all replicas).  Pair terms
- * are recomputed from the list, nothing is stored by md_lj_forces.  Requires
- * an MD_FULL list or an MD_TILE_FULL list (at most MD_TILE_MAX_TYPES types,
- * typed as for md_lj_forces; MD_EUNSUPPORTED for MD_HALF). */
+/* Vector-Jacobian product of md_lj_forces (the derivatives of Eq. lj's pair
+ * force and energy, Sec. 2.1.1, with respect to positions, eps and sigma):
+ * given G = dL/dF (planes gfx, gfy, gfz, [N] each, same atom order) and gE
+ * ([R], dL/dE_r, optional), writes gx = dL/dx (planes [3N]) and, optionally,
+ * geps and gsig ([ntypes^2], derivatives with respect to the shared parameter
+ * of each unordered type pair; both mirrored entries hold it, summed over all
+ * replicas).  Pair terms are recomputed from the list, nothing is stored by
+ * md_lj_forces.  Requires an MD_FULL list or an MD_TILE_FULL list (at most
+ * MD_TILE_MAX_TYPES types, typed as for md_lj_forces; MD_EUNSUPPORTED for
+ * MD_HALF).  prec = MD_FP32_MIXED on a tile list evaluates each pair term in
+ * single precision (G rounded to it) and sums in double. */
 int md_lj_forces_vjp(const md_batch *b, const md_atoms *atoms, const md_nlist *nl,
                      const md_lj *p, int32_t prec, const double *gfx,
                      const double *gfy, const double *gfz, const double *gE,

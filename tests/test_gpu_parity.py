@@ -379,18 +379,35 @@ def test_vjp_matches_oracle(prec, mode):
     np.testing.assert_allclose(gsig.cpu().numpy().reshape(2, 2), gs_ref, rtol=tol * 10)
 
 
+@pytest.fixture(scope="module")
+def lj1m_jittered():
+    # the 1,048,576-atom workload jittered so forces are non-zero, with the
+    # oracle's forces, energy and virial of all atoms (its cell-list path)
+    cfg = md_inputs.lj_fluid(64, temperature=1.0, seed=2, jitter_amp=0.1)
+    ref = oracle.lj_forces(cfg.pos, cfg.box[0], RC, shift=1)
+    return cfg, ref
+
+
 @pytest.mark.parametrize("prec,mode,rows", [("mixed", "full", None), ("fp64", "full", None),
                                             ("mixed", "tile", (1, 1)), ("fp64", "tile", (2, 2)),
                                             ("mixed", "tile", (2, 1))])
-def test_full_size_sampled_forces(prec, mode, rows):
-    # the 1,048,576-atom workload, in the configuration the benchmark times,
-    # jittered so forces are non-zero; 48 sampled atoms by O(N) oracle loops
-    cfg = md_inputs.lj_fluid(64, temperature=1.0, seed=2, jitter_amp=0.1)
-    say(f"case: 1M sampled {prec} {mode} {rows}")
+def test_full_size_sampled_forces(lj1m_jittered, prec, mode, rows):
+    # the 1,048,576-atom workload, in the configuration the benchmark times:
+    # every atom's force, the energy and the virial against the oracle's cell
+    # path, and 48 sampled atoms against its O(N) single-atom loop
+    cfg, (f_ref, e_ref, w_ref) = lj1m_jittered
+    say(f"case: 1M {prec} {mode} {rows}")
     s = _system(cfg, mode=mode, prec=prec, **({"tile_rows": rows} if rows else {}))
     s.setup()
     s.ensure_list()
     f = s.forces_np()
+    err_all = _err(f, f_ref)
+    e_rel = abs(float(s.energy[0]) - e_ref) / abs(e_ref)
+    w_rel = abs(float(s.virial[0]) - w_ref) / abs(w_ref)
+    say(f"  all atoms e_F = {err_all:.3e}, E rel {e_rel:.3e}, W rel {w_rel:.3e}")
+    assert err_all < (1e-12 if prec == "fp64" else 1e-5)
+    assert e_rel < (1e-11 if prec == "fp64" else 1e-6)
+    assert w_rel < (1e-11 if prec == "fp64" else 1e-6)
     planes = tuple(np.ascontiguousarray(cfg.pos[:, k]) for k in range(3))
     rng = np.random.default_rng(1)
     sample = rng.choice(cfg.n, 48, replace=False)
