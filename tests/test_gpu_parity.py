@@ -18,6 +18,8 @@ Tolerances (derivations):
     whose total energy nearly cancels the bound is |dE| <= 1e-5 N_r.
   Integer work (pair sets, counts, rebuild schedule): exact.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -141,6 +143,39 @@ def test_verlet_list_is_the_skin_pair_set(c1_snapshot, mode, rows):
     exp = set(map(tuple, ref))
     # the set is unique up to pairs within rounding of the Verlet radius
     diff = got.symmetric_difference(exp)
+    for i, j in diff:
+        d = cfg.pos[i] - cfg.pos[j]
+        d -= cfg.box[0] * np.rint(d / cfg.box[0])
+        assert abs(np.dot(d, d) - rl * rl) < 1e-10
+    assert len(diff) <= 2
+
+
+@pytest.mark.parametrize("mode,rows", [("full", None), ("half", None), ("tile", (1, 1)),
+                                       ("tile", (2, 2))])
+def test_pairs_at_the_verlet_radius_are_decided_in_fp64(mode, rows):
+    # simple cubic lattice of spacing rl/2: every axis pair sits at rl, moved by
+    # a jitter of 1e-7 to either side, far inside a single-precision distance
+    # test's rounding and far outside double precision's
+    rl = RC + SKIN
+    k = 20
+    g = (np.arange(k) + 0.25) * (rl / 2)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pos = md_inputs.jitter(pos, 1e-7, seed=11)
+    cfg = md_inputs.lj_fluid(10)
+    n = pos.shape[0]
+    cfg = dataclasses.replace(cfg, pos=pos, vel=np.zeros_like(pos),
+                              box=np.full((1, 3), k * rl / 2), natoms=np.array([n]),
+                              types=np.zeros(n, np.int32))
+    say(f"case: pairs at the Verlet radius {mode} {rows}")
+    s = _system(cfg, mode=mode, **({"tile_rows": rows} if rows else {}))
+    s.setup()
+    pairs, _ = s.list_pairs()
+    exp = set(map(tuple, oracle.pairs_cells(cfg.pos, cfg.box[0], rl)))
+    # 26 lattice neighbours inside rl per atom, and about half of the six on it
+    assert 26 * n // 2 + n < len(exp) < 29 * n // 2 + n // 2
+    # as for the skin pair set, only pairs within rounding of rl may differ
+    # (a tile list keeps pairs up to rl^2 (1 + 2^-40))
+    diff = _unordered(pairs).symmetric_difference(exp)
     for i, j in diff:
         d = cfg.pos[i] - cfg.pos[j]
         d -= cfg.box[0] * np.rint(d / cfg.box[0])
