@@ -82,6 +82,36 @@ def test_forces_mixed_within_bound(c1_snapshot, mode):
     assert float(s.virial[0]) == pytest.approx(w, rel=1e-6)
 
 
+@pytest.mark.parametrize("prec,ntypes", [("mixed", 1), ("mixed", 2), ("mixed", 3),
+                                          ("fp64", 1)])
+def test_cutoff_at_rc_is_decided_as_in_double(prec, ntypes):
+    # simple cubic lattice of spacing rc/2: every axis pair sits at rc, moved
+    # by a jitter of 1e-9 to either side.  The single-precision path's
+    # displacements carry rounding of order 1e-8, and a pair put on the wrong
+    # side of rc moves two forces by |F(rc)| (above 0.008 for every type pair
+    # here); decided as in double, the forces match the oracle's to the
+    # single-precision rounding of the pair terms (~1e-4 at most).
+    k = 20
+    g = (np.arange(k) + 0.25) * (RC / 2)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pos = md_inputs.jitter(pos, 1e-9, seed=13)
+    n = pos.shape[0]
+    cfg = dataclasses.replace(md_inputs.lj_fluid(10), pos=pos, vel=np.zeros_like(pos),
+                              box=np.full((1, 3), k * RC / 2), natoms=np.array([n]),
+                              types=np.zeros(n, np.int32))
+    if ntypes > 1:
+        cfg = md_inputs.retyped(cfg, ntypes, seed=31)
+    say(f"case: cutoff at rc {prec} ntypes={ntypes}")
+    s = _system(cfg, mode="tile", prec=prec)
+    s.setup()
+    assert s.ensure_list() == 0
+    f = s.forces_np()
+    ref, _, _ = oracle.lj_forces(cfg.pos, cfg.box[0], RC, cfg.eps, cfg.sig, cfg.types, shift=1)
+    # the axis pairs inside rc leave net forces of order |F(rc)|
+    assert np.abs(ref).max() > 0.008
+    assert np.abs(f - ref).max() < (1e-3 if prec == "mixed" else 1e-10)
+
+
 def test_full_list_forces_are_deterministic_and_match_half(c1_snapshot):
     cfg = c1_snapshot
     say("case: determinism full vs half")
