@@ -270,11 +270,12 @@ __global__ __launch_bounds__(kUnit) void k_copy_next(int32_t n, const double *__
 // Per replica: fixed-order sums of its tiles' partials (energy, virial,
 // kinetic energy) and the largest displacement (the rebuild gate).
 // Fixed-order sums of the per-tile partials in rows [t0, t1) of tp (stride
-// kTilePartials): E, W, KE summed, the displacement maximum taken.  The
-// four reductions share one barrier; wave totals are then summed in wave
+// kTilePartials): E, W, KE summed, the displacement maximum taken; only the
+// columns asked for are read (a step that needs the gate alone reads one).
+// The four reductions share one barrier; wave totals are then summed in wave
 // order, as by block_sum_n.  Thread 0 returns the results.
-__device__ __forceinline__ void tile_sums(int t0, int t1, const double *tp, bool want_ke,
-                                          bool want_gate, double out[4])
+__device__ __forceinline__ void tile_sums(int t0, int t1, const double *tp, bool want_ew,
+                                          bool want_ke, bool want_gate, double out[4])
 {
     constexpr int kW = kFin / kWave;
     __shared__ double red[4][kW];
@@ -282,13 +283,17 @@ __device__ __forceinline__ void tile_sums(int t0, int t1, const double *tp, bool
 #pragma unroll 4
     for (int t = t0 + threadIdx.x; t < t1; t += kFin) {
         const double *q = tp + size_t(t) * kTilePartials;
-        s0 += q[0];
-        s1 += q[1];
+        if (want_ew) {
+            s0 += q[0];
+            s1 += q[1];
+        }
         if (want_ke) s2 += q[2];
         if (want_gate) m = fmax(m, q[3]);
     }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
+    if (want_ew) {
+        s0 = wave_sum(s0);
+        s1 = wave_sum(s1);
+    }
     if (want_ke) s2 = wave_sum(s2);
     if (want_gate) m = wave_max(m);
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
@@ -329,7 +334,8 @@ __global__ __launch_bounds__(kFin) void k_tile_finalize(const int32_t *tile_off,
     const int r = blockIdx.x;
     const int t0 = tile_off ? tile_off[r] : 0, t1 = tile_off ? tile_off[r + 1] : n_rows;
     double v[4];
-    tile_sums(t0, t1, tpart, ke != nullptr, gate != nullptr, v);
+    tile_sums(t0, t1, tpart, energy != nullptr || virial != nullptr, ke != nullptr,
+              gate != nullptr, v);
     if (threadIdx.x == 0) {
         if (energy) energy[r] = v[0];
         if (virial) virial[r] = v[1];
@@ -346,12 +352,13 @@ constexpr int kTileChunkedFrom = 4 * kTileChunk;
 static_assert(kPartials == kTilePartials, "chunk sums use the per-unit partial rows");
 
 __global__ __launch_bounds__(kFin) void k_tile_chunk_sums(int n_tiles, const double *tpart,
-                                                          double *out, bool want_ke,
-                                                          bool want_gate)
+                                                          double *out, bool want_ew,
+                                                          bool want_ke, bool want_gate)
 {
     const int c = blockIdx.x;
     double v[4];
-    tile_sums(c * kTileChunk, min((c + 1) * kTileChunk, n_tiles), tpart, want_ke, want_gate, v);
+    tile_sums(c * kTileChunk, min((c + 1) * kTileChunk, n_tiles), tpart, want_ew, want_ke,
+              want_gate, v);
     if (threadIdx.x == 0)
         for (int q = 0; q < kTilePartials; ++q) out[size_t(c) * kTilePartials + q] = v[q];
 }
@@ -450,7 +457,8 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
     if ((energy || virial || ke || gate) && b->R == 1 && nl->n_tiles >= kTileChunkedFrom &&
         chunk_sums && n_chunks <= chunk_rows) {
         hipLaunchKernelGGL(k_tile_chunk_sums, dim3(n_chunks), dim3(kFin), 0, s, nl->n_tiles,
-                           tpart, chunk_sums, ke != nullptr, gate != nullptr);
+                           tpart, chunk_sums, energy != nullptr || virial != nullptr,
+                           ke != nullptr, gate != nullptr);
         hipLaunchKernelGGL(k_tile_finalize, dim3(1), dim3(kFin), 0, s, nullptr, n_chunks,
                            chunk_sums, energy, virial, ke, gate, fuse ? vvf->lim2 : 0.0,
                            fuse ? vvf->step : nullptr);

@@ -414,15 +414,18 @@ class MDSystem:
             ctypes.byref(self.lj), self.prec, int(accumulate), _ptr(self.energy),
             _ptr(self.virial), _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
 
-    def forces_vv(self):
+    def forces_vv(self, energies=True):
         """Forces at the current positions (plus the thermostat, if any), then
-        velocity-Verlet phase 3, in one call (pair forces on tile lists)."""
+        velocity-Verlet phase 3, in one call (pair forces on tile lists).
+        energies=False leaves energy, virial and ke as they were (the call
+        then sums only the rebuild gate)."""
         two = len(self._pos) == 2
         nxt = self._pos[self._par ^ 1] if two else (None, None, None)
+        e, w, k = (self.energy, self.virial, self.ke) if energies else (None, None, None)
         check("md_lj_forces_vv", self.lib.md_lj_forces_vv(
             ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.nlist),
             ctypes.byref(self.lj), self.prec, self.dt, _ptr(self.inv_mass), self.ntypes,
-            self.skin, _ptr(self.gate), _ptr(self.ke), _ptr(self.energy), _ptr(self.virial),
+            self.skin, _ptr(self.gate), _ptr(k), _ptr(e), _ptr(w),
             _ptr(nxt[0]), _ptr(nxt[1]), _ptr(nxt[2]),
             ctypes.byref(self.thermo) if self.thermo is not None else None,
             _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
@@ -617,8 +620,10 @@ class MDSystem:
     def fused_body(self):
         """The same work in the fused order: the forces of one step with its
         Integrate2 and the next step's Integrate1 (one call), then the gated
-        re-sort and list build of the next step."""
-        self.forces_vv()
+        re-sort and list build of the next step.  A run's energies are those
+        its last step (the tail) computes, so the repeated steps sum only the
+        rebuild gate."""
+        self.forces_vv(energies=False)
         self.sort()
         self.build()
 
