@@ -6,14 +6,15 @@
 // contiguous index range and neighbour gathers in the list build and the
 // force loop hit nearby addresses.
 //
-// Five stream-ordered kernels, each skipping replicas whose gate is 0:
-//   1 bin      wrap, cell index, histogram slot (atomic per cell)
+// Four stream-ordered kernels, each skipping replicas whose gate is 0:
+//   1 bin      wrap, cell index, histogram slot (atomic per cell); the
+//              atom's data copied to scratch at its current index
 //   2 scan     per-replica exclusive scan of cell counts -> cell_start,
 //              clearing the counts for the next call
 //   3 keys     key[cell_start[c] + slot] = id   (cell members, any order)
-//   4 gather   rank inside the cell by id (deterministic order), gather the
-//              atom's wrapped data into scratch at its final index
-//   5 copy     scratch -> atoms, x_build := x (and the packed copy)
+//   4 gather   rank inside the cell by id (deterministic order), the atom's
+//              wrapped data from scratch into atoms at its final index,
+//              x_build := x (and the packed copy)
 #include "md_common.hpp"
 
 namespace md {
@@ -74,10 +75,8 @@ __device__ __forceinline__ int aggregated_slot(int32_t *count, int c, bool activ
         if (const Unit w = unit_of(lb_, (a).unit_rep, (a).unit_off, (a).atom_off); \
             !gated_off((a), w.rep))
 
-__global__ __launch_bounds__(kUnit) void k_bin(BatchArgs a, const double *__restrict__ x,
-                                               const double *__restrict__ y,
-                                               const double *__restrict__ z,
-                                               int32_t *__restrict__ cell_count,
+__global__ __launch_bounds__(kUnit) void k_bin(BatchArgs a, md_atoms in, md_atoms cp,
+                                               int32_t N, int32_t *__restrict__ cell_count,
                                                int32_t *__restrict__ cell_of,
                                                int32_t *__restrict__ slot)
 {
@@ -86,13 +85,26 @@ __global__ __launch_bounds__(kUnit) void k_bin(BatchArgs a, const double *__rest
         const bool active = i < w.end;
         int c = 0;
         if (active) {
+            const double x = in.x[i], y = in.y[i], z = in.z[i];
             const double *L = a.box + 3 * w.rep;
             const int32_t *n = a.ncell + 3 * w.rep;
             int s;
-            const int cx = cell_coord(wrap_coord(x[i], L[0], &s), cells_per_length(n[0], L[0]), n[0]);
-            const int cy = cell_coord(wrap_coord(y[i], L[1], &s), cells_per_length(n[1], L[1]), n[1]);
-            const int cz = cell_coord(wrap_coord(z[i], L[2], &s), cells_per_length(n[2], L[2]), n[2]);
+            const int cx = cell_coord(wrap_coord(x, L[0], &s), cells_per_length(n[0], L[0]), n[0]);
+            const int cy = cell_coord(wrap_coord(y, L[1], &s), cells_per_length(n[1], L[1]), n[1]);
+            const int cz = cell_coord(wrap_coord(z, L[2], &s), cells_per_length(n[2], L[2]), n[2]);
             c = a.cell_off[w.rep] + (cz * n[1] + cy) * n[0] + cx;
+            // the gather reads the atom from here, so it can write atoms in place
+            cp.x[i] = x;
+            cp.y[i] = y;
+            cp.z[i] = z;
+            cp.vx[i] = in.vx[i];
+            cp.vy[i] = in.vy[i];
+            cp.vz[i] = in.vz[i];
+            cp.type[i] = in.type[i];
+            cp.id[i] = in.id[i];
+            cp.img[i] = in.img[i];
+            cp.img[N + i] = in.img[N + i];
+            cp.img[2 * N + i] = in.img[2 * N + i];
         }
         const int sl = aggregated_slot(cell_count, c, active);
         if (active) {
@@ -225,9 +237,16 @@ __global__ __launch_bounds__(kUnit) void k_gather(BatchArgs a, md_atoms in, md_a
         const int dst = s + rank;
         const double *L = a.box + 3 * w.rep;
         int sx, sy, sz;
-        out.x[dst] = wrap_coord(x0, L[0], &sx);
-        out.y[dst] = wrap_coord(y0, L[1], &sy);
-        out.z[dst] = wrap_coord(z0, L[2], &sz);
+        const double xw = wrap_coord(x0, L[0], &sx);
+        const double yw = wrap_coord(y0, L[1], &sy);
+        const double zw = wrap_coord(z0, L[2], &sz);
+        out.x[dst] = xw;
+        out.y[dst] = yw;
+        out.z[dst] = zw;
+        out.xb[dst] = xw;
+        out.yb[dst] = yw;
+        out.zb[dst] = zw;
+        if (out.pos4) reinterpret_cast<double4 *>(out.pos4)[dst] = make_double4(xw, yw, zw, 0.0);
         out.vx[dst] = vx;
         out.vy[dst] = vy;
         out.vz[dst] = vz;
@@ -236,26 +255,7 @@ __global__ __launch_bounds__(kUnit) void k_gather(BatchArgs a, md_atoms in, md_a
         out.img[dst] = ix + sx;
         out.img[N + dst] = iy + sy;
         out.img[2 * N + dst] = iz + sz;
-        if (in.where) in.where[me] = dst;
-    }
-}
-
-__global__ __launch_bounds__(kUnit) void k_copy_back(BatchArgs a, md_atoms s, md_atoms d,
-                                                     int32_t N)
-{
-    MD_FOR_UNITS(a, w) {
-        const int i = w.begin + threadIdx.x;
-        if (i >= w.end) continue;
-        const double x = s.x[i], y = s.y[i], z = s.z[i];
-        d.x[i] = x; d.y[i] = y; d.z[i] = z;
-        d.xb[i] = x; d.yb[i] = y; d.zb[i] = z;
-        if (d.pos4) reinterpret_cast<double4 *>(d.pos4)[i] = make_double4(x, y, z, 0.0);
-        d.vx[i] = s.vx[i]; d.vy[i] = s.vy[i]; d.vz[i] = s.vz[i];
-        d.type[i] = s.type[i];
-        d.id[i] = s.id[i];
-        d.img[i] = s.img[i];
-        d.img[N + i] = s.img[N + i];
-        d.img[2 * N + i] = s.img[2 * N + i];
+        if (out.where) out.where[me] = dst;
     }
 }
 
@@ -292,10 +292,9 @@ extern "C" int md_cell_sort(const md_batch *b, md_atoms *atoms, md_atoms *scratc
     int32_t *slot = ws_at<int32_t>(ws, l.slot);
     int32_t *key = ws_at<int32_t>(ws, l.key);
     const dim3 grid(gated_grid(b->n_units, gate != nullptr)), block(kUnit);
-    hipLaunchKernelGGL(k_bin, grid, block, 0, s, a, atoms->x, atoms->y, atoms->z, cnt, cell_of, slot);
+    hipLaunchKernelGGL(k_bin, grid, block, 0, s, a, *atoms, *scratch, b->N, cnt, cell_of, slot);
     hipLaunchKernelGGL(k_scan, dim3(b->R), dim3(kScan), 0, s, a, cnt, cell_start);
     hipLaunchKernelGGL(k_keys, grid, block, 0, s, a, atoms->id, cell_of, slot, cell_start, key);
-    hipLaunchKernelGGL(k_gather, grid, block, 0, s, a, *atoms, *scratch, b->N, cell_of, cell_start, key);
-    hipLaunchKernelGGL(k_copy_back, grid, block, 0, s, a, *scratch, *atoms, b->N);
+    hipLaunchKernelGGL(k_gather, grid, block, 0, s, a, *scratch, *atoms, b->N, cell_of, cell_start, key);
     return launch_status();
 }
