@@ -383,6 +383,32 @@ def test_small_boxes_with_two_cells_per_dimension():
             assert float(s.virial[r]) == pytest.approx(w, rel=1e-12)
 
 
+@pytest.mark.parametrize("mode,prec", [("full", "fp64"), ("half", "fp64"), ("tile", "fp64"),
+                                       ("full", "mixed"), ("tile", "mixed")])
+def test_one_pair_and_an_isolated_atom(mode, prec):
+    # the smallest system the method has: two atoms 1.2 apart (one pair inside
+    # rc, across a cell boundary) and one atom beyond rc + skin of both, in a
+    # box of two cells per side; the isolated atom's list is empty and its
+    # force exactly zero, and the pair's forces are equal and opposite
+    pos = np.array([[3.4, 1.0, 1.0], [4.6, 1.0, 1.0], [5.5, 5.5, 5.5]])
+    cfg = dataclasses.replace(md_inputs.lj_fluid(10), pos=pos, vel=np.zeros_like(pos),
+                              box=np.full((1, 3), 8.0), natoms=np.array([3]),
+                              types=np.zeros(3, np.int32))
+    say(f"case: one pair and an isolated atom {mode} {prec}")
+    s = _system(cfg, mode=mode, prec=prec)
+    s.setup()
+    assert s.ensure_list() == 0
+    pairs, _ = s.list_pairs()
+    assert _unordered(pairs) == {(0, 1)}
+    f = s.forces_np()
+    ref, e, w = oracle.lj_forces(cfg.pos, cfg.box[0], RC, shift=1)
+    assert np.all(f[2] == 0.0)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert np.abs(f - ref).max() <= tol * np.abs(ref).max()
+    assert float(s.energy[0]) == pytest.approx(e, rel=tol)
+    assert float(s.virial[0]) == pytest.approx(w, rel=tol)
+
+
 def test_batch_equals_each_replica_alone():
     cfg = md_inputs.replica_batch(nrep=6, nmin=500, nmax=5000, seed=12)
     say("case: batch vs single")
