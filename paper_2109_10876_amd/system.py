@@ -408,11 +408,12 @@ class MDSystem:
             self.rc, self.skin, ctypes.byref(self.nlist), _ptr(self.need),
             _ptr(self.gate) if gated else None, _ptr(self.status), self.stream))
 
-    def forces(self, accumulate=False):
+    def forces(self, accumulate=False, energies=True, atoms=None):
+        e, w = (self.energy, self.virial) if energies else (None, None)
         check("md_lj_forces", self.lib.md_lj_forces(
-            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.nlist),
-            ctypes.byref(self.lj), self.prec, int(accumulate), _ptr(self.energy),
-            _ptr(self.virial), _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
+            ctypes.byref(self.batch), ctypes.byref(atoms or self.atoms), ctypes.byref(self.nlist),
+            ctypes.byref(self.lj), self.prec, int(accumulate), _ptr(e), _ptr(w),
+            _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
 
     def forces_vv(self, energies=True):
         """Forces at the current positions (plus the thermostat, if any), then
@@ -432,11 +433,12 @@ class MDSystem:
         if two:
             self._par ^= 1   # the next positions are now the current ones
 
-    def vv(self, phase):
+    def vv(self, phase, energies=True):
         thermo = self.thermo if self.vv_thermo and phase >= 2 else None
         check("md_vv_step", self.lib.md_vv_step(
             ctypes.byref(self.batch), ctypes.byref(self.atoms), int(phase), self.dt,
-            _ptr(self.inv_mass), self.ntypes, self.skin, _ptr(self.gate), _ptr(self.ke),
+            _ptr(self.inv_mass), self.ntypes, self.skin, _ptr(self.gate),
+            _ptr(self.ke if energies else None),
             ctypes.byref(thermo) if thermo is not None else None,
             _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
 
@@ -447,25 +449,28 @@ class MDSystem:
             _ptr(gx), _ptr(geps), _ptr(gsig), _ptr(self.ws), self.ws_bytes,
             _ptr(self.status), self.stream))
 
-    def fene(self):
+    def fene(self, energies=True, atoms=None):
+        e, w = (self.energy_bond, self.virial_bond) if energies else (None, None)
         check("md_fene_forces", self.lib.md_fene_forces(
-            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self._bonds_k),
-            self.fene_K, self.fene_R0, _ptr(self.energy_bond), _ptr(self.virial_bond),
+            ctypes.byref(self.batch), ctypes.byref(atoms or self.atoms), ctypes.byref(self._bonds_k),
+            self.fene_K, self.fene_R0, _ptr(e), _ptr(w),
             _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
 
-    def bonded(self):
+    def bonded(self, energies=True, atoms=None):
         """FENE bonds and angle triples in one call (tables keyed by index)."""
+        ebs = (self.energy_bond, self.virial_bond, self.energy_angle, self.virial_angle) \
+            if energies else (None, None, None, None)
         check("md_bonded_forces", self.lib.md_bonded_forces(
-            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self._bonds_k),
+            ctypes.byref(self.batch), ctypes.byref(atoms or self.atoms), ctypes.byref(self._bonds_k),
             self.fene_K, self.fene_R0, ctypes.byref(self._angles_k), self.angle_K,
-            _ptr(self.energy_bond), _ptr(self.virial_bond), _ptr(self.energy_angle),
-            _ptr(self.virial_angle), _ptr(self.ws), self.ws_bytes, _ptr(self.status),
+            *(_ptr(q) for q in ebs), _ptr(self.ws), self.ws_bytes, _ptr(self.status),
             self.stream))
 
-    def angle(self):
+    def angle(self, energies=True, atoms=None):
+        e, w = (self.energy_angle, self.virial_angle) if energies else (None, None)
         check("md_angle_forces", self.lib.md_angle_forces(
-            ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self._angles_k),
-            self.angle_K, _ptr(self.energy_angle), _ptr(self.virial_angle),
+            ctypes.byref(self.batch), ctypes.byref(atoms or self.atoms), ctypes.byref(self._angles_k),
+            self.angle_K, _ptr(e), _ptr(w),
             _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
 
     def langevin(self):
@@ -475,20 +480,35 @@ class MDSystem:
             gamma, temp, self.dt, seed, _ptr(self.noise_step), _ptr(self.status),
             self.stream))
 
-    def all_forces(self, initial=False):
+    def all_forces(self, initial=False, energies=True):
         """Pair forces, then (if configured) bond and angle forces and the
         thermostat (which the next half kick adds instead, except for the
-        initial forces, when the split calls are used)."""
-        self.forces()
-        if self.bonds is not None and self.angles is not None and self.bonded_by_index:
-            self.bonded()
-        else:
-            if self.bonds is not None:
-                self.fene()
-            if self.angles is not None:
-                self.angle()
+        initial forces, when the split calls are used).  energies=False
+        leaves the energy and virial outputs as they were."""
+        self._conservative(energies)
         if self.langevin_cfg is not None and (initial or not self.vv_thermo):
             self.langevin()
+
+    def _conservative(self, energies, atoms=None):
+        # pair, bond and angle terms into the given atoms' force planes
+        self.forces(energies=energies, atoms=atoms)
+        if self.bonds is not None and self.angles is not None and self.bonded_by_index:
+            self.bonded(energies=energies, atoms=atoms)
+        else:
+            if self.bonds is not None:
+                self.fene(energies=energies, atoms=atoms)
+            if self.angles is not None:
+                self.angle(energies=energies, atoms=atoms)
+
+    def energies_now(self):
+        """Energy and virial outputs of the current positions, evaluated into
+        the re-sort's scratch planes (free between steps), so that the forces,
+        velocities and the thermostat's noise counter stay as they are."""
+        a = self.atoms
+        tmp = abi.MdAtoms(a.x, a.y, a.z, a.vx, a.vy, a.vz, self.s_vx.data_ptr(),
+                          self.s_vy.data_ptr(), self.s_vz.data_ptr(), a.xb, a.yb, a.zb,
+                          a.type, a.id, a.img, a.where, a.pos4)
+        self._conservative(True, atoms=tmp)
 
     # ------------------------------------------------------------ the step
     def setup(self):
@@ -610,12 +630,12 @@ class MDSystem:
             raise RuntimeError(f"device status flags 0x{st:x}")
         return bool(st & self._OVERFLOW)
 
-    def step_body(self, first):
+    def step_body(self, first, energies=True):
         """One velocity-Verlet step except its final half kick."""
-        self.vv(1 if first else 3)
+        self.vv(1 if first else 3, energies=energies)
         self.sort()
         self.build()
-        self.all_forces()
+        self.all_forces(energies=energies)
 
     def fused_body(self):
         """The same work in the fused order: the forces of one step with its
@@ -628,11 +648,13 @@ class MDSystem:
         self.build()
 
     def _body(self):
+        # a run's energies are those its tail computes, so the repeated steps
+        # sum only the rebuild gate
         self._stepped += 1
         if self.fuse:
             self.fused_body()
         else:
-            self.step_body(first=False)
+            self.step_body(first=False, energies=False)
 
     def _head(self):
         # first step up to its forces (fused: up to its list build)
@@ -642,12 +664,15 @@ class MDSystem:
             self.sort()
             self.build()
         else:
-            self.step_body(first=True)
+            self.step_body(first=True, energies=False)
 
     def _tail(self):
-        # last step's forces (fused) and the final half kick
+        # last step's forces (fused) or its energies (split: the forces are
+        # those of the last step), and the final half kick
         if self.fuse:
             self.all_forces()
+        else:
+            self.energies_now()
         self.vv(2)
 
     def run(self, steps, check_every=50, max_recoveries=8):
