@@ -618,3 +618,37 @@ def test_melt_mixed_trajectory_short_horizon(rings):
     assert np.abs(s.positions() - ref["pos"]).max() < 1e-6
     assert np.abs(s.velocities() - ref["vel"]).max() < 1e-5
     assert float(s.ke[0]) == pytest.approx(ref["ekin"][-1], rel=1e-6)
+    # the potential energy the run leaves (evaluated by its tail)
+    e_pot = float(s.energy[0]) + float(s.energy_bond[0]) + \
+        (float(s.energy_angle[0]) if rings else 0.0)
+    assert e_pot == pytest.approx(ref["epot"][-1], rel=1e-5)
+
+
+def test_run_energies_are_those_of_the_final_state():
+    # a run's repeated steps sum no energies; its tail evaluates them at the
+    # final positions without touching the forces or the noise counter: the
+    # potential and kinetic energy after 30 graphed FP64 steps equal the
+    # oracle's, and the forces and counter equal those of step-by-step calls
+    cfg = _rings((8, 8, 8), 23, jit=0.02)
+    print("case: run energies of the final state", flush=True)
+    a = _system(cfg, langevin=(0.5, 1.0, 57, 0), mode="full")
+    a.setup()
+    a.run_graphed(30, k=8)
+    assert a.ensure_list() == 0
+    ref = oracle.md_run_ext(cfg.pos, cfg.vel, cfg.box[0], cfg.rc, cfg.skin, cfg.dt, 30,
+                            bonds=cfg.bonds, angles=cfg.angles, gamma=0.5, temperature=1.0,
+                            seed=57, step0=0)
+    assert ref["broken"] == 0
+    assert np.abs(a.positions() - ref["pos"]).max() < 1e-9
+    e_pot = float(a.energy[0]) + float(a.energy_bond[0]) + float(a.energy_angle[0])
+    assert e_pot == pytest.approx(ref["epot"][-1], rel=1e-10)
+    assert float(a.ke[0]) == pytest.approx(ref["ekin"][-1], rel=1e-10)
+    b = _system(cfg, langevin=(0.5, 1.0, 57, 0), mode="full")
+    b.setup()
+    for t in range(30):
+        b.step_body(first=(t == 0))
+    b.vv(2)
+    assert np.array_equal(a.forces_np(), b.forces_np())
+    assert int(a.noise_step[0].item()) == int(b.noise_step[0].item())
+    assert float(a.energy[0]) == float(b.energy[0])
+    assert float(a.energy_bond[0]) == float(b.energy_bond[0])
