@@ -400,8 +400,9 @@ int md_lj_forces_noalloc(const md_batch *b, const md_atoms *atoms, const md_nlis
  * Integrate2 and the next step's Integrate1 directly): on return fx, fy, fz
  * hold the forces at the positions on entry, velocities and positions are
  * advanced, gate[r] and ke[r] (optional) are set as by md_vv_step phase 3,
- * energy/virial as by md_lj_forces.  Pair forces of one atom type over
- * MD_TILE_FULL lists (MD_EUNSUPPORTED otherwise), optionally with the
+ * energy/virial as by md_lj_forces.  Pair forces over MD_TILE_FULL lists
+ * (MD_EUNSUPPORTED otherwise; with several atom types, up to
+ * MD_TILE_MAX_TYPES, over a typed list as md_lj_forces needs), optionally with the
  * Langevin thermostat: with thermo set, each atom's force also receives the
  * md_langevin force (velocity on entry, noise counter *thermo->step, which
  * is then advanced by one) before the integrator uses it, as md_lj_forces,

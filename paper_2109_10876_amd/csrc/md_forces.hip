@@ -346,7 +346,9 @@ extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlis
         return MD_EINVAL;
     if (nl->mode != MD_TILE_FULL) return MD_EUNSUPPORTED;
     if (nl->max_nbr < 1 || nl->ld < b->N || nl->ld % 64 != 0) return MD_EINVAL;
-    if (p->ntypes != 1 || !(p->rc > 0.0)) return p->ntypes > 1 ? MD_EUNSUPPORTED : MD_EINVAL;
+    if (p->ntypes < 1 || !(p->rc > 0.0)) return MD_EINVAL;
+    if (p->ntypes > MD_TILE_MAX_TYPES) return MD_EUNSUPPORTED;
+    if (p->ntypes > 1 && !atoms->type) return MD_EINVAL;
     if (ntypes < 1 || ntypes > MD_MAX_TYPES || (ntypes > 1 && !atoms->type)) return MD_EINVAL;
     if (prec != MD_FP64 && prec != MD_FP32_MIXED) return MD_EINVAL;
     if (!(skin >= 0.0) || !(dt > 0.0)) return MD_EINVAL;
@@ -355,7 +357,10 @@ extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlis
         return MD_EINVAL;
     const WsLayout l = ws_layout(b);
     if (ws_bytes < l.total) return MD_ENOWS;
-    if (!tile_list_ok(b, nl) || !nl->cell_start || nl->tile_types > 1) return MD_EINVAL;
+    // a typed list for several types, and only then
+    if (!tile_list_ok(b, nl) || !nl->cell_start ||
+        (p->ntypes > 1 ? nl->tile_types != p->ntypes : nl->tile_types > 1))
+        return MD_EINVAL;
     // next positions: the caller's buffers (all three, not overlapping the
     // current ones, and no packed copy to keep), or workspace copied back
     const bool given = x_next || y_next || z_next;

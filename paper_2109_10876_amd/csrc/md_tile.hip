@@ -429,12 +429,25 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
         if (p4) hipLaunchKernelGGL((k_tile_lj<SH, P, U, true, T, F>), grid, blk, 0, s, a);  \
         else hipLaunchKernelGGL((k_tile_lj<SH, P, U, false, T, F>), grid, blk, 0, s, a);    \
     } while (0)
-        if (fuse && vvf->step) {
-            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 0, 2);
-            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, 2);
-        } else if (fuse) {
-            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 0, 1);
-            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, 1);
+        if (fuse) {
+            // the integrator (FUSE 1), with the thermostat first (FUSE 2)
+            const int ty = !typed ? 0 : (p->ntypes == 2 ? 2 : 4);
+#define MD_TILE_FUSED(F)                                                                  \
+    do {                                                                                  \
+        if (ty == 0) {                                                                    \
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 0, F);                        \
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, F);                                  \
+        } else if (ty == 2) {                                                             \
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 2, F);                        \
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 2, F);                                  \
+        } else {                                                                          \
+            if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 4, F);                        \
+            else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 4, F);                                  \
+        }                                                                                 \
+    } while (0)
+            if (vvf->step) MD_TILE_FUSED(2);
+            else MD_TILE_FUSED(1);
+#undef MD_TILE_FUSED
         } else if (typed && p->ntypes == 2) {
             if (prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 2, 0);
             else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 2, 0);

@@ -282,11 +282,11 @@ class MDSystem:
             self.langevin_cfg = (float(gamma), float(temp), int(seed))
             self.mass_t = f64(mass)
             self.noise_step = torch.tensor([int(step0)], dtype=torch.int64, device=d)
-        # pair forces of one type on tile lists, with or without the
+        # pair forces on tile lists (typed for several types), with or without the
         # thermostat: the force call also advances the step
         # (md_lj_forces_vv); bonds or angles need the split calls
         self.fuse = bool(fuse) and self.mode == abi.MD_TILE_FULL and self.bonds is None \
-            and self.angles is None and self.ntypes == 1
+            and self.angles is None and self.ntypes <= abi.MD_TILE_MAX_TYPES
         self.thermo = None
         if self.langevin_cfg is not None:
             gamma, temp, seed = self.langevin_cfg
