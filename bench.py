@@ -209,7 +209,7 @@ def time_sections(s, step_ms, pair_ms, nsteps=200, nrep=10):
     s._head()
     for _ in range(nsteps):
         s._body()
-        rebuilds += int(s.gate.max().item() > 0)
+        rebuilds += int(s.step_gate.max().item() > 0)
     s._tail()
     if s.overflowed():
         s.restore(cp)   # the count stands; the state goes back to a valid list

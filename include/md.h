@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define MD_ABI_VERSION 10
+#define MD_ABI_VERSION 11
 
 /* ------------------------------------------------------------ return codes */
 #define MD_OK            0
@@ -415,10 +415,18 @@ int md_lj_forces_noalloc(const md_batch *b, const md_atoms *atoms, const md_nlis
  * three given ([N] device each, not overlapping atoms->x, y, z; atoms->pos4
  * must be NULL) they are written there and atoms->x, y, z stay as they were,
  * so a caller that alternates two position buffers skips the copy.  Other
- * combinations return MD_EINVAL. */
+ * combinations return MD_EINVAL.  gate_clear (optional, [R] device, not
+ * overlapping gate, not with thermo): the call then zeroes gate_clear and sets
+ * gate[r] to 1 if an atom of replica r moved more than skin/2, leaving it as
+ * it is otherwise (with one atom type from the force kernel itself, so that
+ * no finaliser runs when ke, energy and virial are NULL; with several, from
+ * the finaliser); a caller that passes two words alternately, each the
+ * gate of one call and the gate_clear of the next, gets the gate of
+ * md_vv_step phase 3 on every call once both start at zero. */
 int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlist *nl, const md_lj *p,
                     int32_t prec, double dt, const double *inv_mass, int32_t ntypes,
-                    double skin, uint32_t *gate, double *ke, double *energy, double *virial,
+                    double skin, uint32_t *gate, uint32_t *gate_clear, double *ke,
+                    double *energy, double *virial,
                     double *x_next, double *y_next, double *z_next,
                     const md_thermostat *thermo, void *ws, size_t ws_bytes,
                     uint32_t *status, void *stream);

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmd.so")
 
 # Constants mirrored from md.h.
-MD_ABI_VERSION = 10
+MD_ABI_VERSION = 11
 MD_OK = 0
 MD_EINVAL = -1
 MD_EBOX = -2
@@ -175,7 +175,7 @@ def load():
                                P(MdThermostat), _vp, ctypes.c_size_t, _vp, _vp]
     lib.md_lj_forces_vv.restype = ctypes.c_int
     lib.md_lj_forces_vv.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32, _dbl,
-                                    _vp, _i32, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    _vp, _i32, _dbl, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                     P(MdThermostat), _vp, ctypes.c_size_t, _vp, _vp]
     lib.md_lj_forces_vjp.restype = ctypes.c_int
     lib.md_lj_forces_vjp.argtypes = [P(MdBatch), P(MdAtoms), P(MdNlist), P(MdLj), _i32,

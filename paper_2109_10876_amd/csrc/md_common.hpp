@@ -266,6 +266,10 @@ struct VVFuse {
     double *xn, *yn, *zn;
     double *ke;
     uint32_t *gate;
+    // non-null: gate is set to 1 by the workgroups whose atoms moved more
+    // than skin/2 (left as it is otherwise) and gate_clear is zeroed, instead
+    // of a finaliser writing gate
+    uint32_t *gate_clear;
     bool copy_back;   // xn/yn/zn are workspace: copy them into atoms->x/y/z
     // Langevin thermostat (step == nullptr: none)
     const int32_t *id;

@@ -331,7 +331,8 @@ extern "C" int md_lj_forces(const md_batch *b, const md_atoms *atoms, const md_n
 
 extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlist *nl,
                                const md_lj *p, int32_t prec, double dt, const double *inv_mass,
-                               int32_t ntypes, double skin, uint32_t *gate, double *ke,
+                               int32_t ntypes, double skin, uint32_t *gate,
+                               uint32_t *gate_clear, double *ke,
                                double *energy, double *virial, double *x_next, double *y_next,
                                double *z_next, const md_thermostat *thermo, void *ws,
                                size_t ws_bytes, uint32_t *status, void *stream)
@@ -355,6 +356,10 @@ extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlis
     if (thermo && (!thermo->step || !thermo->mass || !atoms->id || !(thermo->gamma >= 0.0) ||
                    !(thermo->temperature >= 0.0)))
         return MD_EINVAL;
+    // alternating gate words: not with the thermostat (its counter is
+    // advanced by the finaliser), and not overlapping
+    if (gate_clear && (thermo || (gate_clear < gate + b->R && gate < gate_clear + b->R)))
+        return MD_EINVAL;
     const WsLayout l = ws_layout(b);
     if (ws_bytes < l.total) return MD_ENOWS;
     // a typed list for several types, and only then
@@ -376,7 +381,7 @@ extern "C" int md_lj_forces_vv(const md_batch *b, md_atoms *atoms, const md_nlis
     const VVFuse f{atoms->vx, atoms->vy, atoms->vz, atoms->xb, atoms->yb, atoms->zb, inv_mass,
                    ntypes, 0.5 * dt, dt, 0.25 * skin * skin,
                    given ? x_next : xw, given ? y_next : xw + b->N,
-                   given ? z_next : xw + 2 * size_t(b->N), ke, gate, !given,
+                   given ? z_next : xw + 2 * size_t(b->N), ke, gate, gate_clear, !given,
                    thermo ? atoms->id : nullptr, thermo ? thermo->mass : nullptr,
                    thermo ? thermo->gamma : 0.0,
                    thermo ? 2.0 * thermo->temperature / dt : 0.0,

@@ -93,6 +93,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
         });
     if (total < 0) {
         if (threadIdx.x < kTilePartials) a.tpart[size_t(row) * kTilePartials + threadIdx.x] = 0.0;
+        if (FUSE == 1 && !TY && a.vv.gate_clear && threadIdx.x == 0) a.vv.gate_clear[s.rep] = 0u;
         return;
     }
     double e_acc = 0.0, w_acc = 0.0, ke_acc = 0.0, d2_max = 0.0;
@@ -248,6 +249,15 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
         tp[1] = ws;
         tp[2] = FUSE ? ks : 0.0;
         tp[3] = FUSE ? dm : 0.0;
+        // alternating gate words (one atom type): the skin test of the tile's
+        // replica, and its other word cleared (this kernel never reads it),
+        // by every workgroup on its way out, without a finaliser (done before
+        // the staging loads, the clear cost the pair loop registers; the
+        // typed kernels leave both to the finaliser for the same reason)
+        if (FUSE == 1 && !TY && a.vv.gate_clear) {
+            a.vv.gate_clear[s.rep] = 0u;
+            if (dm > a.vv.lim2) atomicOr(a.vv.gate + s.rep, 1u);
+        }
     }
 }
 
@@ -325,8 +335,8 @@ __device__ __forceinline__ void tile_sums(int t0, int t1, const double *tp, bool
 __global__ __launch_bounds__(kFin) void k_tile_finalize(const int32_t *tile_off, int n_rows,
                                                         const double *tpart, double *energy,
                                                         double *virial, double *ke,
-                                                        uint32_t *gate, double lim2,
-                                                        uint64_t *step)
+                                                        uint32_t *gate, uint32_t *gate_zero,
+                                                        double lim2, uint64_t *step)
 {
     // the thermostat's noise counter advances once per call, after every
     // tile has read it
@@ -341,6 +351,7 @@ __global__ __launch_bounds__(kFin) void k_tile_finalize(const int32_t *tile_off,
         if (virial) virial[r] = v[1];
         if (ke) ke[r] = v[2];
         if (gate) gate[r] = v[3] > lim2 ? 1u : 0u;
+        if (gate_zero) gate_zero[r] = 0u;
     }
 }
 
@@ -465,7 +476,11 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
     });
     timing_end(timed, s);
     double *ke = fuse ? vvf->ke : nullptr;
-    uint32_t *gate = fuse ? vvf->gate : nullptr;
+    // alternating gate words are set and cleared by the one-type force
+    // kernel itself, for typed lists by the finaliser
+    const bool gate_in_kernel = fuse && vvf->gate_clear && !typed;
+    uint32_t *gate = fuse && !gate_in_kernel ? vvf->gate : nullptr;
+    uint32_t *gate_zero = fuse && !gate_in_kernel ? vvf->gate_clear : nullptr;
     const int n_chunks = (nl->n_tiles + kTileChunk - 1) / kTileChunk;
     if ((energy || virial || ke || gate) && b->R == 1 && nl->n_tiles >= kTileChunkedFrom &&
         chunk_sums && n_chunks <= chunk_rows) {
@@ -473,11 +488,11 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
                            tpart, chunk_sums, energy != nullptr || virial != nullptr,
                            ke != nullptr, gate != nullptr);
         hipLaunchKernelGGL(k_tile_finalize, dim3(1), dim3(kFin), 0, s, nullptr, n_chunks,
-                           chunk_sums, energy, virial, ke, gate, fuse ? vvf->lim2 : 0.0,
-                           fuse ? vvf->step : nullptr);
+                           chunk_sums, energy, virial, ke, gate, gate_zero,
+                           fuse ? vvf->lim2 : 0.0, fuse ? vvf->step : nullptr);
     } else if (energy || virial || ke || gate) {
         hipLaunchKernelGGL(k_tile_finalize, dim3(b->R), dim3(kFin), 0, s, nl->tile_off, 0, tpart,
-                           energy, virial, ke, gate, fuse ? vvf->lim2 : 0.0,
+                           energy, virial, ke, gate, gate_zero, fuse ? vvf->lim2 : 0.0,
                            fuse ? vvf->step : nullptr);
     }
     if (fuse && vvf->copy_back)

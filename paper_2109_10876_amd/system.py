@@ -194,6 +194,12 @@ class MDSystem:
         self.ws_bytes = int(self.lib.md_workspace_bytes(ctypes.byref(self.batch)))
         self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=d)
         self.gate = torch.ones(self.R, dtype=torch.int32, device=d)
+        # the repeated fused NVE steps' gate: two words per replica, used
+        # alternately with the two position buffers (md_lj_forces_vv's
+        # gate_clear); _gate_cur is the gate the current step's re-sort and
+        # list build read
+        self.gates = torch.zeros(2, self.R, dtype=torch.int32, device=d)
+        self._gate_cur = self.gate
         self.status = torch.zeros(1, dtype=torch.int32, device=d)
         self.need = torch.zeros(1, dtype=torch.int32, device=d)
         self.energy = torch.zeros(self.R, dtype=torch.float64, device=d)
@@ -390,7 +396,7 @@ class MDSystem:
         check("md_cell_sort", self.lib.md_cell_sort(
             ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.scratch),
             _ptr(self.cell_start), _ptr(self.ws), self.ws_bytes,
-            _ptr(self.gate) if gated else None, _ptr(self.status), self.stream))
+            _ptr(self._gate_cur) if gated else None, _ptr(self.status), self.stream))
         if self.bonded_by_index and (self.bonds is not None or self.angles is not None):
             check("md_bonded_reindex", self.lib.md_bonded_reindex(
                 ctypes.byref(self.batch), ctypes.byref(self.atoms),
@@ -400,13 +406,13 @@ class MDSystem:
                 ctypes.byref(self.angles) if self.angles is not None else None,
                 _ptr(getattr(self, "angle_count_ix", None)),
                 _ptr(getattr(self, "angle_tri_ix", None)),
-                _ptr(self.gate) if gated else None, self.stream))
+                _ptr(self._gate_cur) if gated else None, self.stream))
 
     def build(self, gated=True):
         check("md_verlet_build", self.lib.md_verlet_build(
             ctypes.byref(self.batch), ctypes.byref(self.atoms), _ptr(self.cell_start),
             self.rc, self.skin, ctypes.byref(self.nlist), _ptr(self.need),
-            _ptr(self.gate) if gated else None, _ptr(self.status), self.stream))
+            _ptr(self._gate_cur) if gated else None, _ptr(self.status), self.stream))
 
     def forces(self, accumulate=False, energies=True, atoms=None):
         e, w = (self.energy, self.virial) if energies else (None, None)
@@ -423,10 +429,15 @@ class MDSystem:
         two = len(self._pos) == 2
         nxt = self._pos[self._par ^ 1] if two else (None, None, None)
         e, w, k = (self.energy, self.virial, self.ke) if energies else (None, None, None)
+        # repeated NVE steps with two position buffers: the gate words alternate
+        # with the buffers, so the force kernel sets the gate itself
+        alt = two and not energies and self.thermo is None
+        g, gc = (self.gates[self._par], self.gates[self._par ^ 1]) if alt else (self.gate, None)
+        self._gate_cur = g
         check("md_lj_forces_vv", self.lib.md_lj_forces_vv(
             ctypes.byref(self.batch), ctypes.byref(self.atoms), ctypes.byref(self.nlist),
             ctypes.byref(self.lj), self.prec, self.dt, _ptr(self.inv_mass), self.ntypes,
-            self.skin, _ptr(self.gate), _ptr(k), _ptr(e), _ptr(w),
+            self.skin, _ptr(g), _ptr(gc), _ptr(k), _ptr(e), _ptr(w),
             _ptr(nxt[0]), _ptr(nxt[1]), _ptr(nxt[2]),
             ctypes.byref(self.thermo) if self.thermo is not None else None,
             _ptr(self.ws), self.ws_bytes, _ptr(self.status), self.stream))
@@ -435,6 +446,8 @@ class MDSystem:
 
     def vv(self, phase, energies=True):
         thermo = self.thermo if self.vv_thermo and phase >= 2 else None
+        if phase != 2:
+            self._gate_cur = self.gate
         check("md_vv_step", self.lib.md_vv_step(
             ctypes.byref(self.batch), ctypes.byref(self.atoms), int(phase), self.dt,
             _ptr(self.inv_mass), self.ntypes, self.skin, _ptr(self.gate),
@@ -612,6 +625,7 @@ class MDSystem:
             self._regrow(st)
         else:
             self.status.zero_()
+        self.gates.zero_()
         self.sort(gated=False)
         self.build(gated=False)
         self._stepped = 0
@@ -621,6 +635,12 @@ class MDSystem:
             t.copy_(torch.from_numpy(np.ascontiguousarray(f_new[:, k])))
         torch.cuda.synchronize(self.dev)
         return st
+
+    @property
+    def step_gate(self):
+        """The rebuild gate ([R] device) that the latest step's re-sort and
+        list build read."""
+        return self._gate_cur
 
     def overflowed(self):
         """Synchronise; True if a list overflow flag is set (other flags raise)."""

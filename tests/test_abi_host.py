@@ -314,10 +314,10 @@ def test_fused_step_next_position_buffers_are_checked():
     packed = abi.MdAtoms(X, Y, Z, *([8] * 13), 8)
     far = 16 << 20
 
-    def call(a, xn, yn, zn, thermo=None):
-        return lib.md_lj_forces_vv(P(ok), P(a), P(nl), P(lj1), 0, 0.005, 8, 1, 0.3, 8, None,
-                                   None, None, xn, yn, zn, P(thermo) if thermo else None, 8,
-                                   1 << 30, None, None)
+    def call(a, xn, yn, zn, thermo=None, gate_clear=None):
+        return lib.md_lj_forces_vv(P(ok), P(a), P(nl), P(lj1), 0, 0.005, 8, 1, 0.3, 8,
+                                   gate_clear, None, None, None, xn, yn, zn,
+                                   P(thermo) if thermo else None, 8, 1 << 30, None, None)
 
     assert call(atoms, far, None, None) == abi.MD_EINVAL             # not all three
     assert call(atoms, X + 8 * 500, far, far + (1 << 20)) == abi.MD_EINVAL   # overlaps x
@@ -329,6 +329,10 @@ def test_fused_step_next_position_buffers_are_checked():
                abi.MdThermostat(-0.5, 1.0, 7, 8, 8), abi.MdThermostat(0.5, -1.0, 7, 8, 8),
                abi.MdThermostat(float("nan"), 1.0, 7, 8, 8)):
         assert call(atoms, *nxt, thermo=th) == abi.MD_EINVAL
+    # alternating gate words: not overlapping the gate, not with a thermostat
+    assert call(atoms, *nxt, gate_clear=8) == abi.MD_EINVAL
+    assert call(atoms, *nxt, gate_clear=16 << 10,
+                thermo=abi.MdThermostat(0.5, 1.0, 7, 8, 8)) == abi.MD_EINVAL
 
 
 def test_bonded_tables_check_their_order_without_a_gpu():

@@ -845,6 +845,38 @@ def test_fused_force_step_trajectory_matches_oracle(rows):
     np.testing.assert_allclose(ek, ref["ekin"][1:], rtol=1e-10)
 
 
+def test_repeated_fused_steps_set_the_oracles_rebuild_schedule():
+    # the repeated steps of a run take the skin test from the force kernel
+    # itself, into two gate words used alternately with the position buffers
+    # (md_lj_forces_vv's gate_clear): the gate each step's re-sort and list
+    # build read is the oracle's rebuild schedule, and the trajectory is the
+    # oracle's, eagerly and through graphs
+    cfg = md_inputs.lj_fluid(10, temperature=0.72, seed=1)
+    say("case: rebuild schedule of repeated fused steps")
+    ref = oracle.md_run(cfg.pos, cfg.vel, cfg.box[0], RC, SKIN, cfg.dt, cfg.steps)
+    s = _system(cfg, mode="tile", prec="fp64")
+    assert s.fuse and len(s._pos) == 2
+    s.setup()
+    s._head()
+    flags = [int(s.step_gate[0].item())]
+    for _ in range(1, cfg.steps):
+        s._body()
+        assert s.step_gate.data_ptr() != s.gate.data_ptr()
+        flags.append(int(s.step_gate[0].item()))
+    s._tail()
+    assert s.ensure_list() == 0
+    assert flags == list(ref["rebuild"].astype(int))
+    assert sum(flags) >= 2
+    assert np.abs(s.positions() - ref["pos"]).max() < 1e-9
+    assert float(s.energy[0]) == pytest.approx(ref["epot"][-1], rel=1e-10)
+    assert float(s.ke[0]) == pytest.approx(ref["ekin"][-1], rel=1e-10)
+    g = _system(cfg, mode="tile", prec="fp64")
+    g.setup()
+    g.run_graphed(cfg.steps, k=6)
+    assert g.ensure_list() == 0
+    assert np.array_equal(g.positions(), s.positions())
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_fused_and_split_steps_are_bitwise_equal(prec):
     # same FMA sequence in one kernel or in md_lj_forces + md_vv_step:
