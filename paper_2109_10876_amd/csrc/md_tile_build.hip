@@ -44,12 +44,18 @@ __device__ __forceinline__ void store_block(const TileArgs &a, const uint16_t *w
 __device__ __forceinline__ int flush_blocks(const TileArgs &a, uint16_t *wb, int i, int kb, int cnt,
                                             int lane)
 {
-    const int nfb = (cnt - kb) >> 3, rest = (cnt - kb) & 7;
+    const int nfb = (cnt - kb) >> 3;
     __builtin_amdgcn_wave_barrier();
     if (lane < nfb && kb + 8 * lane < a.max_nbr) store_block(a, wb, i, kb, lane);
-    const uint16_t t = lane < rest ? wb[8 * nfb + lane] : uint16_t(0);
+    // Every lane moves one entry of the partial block (lanes past it copy its
+    // last slot; entries past the count are overwritten before they are
+    // stored).  An unconditional read and write leave no LDS load in flight
+    // past this call, so the hit stores that follow need not wait for the
+    // LDS queue to drain.  The caller keeps cnt - kb <= 272 here, so the
+    // read stays inside the buffer.
+    const uint16_t t = wb[8 * nfb + min(lane, 7)];
     __builtin_amdgcn_wave_barrier();
-    if (lane < rest) wb[lane] = t;
+    wb[lane] = t;
     __builtin_amdgcn_wave_barrier();
     return kb + 8 * nfb;
 }

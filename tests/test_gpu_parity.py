@@ -650,6 +650,65 @@ def test_tile_list_padding_and_neighbour_overflow(c1_snapshot):
     assert float(s.energy[0]) == pytest.approx(e, rel=1e-12)
 
 
+def _crowded_cells():
+    # 8 cells of 2.9 per side (Verlet radius 2.8) holding a jittered lattice of
+    # 8000 atoms (15.6 per cell), except two cells: cell A = (3, 3, 3) holds a
+    # clump of 60 atoms near its low y/z corner and cell B = (3, 2, 2), which
+    # lies in A's first stencil row, a clump of 30 atoms near the corner
+    # they share.  Every clump atom of A is within the Verlet radius of the
+    # other 89, so the list build holds over 80 entries of one home atom after
+    # its first three candidate chunks while the stencil still has over 192
+    # candidates left: the wave's entry buffer is flushed mid-list.
+    L, nc = 23.2, 8
+    w = L / nc
+    rng = np.random.default_rng(23)
+    g = (np.arange(20) + 0.5) * (L / 20)
+    bg = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    bg = bg + rng.uniform(-0.1, 0.1, bg.shape)
+    cell = np.floor(bg / w).astype(int)
+    keep = ~(np.all(cell == (3, 3, 3), 1) | np.all(cell == (3, 2, 2), 1))
+    a = np.stack(np.meshgrid(*(np.arange(4),) * 3, indexing="ij"), -1).reshape(-1, 3)[:60]
+    a = np.array([3 * w + 0.05, 3 * w + 0.05, 3 * w + 0.05]) + 0.3 * a
+    b = np.stack(np.meshgrid(*(np.arange(4),) * 3, indexing="ij"), -1).reshape(-1, 3)[:30]
+    b = np.array([3 * w + 0.05, 3 * w - 0.7, 3 * w - 0.7]) + np.array([0.3, 0.2, 0.2]) * b
+    clumps = np.concatenate([a, b]) + rng.uniform(-0.01, 0.01, (90, 3))
+    pos = np.mod(np.concatenate([bg[keep], clumps]), L)
+    n = pos.shape[0]
+    cfg = md_inputs.Config("crowded_cells", pos, np.zeros((n, 3)), np.full((1, 3), L),
+                           np.array([n]), np.zeros(n, np.int32), 1, np.ones((1, 1)),
+                           np.ones((1, 1)), np.ones(1), RC, SKIN, 0.005, 1.0, 1)
+    # the construction does what it is for (checked on the host)
+    c = np.floor(pos / w).astype(int)
+    in_a = np.all(c == (3, 3, 3), 1)
+    assert in_a.sum() == 60 and np.all(c == (3, 2, 2), 1).sum() == 30
+    d = np.abs(c - np.array([3, 3, 3]))
+    assert 384 <= np.all(d <= 1, 1).sum() <= 768
+    pa = pos[in_a]
+    near = np.linalg.norm(pa[:, None, :] - pos[None, :, :], axis=2) < RC + SKIN
+    assert near.sum(1).min() - 1 > 80
+    return cfg
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_tile_build_flushes_a_crowded_cells_entries(prec):
+    cfg = _crowded_cells()
+    say(f"case: tile build of crowded cells {prec} N={cfg.n}")
+    s = _system(cfg, mode="tile", prec=prec)
+    s.setup()
+    s.ensure_list()
+    got = _unordered(s.list_pairs()[0])
+    rl = RC + SKIN
+    exp = set(map(tuple, oracle.pairs_cells(cfg.pos, cfg.box[0], rl)))
+    # the set is unique up to pairs within rounding of the Verlet radius
+    for i, j in got.symmetric_difference(exp):
+        d = cfg.pos[i] - cfg.pos[j]
+        d -= cfg.box[0] * np.rint(d / cfg.box[0])
+        assert abs(np.dot(d, d) - rl * rl) < 1e-10
+    assert len(got.symmetric_difference(exp)) <= 2
+    ref, e, _ = oracle.lj_forces(cfg.pos, cfg.box[0], RC, shift=1)
+    assert _err(s.forces_np(), ref) < (1e-12 if prec == "fp64" else 1e-5)
+
+
 def _one_type(cfg):
     # the replica batch with every atom of type 0 and a 1 x 1 (eps, sigma)
     return md_inputs.Config(cfg.name + "_1t", cfg.pos, cfg.vel, cfg.box, cfg.natoms,
