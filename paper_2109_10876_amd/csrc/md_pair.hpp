@@ -171,6 +171,32 @@ __device__ __forceinline__ void lj_pair_sums(const PolyConst &pc, double dx, dou
     c.fz = fma(fr, dz, c.fz);
 }
 
+// The force of lj_pair_sums alone, for calls that want no energy or virial:
+// the same expressions for q, q3, w and fr, so the two give the same force
+// bit for bit, without the three sums per pair.
+template <int PREC>
+__device__ __forceinline__ void lj_pair_force(const PolyConst &pc, double dx, double dy,
+                                              double dz, double rc2, Acc &c)
+{
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < rc2)) return;
+    double fr;
+    if (PREC == MD_FP64) {
+        const double q = rcp_f64(r2);
+        const double q3 = q * q * q;
+        const double w = q3 * (pc.A * q3 - pc.B);
+        fr = w * q;
+    } else {
+        const float q = __builtin_amdgcn_rcpf(static_cast<float>(r2));
+        const float q3 = q * q * q;
+        const float w = q3 * fmaf(pc.Af, q3, -pc.Bf);
+        fr = static_cast<double>(w * q);
+    }
+    c.fx = fma(fr, dx, c.fx);
+    c.fy = fma(fr, dy, c.fy);
+    c.fz = fma(fr, dz, c.fz);
+}
+
 // The atom's energy from the sums of lj_pair_sums (sum w, sum q3, count).
 __device__ __forceinline__ double pair_sums_energy(const PolyConst &pc, double sw, double sq3,
                                                    uint32_t n)

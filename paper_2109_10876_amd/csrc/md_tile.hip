@@ -22,7 +22,10 @@ constexpr int kTileMaxTypes = MD_TILE_MAX_TYPES;
 // TY: 0 one atom type; 2 two types, the constants of this atom's two type
 // pairs held in registers and selected per entry; 4 up to four types, the
 // constants read per entry from an LDS table.  FUSE: 0 forces only; 1 then
-// md_vv_step phase 3 per atom; 2 the thermostat force added before it.
+// md_vv_step phase 3 per atom; 2 the thermostat force added before it; 3 as
+// 1 (one type, alternating gate words) for calls that want no energy,
+// virial or kinetic energy: the pair loop sums the force alone and the
+// tile writes no partials, only its gate word.
 template <class SH, int PREC, int U, bool P4, int TY, int FUSE>
 __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
 {
@@ -91,9 +94,11 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
                                                     size_t(min(b, bmax)) * a.ld);
             return true;
         });
+    constexpr bool kGateWords = (FUSE == 1 || FUSE == 3) && !TY;
     if (total < 0) {
-        if (threadIdx.x < kTilePartials) a.tpart[size_t(row) * kTilePartials + threadIdx.x] = 0.0;
-        if (FUSE == 1 && !TY && a.vv.gate_clear && threadIdx.x == 0) a.vv.gate_clear[s.rep] = 0u;
+        if (FUSE != 3 && threadIdx.x < kTilePartials)
+            a.tpart[size_t(row) * kTilePartials + threadIdx.x] = 0.0;
+        if (kGateWords && a.vv.gate_clear && threadIdx.x == 0) a.vv.gate_clear[s.rep] = 0u;
         return;
     }
     double e_acc = 0.0, w_acc = 0.0, ke_acc = 0.0, d2_max = 0.0;
@@ -141,6 +146,8 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
                     else if (TY)
                         lj_pair_masked<PREC>(ptab[ti4 + (ent[q] & 7)], xi - px[q], yi - py[q],
                                              zi - pz[q], rc2, c);
+                    else if (FUSE == 3)
+                        lj_pair_force<PREC>(pc, xi - px[q], yi - py[q], zi - pz[q], rc2, c);
                     else
                         lj_pair_sums<PREC>(pc, xi - px[q], yi - py[q], zi - pz[q], rc2, c);
                 }
@@ -154,8 +161,10 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
             }
             // one type: the energy follows from the sums of lj_pair_sums
             if (!TY) ed = pair_sums_energy(pc, wd, ed, c.n);
-            e_acc += 0.5 * ed;
-            w_acc += 0.5 * wd;
+            if (FUSE != 3) {
+                e_acc += 0.5 * ed;
+                w_acc += 0.5 * wd;
+            }
             double gx = c.fx, gy = c.fy, gz = c.fz;   // the atom's force
             if (FUSE == 2) {
                 // md_langevin's force, with the velocity on entry
@@ -179,7 +188,8 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
                 a.fy[i] = gy;
                 a.fz[i] = gz;
             }
-            if (a.status && !isfinite(gx + gy + gz + ed)) atomicOr(a.status, MD_F_NONFINITE);
+            if (a.status && !isfinite(gx + gy + gz + (FUSE == 3 ? 0.0 : ed)))
+                atomicOr(a.status, MD_F_NONFINITE);
             if (FUSE) {
                 // md_vv_step phase 3 on this atom with the force just computed
                 const VVFuse &f = a.vv;
@@ -189,7 +199,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
                 vx = fma(k, gx, vx);
                 vy = fma(k, gy, vy);
                 vz = fma(k, gz, vz);
-                ke_acc += 0.5 * (vx * vx + vy * vy + vz * vz) / im;
+                if (FUSE != 3) ke_acc += 0.5 * (vx * vx + vy * vy + vz * vz) / im;
                 vx = fma(k, gx, vx);
                 vy = fma(k, gy, vy);
                 vz = fma(k, gz, vz);
@@ -222,10 +232,12 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
     }
     // the tile's partials: wave totals, one barrier, then the waves' totals
     // in wave order (as block_sum_n sums them)
-    e_acc = wave_sum(e_acc);
-    w_acc = wave_sum(w_acc);
+    if (FUSE != 3) {
+        e_acc = wave_sum(e_acc);
+        w_acc = wave_sum(w_acc);
+    }
     if (FUSE) {
-        ke_acc = wave_sum(ke_acc);
+        if (FUSE != 3) ke_acc = wave_sum(ke_acc);
         d2_max = wave_max(d2_max);
     }
     const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
@@ -244,17 +256,19 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
             ks += red[2][q];
             dm = fmax(dm, red[3][q]);
         }
-        double *tp = a.tpart + size_t(row) * kTilePartials;
-        tp[0] = es;
-        tp[1] = ws;
-        tp[2] = FUSE ? ks : 0.0;
-        tp[3] = FUSE ? dm : 0.0;
+        if (FUSE != 3) {
+            double *tp = a.tpart + size_t(row) * kTilePartials;
+            tp[0] = es;
+            tp[1] = ws;
+            tp[2] = FUSE ? ks : 0.0;
+            tp[3] = FUSE ? dm : 0.0;
+        }
         // alternating gate words (one atom type): the skin test of the tile's
         // replica, and its other word cleared (this kernel never reads it),
         // by every workgroup on its way out, without a finaliser (done before
         // the staging loads, the clear cost the pair loop registers; the
         // typed kernels leave both to the finaliser for the same reason)
-        if (FUSE == 1 && !TY && a.vv.gate_clear) {
+        if (kGateWords && a.vv.gate_clear) {
             a.vv.gate_clear[s.rep] = 0u;
             if (dm > a.vv.lim2) atomicOr(a.vv.gate + s.rep, 1u);
         }
@@ -456,7 +470,13 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
             else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 4, F);                                  \
         }                                                                                 \
     } while (0)
+            // one type, alternating gate words and no energy, virial or
+            // kinetic energy asked: the force-only pair loop (FUSE 3)
+            const bool bare = !vvf->step && vvf->gate_clear && ty == 0 && !energy && !virial &&
+                              !vvf->ke;
             if (vvf->step) MD_TILE_FUSED(2);
+            else if (bare && prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 0, 3);
+            else if (bare) MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, 3);
             else MD_TILE_FUSED(1);
 #undef MD_TILE_FUSED
         } else if (typed && p->ntypes == 2) {
