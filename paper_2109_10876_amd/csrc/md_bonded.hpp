@@ -56,7 +56,7 @@ __device__ __forceinline__ bool fene_atom(int i, int me, const double *x, const 
         const int j = ORDER == MD_BY_ID ? where[p] : p;
         double dx = xi - x[j], dy = yi - y[j], dz = zi - z[j];
         bx.wrap(dx, dy, dz);
-        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double r2 = norm2(dx, dy, dz);
         const double q = 1.0 - r2 / R02;
         if (!(q > 0.0)) {
             ok = false;

@@ -85,7 +85,7 @@ __device__ __forceinline__ void scan_cell(const BuildArgs &a, int i, double xs, 
             const int j = jb + q;
             const double dx = xs - px[q], dy = ys - py[q], dz = zs - pz[q];
             const bool take = j < j1 && (HALF ? j > i : j != i) &&
-                              dx * dx + dy * dy + dz * dz < a.rl2;
+                              norm2(dx, dy, dz) < a.rl2;
             if (take) push(a, i, uint32_t(j) | code, cnt);
         }
     }
@@ -111,7 +111,7 @@ __device__ __forceinline__ void scan_cell_mi(const BuildArgs &a, int i, double x
             dy -= ty * L[1];
             dz -= tz * L[2];
             const bool take = j < j1 && (HALF ? j > i : j != i) &&
-                              dx * dx + dy * dy + dz * dz < a.rl2;
+                              norm2(dx, dy, dz) < a.rl2;
             if (take) {
                 const uint32_t code = (image_code(-int(tx)) | (image_code(-int(ty)) << 2) |
                                        (image_code(-int(tz)) << 4)) << MD_IDX_BITS;

@@ -154,6 +154,15 @@ __device__ __forceinline__ double image_shift(uint32_t c) { return c == 0u ? 0.0
 
 // ------------------------------------------------------------- arithmetic
 
+// |(x, y, z)|^2 rounded in one fixed sequence, fma(x, x, fma(y, y, z z)):
+// left to itself the compiler picks a contraction per kernel, and kernels
+// that must agree bit for bit (a fused step and the split calls, the
+// integrator's skin test in both) would then round differently.
+__device__ __forceinline__ double norm2(double x, double y, double z)
+{
+    return fma(x, x, fma(y, y, z * z));
+}
+
 // Double-precision reciprocal: hardware estimate refined by two
 // Newton-Raphson steps y <- y + y (1 - a y).
 __device__ __forceinline__ double rcp_f64(double a)

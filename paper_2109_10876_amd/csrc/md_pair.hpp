@@ -46,7 +46,7 @@ template <int PREC>
 __device__ __forceinline__ double lj_pair_accumulate(const PairConst &pc, double dx, double dy,
                                                      double dz, double rc2, Acc &c)
 {
-    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r2 = norm2(dx, dy, dz);
     if (!(r2 < rc2)) return 0.0;
     double fr;
     if (PREC == MD_FP64) {
@@ -110,13 +110,13 @@ template <int PREC>
 __device__ __forceinline__ void lj_pair_masked(const PolyConst &pc, double dx, double dy,
                                                double dz, double rc2, Acc &c)
 {
-    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r2 = norm2(dx, dy, dz);
     if (!(r2 < rc2)) return;
     double fr;
     if (PREC == MD_FP64) {
         const double q = rcp_f64(r2);
         const double q3 = q * q * q;
-        const double w = q3 * (pc.A * q3 - pc.B);
+        const double w = q3 * fma(pc.A, q3, -pc.B);
         fr = w * q;
         c.ed += q3 * (pc.C * q3 - pc.D) - pc.ush;
         c.wd = fma(fr, r2, c.wd);
@@ -146,13 +146,13 @@ template <int PREC>
 __device__ __forceinline__ void lj_pair_sums(const PolyConst &pc, double dx, double dy,
                                              double dz, double rc2, Acc &c)
 {
-    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r2 = norm2(dx, dy, dz);
     if (!(r2 < rc2)) return;
     double fr;
     if (PREC == MD_FP64) {
         const double q = rcp_f64(r2);
         const double q3 = q * q * q;
-        const double w = q3 * (pc.A * q3 - pc.B);
+        const double w = q3 * fma(pc.A, q3, -pc.B);
         fr = w * q;
         c.wd += w;
         c.ed += q3;
@@ -178,13 +178,13 @@ template <int PREC>
 __device__ __forceinline__ void lj_pair_force(const PolyConst &pc, double dx, double dy,
                                               double dz, double rc2, Acc &c)
 {
-    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r2 = norm2(dx, dy, dz);
     if (!(r2 < rc2)) return;
     double fr;
     if (PREC == MD_FP64) {
         const double q = rcp_f64(r2);
         const double q3 = q * q * q;
-        const double w = q3 * (pc.A * q3 - pc.B);
+        const double w = q3 * fma(pc.A, q3, -pc.B);
         fr = w * q;
     } else {
         const float q = __builtin_amdgcn_rcpf(static_cast<float>(r2));
@@ -233,7 +233,7 @@ template <int PREC>
 __device__ __forceinline__ void lj_pair_ab(const PairAB<PREC> &k, double dx, double dy,
                                            double dz, double rc2, Acc &c)
 {
-    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r2 = norm2(dx, dy, dz);
     // selects here, not the branch of lj_pair_masked: with per-lane constants
     // the branch form made the two-type kernel 5% slower
     const bool in = r2 < rc2;

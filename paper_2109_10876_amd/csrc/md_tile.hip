@@ -210,7 +210,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_lj(TileArgs a)
                 f.yn[i] = y;
                 f.zn[i] = z;
                 const double ex = x - f.xb[i], ey = y - f.yb[i], ez = z - f.zb[i];
-                d2_max = fmax(d2_max, ex * ex + ey * ey + ez * ez);
+                d2_max = fmax(d2_max, norm2(ex, ey, ez));
                 f.vx[i] = vx;
                 f.vy[i] = vy;
                 f.vz[i] = vz;

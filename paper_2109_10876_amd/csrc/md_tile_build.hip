@@ -262,7 +262,7 @@ __global__ __launch_bounds__(SH::TB) __attribute__((amdgpu_waves_per_eu(3))) voi
                             const double dx = st.x[hs] - px, dyy = st.y[hs] - py,
                                          dzz = st.z[hs] - pz;
                             const bool take = valid & (sl != hs) &
-                                              (dx * dx + dyy * dyy + dzz * dzz < a.rl2);
+                                              (norm2(dx, dyy, dzz) < a.rl2);
                             const uint64_t m = __builtin_amdgcn_ballot_w64(take);
                             const int cnt = __builtin_amdgcn_readlane(vcnt, j);
                             const int k = int(__builtin_amdgcn_mbcnt_hi(

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(SH::TB) void k_tile_vjp(TileArgs a)
                     // typed entries carry the neighbour's type in the low 3 bits
                     const int slot = min(int(e >> 3), CAP);
                     const double dx = xi - st.x[slot], dy = yi - st.y[slot], dz = zi - st.z[slot];
-                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    const double r2 = norm2(dx, dy, dz);
                     if (!(r2 < rc2)) continue;   // pad entries never pass
                     const int tj = NT > 1 ? int(e & 7u) : 0;
                     const VjpConst c = tab[ti * kTT + tj];

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kUnit) void k_vjp(VjpArgs a)
                 dy += image_shift((code >> 2) & 3u) * Ly;
                 dz += image_shift((code >> 4) & 3u) * Lz;
             }
-            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double r2 = norm2(dx, dy, dz);
             if (!(r2 < rc2)) continue;
             const int tj = NT > 1 ? a.type[j] : 0;
             const VjpConst c = tab[ti * nt + tj];

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kUnit) void k_vv(VVArgs a)
             a.z[i] = z;
             if (a.pos4) reinterpret_cast<double4 *>(a.pos4)[i] = make_double4(x, y, z, 0.0);
             const double ex = x - a.xb[i], ey = y - a.yb[i], ez = z - a.zb[i];
-            d2 = ex * ex + ey * ey + ez * ez;
+            d2 = norm2(ex, ey, ez);
         }
         a.vx[i] = vx;
         a.vy[i] = vy;
