@@ -60,10 +60,10 @@ FLOPS_PER_ATOM_VV = 36
 # in); each entry: source hash of the kernel's files and calibrated bytes per
 # launch for the FP32-mixed and FP64 paths.
 COUNTED_TRAFFIC = {
-    "tile_fused": {"src_sha256_16": "f7ddff7c822f2b39",
-                   "bytes_per_launch": {"mixed": 420336521, "fp64": 421808120}},
-    "tile": {"src_sha256_16": "f7ddff7c822f2b39",
-             "bytes_per_launch": {"mixed": 317772556, "fp64": 319337952}},
+    "tile_fused": {"src_sha256_16": "6c97ada23534bfc7",
+                   "bytes_per_launch": {"mixed": 420427262, "fp64": 421714757}},
+    "tile": {"src_sha256_16": "6c97ada23534bfc7",
+             "bytes_per_launch": {"mixed": 317699655, "fp64": 319405946}},
 }
 
 FORCE_KERNEL_SOURCES = {
