@@ -57,13 +57,16 @@ FLOPS_PER_ATOM_VV = 36
 # 512 MiB device copy needs to read back its true size), valid only for the
 # kernel source they were taken on (profiles/k_tile_lj_lj1m_hbm_counters.md).
 # Keyed by list form ("_fused": the force kernel with the integrator fused
-# in); each entry: source hash of the kernel's files and calibrated bytes per
-# launch for the FP32-mixed and FP64 paths.
+# in); each entry: source hash of the kernel's files and, per pair batch of
+# the launch (8 takes 16 entries per pass), calibrated bytes per launch for
+# the FP32-mixed and FP64 paths.
 COUNTED_TRAFFIC = {
-    "tile_fused": {"src_sha256_16": "6c97ada23534bfc7",
-                   "bytes_per_launch": {"mixed": 420427262, "fp64": 421714757}},
-    "tile": {"src_sha256_16": "6c97ada23534bfc7",
-             "bytes_per_launch": {"mixed": 317699655, "fp64": 319405946}},
+    "tile_fused": {"src_sha256_16": "cdb2de62444cf33d",
+                   "bytes_per_launch": {"4": {"mixed": 420400571, "fp64": 421723454},
+                                        "8": {"mixed": 439971407, "fp64": 442008382}}},
+    "tile": {"src_sha256_16": "cdb2de62444cf33d",
+             "bytes_per_launch": {"4": {"mixed": 317826611, "fp64": 319613777},
+                                  "8": {"mixed": 336739664, "fp64": 339324424}}},
 }
 
 FORCE_KERNEL_SOURCES = {
@@ -551,8 +554,9 @@ def main():
         tfs = flops_launch / (f_ms * 1e-3) / 1e12
         traffic = traffic_bytes = None
         counted = COUNTED_TRAFFIC.get(tuned["mode"] + ("_fused" if fused else ""))
-        if counted and force_kernel_src_hash(tuned["mode"]) == counted["src_sha256_16"]:
-            traffic_bytes = counted["bytes_per_launch"][prec]
+        per_batch = counted["bytes_per_launch"].get(str(tuned.get("batch", 4))) if counted else None
+        if per_batch and force_kernel_src_hash(tuned["mode"]) == counted["src_sha256_16"]:
+            traffic_bytes = per_batch[prec]
             traffic = traffic_bytes / (f_ms * 1e-3) / 1e9
         if fused:
             kernel = "md_lj_forces_vv (k_tile_lj fused with velocity-Verlet)"

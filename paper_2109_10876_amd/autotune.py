@@ -144,8 +144,12 @@ def tune(make, key, steps=40, warmup=10, cache=DEFAULT_CACHE, retune=False, log=
             best_ms = ms
     best = dict(min(trials, key=lambda t: t[1])[0])
     if best["mode"] == "tile":
-        for batch in (8,):
-            run(dict(best, batch=batch))
+        # 16 entries per pass against 8: within a percent of each other on
+        # a liquid, so each is timed twice, interleaved, and the better
+        # trial of either decides
+        alt = dict(best, batch=8)
+        for cand in (alt, best, alt):
+            run(dict(cand))
         best = dict(min(trials, key=lambda t: t[1])[0])
         # the fused force + integrator call against the split calls (for a
         # factory that takes ``fuse``): with a thermostat the fused kernel

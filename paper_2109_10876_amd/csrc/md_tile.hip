@@ -475,8 +475,13 @@ int tile_forces(const md_batch *b, const md_atoms *atoms, const md_nlist *nl, co
             const bool bare = !vvf->step && vvf->gate_clear && ty == 0 && !energy && !virial &&
                               !vvf->ke;
             if (vvf->step) MD_TILE_FUSED(2);
-            else if (bare && prec == MD_FP64) MD_TILE_LAUNCH(MD_FP64, 8, 0, 3);
-            else if (bare) MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, 3);
+            else if (bare && prec == MD_FP64) {
+                if (big) MD_TILE_LAUNCH(MD_FP64, 16, 0, 3);
+                else MD_TILE_LAUNCH(MD_FP64, 8, 0, 3);
+            } else if (bare) {
+                if (big) MD_TILE_LAUNCH(MD_FP32_MIXED, 16, 0, 3);
+                else MD_TILE_LAUNCH(MD_FP32_MIXED, 8, 0, 3);
+            }
             else MD_TILE_FUSED(1);
 #undef MD_TILE_FUSED
         } else if (typed && p->ntypes == 2) {

@@ -936,10 +936,21 @@ def test_repeated_fused_steps_set_the_oracles_rebuild_schedule():
     assert np.array_equal(g.positions(), s.positions())
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_fused_and_split_steps_are_bitwise_equal(prec):
+@pytest.mark.parametrize("prec,batch", [("fp64", 4), ("mixed", 4), ("fp64", 8), ("mixed", 8)])
+def test_fused_and_split_steps_are_bitwise_equal(prec, batch):
     # same FMA sequence in one kernel or in md_lj_forces + md_vv_step:
-    # positions and velocities equal bit for bit, also through graphs
+    # positions and velocities equal bit for bit, also through graphs; with
+    # a pair batch of 8 the tile kernels take 16 entries per pass
+    from paper_2109_10876_amd import _abi as abi
+    lib = abi.load()
+    assert lib.md_tune_set(abi.MD_TUNE_PAIR_BATCH, batch) == 0
+    try:
+        _fused_and_split(prec)
+    finally:
+        lib.md_tune_set(abi.MD_TUNE_PAIR_BATCH, 4)
+
+
+def _fused_and_split(prec):
     cfg = md_inputs.lj_fluid(8, temperature=1.5, seed=25)
     say(f"case: fused vs split {prec}")
     a = _system(cfg, mode="tile", prec=prec, fuse=False)
